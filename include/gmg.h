@@ -1,0 +1,169 @@
+/*
+ * gmg.h -- C ABI of the MI355X (gfx950) geometric-multigrid-preconditioned
+ * FGMRES solver for the variable-coefficient Poisson-type equation
+ *
+ *     -div(a grad phi) = f   on a uniform nx x ny x nz cell grid,
+ *     phi = phi_bot on the plate z = 0, phi = phi_top on the plate z = 1,
+ *     d phi / dn = 0 on the four x and y sides,
+ *
+ * the elliptic problem solved once per time step of the paper's semi-implicit
+ * streamer scheme (Lin, Zhuang, Cai, Zeng, Bao, "An efficient and accurate
+ * MPI-based parallel simulator for streamer discharges in three dimensions":
+ * problem statement Sec. 1; discretisation eq. e18, Sec. 2.2; solver
+ * Algorithm 1, Sec. 3.1; preconditioner Sec. 3.2; stopping rule eq. criterion,
+ * Sec. 5.2).
+ *
+ * Discretisation (eq. e18): cell-centred finite volumes; the face coefficient
+ * is the arithmetic mean of the two adjacent cells' a; the plates act through
+ * a ghost cell mirrored through the plate (phi_g = 2 phi_b - phi_c) whose face
+ * coefficient is the cell's own a; the sides carry no flux.  The linear system
+ * is A phi = b with b = f + 2 a_c phi_b / hz^2 on the first and last z-layers.
+ *
+ * Layout of every field: float64, C order (nz, ny, nx), x fastest; cell
+ * (i, j, k) is element (k*ny + j)*nx + i; cell centre ((i+1/2)hx, ...).
+ * Every pointer named *_dev is a device pointer on the current HIP device.
+ *
+ * Ownership: the caller allocates and frees every device buffer, including
+ * the workspace.  The context keeps the pointers a_dev (until the next
+ * gmg_update_coefficient or gmg_destroy) and workspace_dev (until
+ * gmg_destroy); it keeps no pointer to f, phi, x, y, lam or dLda after a call
+ * returns.  gmg_destroy frees only host-side state.
+ *
+ * Streams: every kernel is enqueued on the stream given to gmg_setup (or
+ * gmg_set_stream).  Calls block the host only where they must read a scalar
+ * back (one read per Arnoldi step in fgmres_solve) and before returning.
+ *
+ * Threads: a context is not re-entrant; calls on one context must not
+ * overlap.  Distinct contexts with distinct workspaces are independent.
+ *
+ * Errors: functions return a status code (never throw); gmg_status_string
+ * gives its text.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmg_ctx gmg_ctx;
+
+enum {
+  GMG_OK = 0,
+  GMG_NOT_CONVERGED = 1, /* max_iter Arnoldi steps taken; phi holds the last iterate */
+  GMG_ERR_ARG = -1,      /* null pointer, bad option, a <= 0, tol < 0 */
+  GMG_ERR_SHAPE = -2,    /* grid does not coarsen to <= coarse_max_cells cells */
+  GMG_ERR_NONFINITE = -3,/* NaN or Inf in a, f, phi (x0) or during the iteration */
+  GMG_ERR_WORKSPACE = -4,/* workspace null, too small or misaligned (256 B) */
+  GMG_ERR_HIP = -5       /* a HIP runtime call failed */
+};
+
+enum { GMG_FP64 = 0, GMG_MIXED = 1 };
+
+/* Solver options.  gmg_default_options fills the defaults given below. */
+typedef struct gmg_options {
+  int restart;          /* Krylov dimension m of FGMRES(m), 1..32 (default 10)   */
+  int max_iter;         /* cap on Arnoldi steps over all restarts (default 200)  */
+  int nu_pre;           /* red-black Gauss-Seidel pre-sweeps, 0..8 (default 2)   */
+  int nu_post;          /* post-sweeps, 0..8 (default 2)                         */
+  int precision;        /* GMG_FP64: whole solve in float64; GMG_MIXED: V-cycle
+                           (coefficients, smoother, transfers, coarse solve) in
+                           float32, FGMRES in float64 (default GMG_MIXED)       */
+  int coarse_max_cells; /* largest coarsest level solved directly (default 4096) */
+  int reserved[4];      /* must be zero */
+} gmg_options;
+
+void gmg_default_options(gmg_options* opt);
+
+/* Bytes of device workspace a grid needs (0 if the shape or options are
+ * invalid).  The workspace must be 256-byte aligned. */
+size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt);
+
+/* Build the multigrid hierarchy for coefficient a (float64, > 0, finite)
+ * on an nx x ny x nz grid with spacings hx, hy, hz (Sec. 2.2).  Levels halve
+ * every dimension while all are even and >= 4 (Sec. 3.2, 2x2x2 agglomeration);
+ * the coarsest level (<= coarse_max_cells cells) is solved directly (Sec. 3.2,
+ * coarsest-mesh direct solver).  hip_stream is a hipStream_t (NULL = default
+ * stream).  On success *out receives the context. */
+int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz,
+              const double* a_dev, const gmg_options* opt, void* workspace_dev,
+              size_t workspace_bytes, void* hip_stream, gmg_ctx** out);
+
+/* Replace the coefficient (same grid) and rebuild the hierarchy: the
+ * per-time-step renewal of operator and preconditioner (Sec. 2.1, last
+ * paragraphs). */
+int gmg_update_coefficient(gmg_ctx* ctx, const double* a_dev);
+
+/* Change the stream later calls enqueue on. */
+int gmg_set_stream(gmg_ctx* ctx, void* hip_stream);
+
+/* FGMRES(m) (Algorithm 1), right-preconditioned by one V-cycle per step
+ * from a zero guess (Sec. 3.2), on A phi = b.  Stops when the relative
+ * residual ||b - A phi|| / ||b|| < tol (eq. criterion; the in-cycle least-
+ * squares estimate triggers the check, the true residual decides it) or after
+ * opt->max_iter Arnoldi steps.
+ *   f_dev        right side f (nz*ny*nx float64), read only.
+ *   phi_bot/top  plate values.
+ *   tol          relative tolerance >= 0 (tol = 0 runs exactly max_iter steps).
+ *   phi_dev      output phi; if use_x0 != 0 it holds the initial guess on
+ *                entry (warm start), otherwise it is overwritten.
+ *   iterations   (may be NULL) Arnoldi steps taken over all restarts.
+ *   res_hist     (may be NULL) res_hist[0] = ||b - A x0|| / ||b||, then one
+ *                least-squares estimate per step; at most res_hist_cap
+ *                entries are written, *res_hist_len (may be NULL) gets the
+ *                number written.
+ *   final_true_relres (may be NULL) recomputed ||b - A phi|| / ||b||.
+ * b = 0 gives phi = 0, 0 steps, GMG_OK.
+ * Returns GMG_OK, GMG_NOT_CONVERGED or an error. */
+int fgmres_solve(gmg_ctx* ctx, const double* f_dev, double phi_bot,
+                 double phi_top, double tol, double* phi_dev, int use_x0,
+                 int* iterations, double* res_hist, int res_hist_cap,
+                 int* res_hist_len, double* final_true_relres);
+
+/* y = A x - lifting: the left side of e18 on cell values x with plate values
+ * phi_bot, phi_top (so y = f exactly when x solves the problem).  x and y
+ * must not overlap. */
+int gmg_apply_operator(gmg_ctx* ctx, const double* x_dev, double* y_dev,
+                       double phi_bot, double phi_top);
+
+/* One V-cycle from a zero guess with right side v (Sec. 3.2, last
+ * paragraph): z = M v, in the context's precision (in GMG_MIXED, v is rounded
+ * to float32 and the float32 result is promoted exactly).  v and z must not
+ * overlap. */
+int gmg_vcycle(gmg_ctx* ctx, const double* v_dev, double* z_dev);
+
+/* Gradient with respect to the coefficient of a loss L(phi) through the
+ * solve, given phi (the solution for plate values phi_bot, phi_top) and the
+ * adjoint lam (the solution of A lam = dL/dphi with zero plate values):
+ *   dLda_c = -1/2 * sum over the faces of cell c of (d phi)_f (d lam)_f,
+ * with (d u)_f = (u_nb - u_c)/h on interior faces, the half-cell quotients
+ * (phi_c - phi_b)/(hz/2) and lam_c/(hz/2) on plate faces, and no term on the
+ * sides (derived from e18).  dL/df is lam itself. */
+int gmg_face_flux_grad(gmg_ctx* ctx, const double* phi_dev,
+                       const double* lam_dev, double phi_bot, double phi_top,
+                       double* dLda_dev);
+
+/* Hierarchy description: number of levels and, for level l < cap, its
+ * (nx, ny, nz) in shapes[3l..3l+2]. */
+int gmg_get_levels(gmg_ctx* ctx, int* nlevels, int* shapes, int cap);
+
+/* Per-kernel timing with HIP events on the context's stream.  While enabled,
+ * every kernel launch is bracketed by events; gmg_profile_read sums the
+ * elapsed times per kernel name since the last reset (it synchronises the
+ * stream).  names[i] point to static strings. */
+int gmg_profile_enable(gmg_ctx* ctx, int enable);
+int gmg_profile_reset(gmg_ctx* ctx);
+int gmg_profile_read(gmg_ctx* ctx, const char** names, double* total_ms,
+                     long long* launches, int cap, int* count);
+
+void gmg_destroy(gmg_ctx* ctx);
+
+const char* gmg_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMG_H */

@@ -1,0 +1,931 @@
+// gmg.hip -- host side of the GMG-preconditioned FGMRES solver: workspace
+// layout, hierarchy set-up, V-cycle schedule, FGMRES(m) with host Givens
+// least squares (Algorithm 1, Sec. 3.1), profiling, and the C ABI of gmg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gmg.h"
+#include "gmg_kernels.hpp"
+
+using namespace gmg;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_RESTART = 32;
+constexpr double BREAKDOWN_TOL = 1e-14;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct LevelShape {
+  int nx, ny, nz;
+  double hx, hy, hz;
+  size_t n() const { return (size_t)nx * ny * nz; }
+  Geom geom() const { return Geom{nx, ny, nz, 1.0 / (hx * hx), 1.0 / (hy * hy), 1.0 / (hz * hz)}; }
+};
+
+// Level shapes: halve all dimensions while every one is even and >= 4.
+std::vector<LevelShape> level_shapes(int nx, int ny, int nz, double hx, double hy, double hz) {
+  std::vector<LevelShape> v;
+  v.push_back({nx, ny, nz, hx, hy, hz});
+  while (true) {
+    const LevelShape& l = v.back();
+    if (l.nx % 2 || l.ny % 2 || l.nz % 2 || l.nx < 4 || l.ny < 4 || l.nz < 4) break;
+    v.push_back({l.nx / 2, l.ny / 2, l.nz / 2, 2 * l.hx, 2 * l.hy, 2 * l.hz});
+  }
+  return v;
+}
+
+// Byte offsets of every buffer in the caller's workspace.
+struct LevelOffsets {
+  size_t wx, wy, wz, tp;          // precision T faces (levels >= 1)
+  size_t wx64, wy64, wz64, tp64;  // float64 faces (levels >= 1; == T faces in FP64)
+  size_t b, x;                    // precision T right side and iterate
+};
+
+struct Layout {
+  std::vector<LevelShape> shapes;
+  std::vector<LevelOffsets> lv;
+  size_t V, Z, a32, b0, partials, scal, cinv, total;
+  size_t tsize;  // bytes of the V-cycle precision
+  int m;
+};
+
+bool options_valid(const gmg_options* o) {
+  if (!o) return false;
+  if (o->restart < 1 || o->restart > MAX_RESTART) return false;
+  if (o->max_iter < 0) return false;
+  if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8) return false;
+  if (o->precision != GMG_FP64 && o->precision != GMG_MIXED) return false;
+  if (o->coarse_max_cells < 1 || o->coarse_max_cells > 4096) return false;
+  for (int r : o->reserved)
+    if (r) return false;
+  return true;
+}
+
+int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const gmg_options* o, Layout* L) {
+  if (!options_valid(o)) return GMG_ERR_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return GMG_ERR_SHAPE;
+  if ((nx + BX - 1) / BX > MAX_RED_BLOCKS) return GMG_ERR_SHAPE;
+  L->shapes = level_shapes(nx, ny, nz, hx, hy, hz);
+  const LevelShape& last = L->shapes.back();
+  if (last.n() > (size_t)o->coarse_max_cells) return GMG_ERR_SHAPE;
+  const bool mixed = o->precision == GMG_MIXED;
+  L->tsize = mixed ? 4 : 8;
+  L->m = o->restart;
+  const size_t N = L->shapes[0].n();
+  const int nl = (int)L->shapes.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L->V = take((size_t)(L->m + 1) * N * 8);
+  L->Z = take((size_t)L->m * N * L->tsize);
+  L->a32 = mixed ? take(N * 4) : 0;
+  // finest-level right side in T: the float32 copy of v_j (mixed) or, when
+  // the finest level is also the coarsest, the scaled right side
+  L->b0 = (mixed || nl == 1) ? take(N * L->tsize) : 0;
+  L->lv.assign(nl, LevelOffsets{});
+  for (int l = 1; l < nl; ++l) {
+    const LevelShape& s = L->shapes[l];
+    const size_t n = s.n(), nxy = (size_t)s.nx * s.ny;
+    LevelOffsets& lo = L->lv[l];
+    lo.wx64 = take(n * 8);
+    lo.wy64 = take(n * 8);
+    lo.wz64 = take(n * 8);
+    lo.tp64 = take(nxy * 8);
+    if (mixed) {
+      lo.wx = take(n * 4);
+      lo.wy = take(n * 4);
+      lo.wz = take(n * 4);
+      lo.tp = take(nxy * 4);
+    } else {
+      lo.wx = lo.wx64;
+      lo.wy = lo.wy64;
+      lo.wz = lo.wz64;
+      lo.tp = lo.tp64;
+    }
+    lo.b = take(n * L->tsize);
+    lo.x = take(n * L->tsize);
+  }
+  L->partials = take((size_t)MAXV * MAX_RED_BLOCKS * 8);
+  L->scal = take((size_t)(L->m * (L->m + 2) + (L->m + 2) + 16) * 8);
+  const size_t nc = last.n();
+  L->cinv = take(nc * nc * L->tsize);
+  L->total = off;
+  return GMG_OK;
+}
+
+struct Launch {
+  dim3 grid, block;
+  int kc;
+  int nblocks() const { return (int)(grid.x * grid.y * grid.z); }
+};
+
+// Column-marching launch over an nx x ny x nz grid with at most max_blocks
+// blocks (the reduction kernels keep one partial per block).
+Launch col_launch(int nx, int ny, int nz, int max_blocks = MAX_RED_BLOCKS) {
+  const int gx = (nx + BX - 1) / BX;
+  int gy = (ny + BY - 1) / BY;
+  if ((long long)gx * gy > max_blocks) gy = std::max(1, max_blocks / gx);
+  gy = std::min(gy, 65535);
+  int gz = std::max(1, std::min(nz, max_blocks / (gx * gy)));
+  const int kc = (nz + gz - 1) / gz;
+  gz = (nz + kc - 1) / kc;
+  return Launch{dim3(gx, gy, gz), dim3(BX, BY, 1), kc};
+}
+
+Launch flat_launch(size_t n) {
+  const size_t b = std::min<size_t>((n + NTHREADS - 1) / NTHREADS, 8192);
+  return Launch{dim3((unsigned)std::max<size_t>(b, 1)), dim3(BX, BY, 1), 0};
+}
+
+// Per-kernel event timing.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, long long>> totals;
+  std::map<std::string, const char*> names;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+}  // namespace
+
+struct gmg_ctx {
+  int nx, ny, nz;
+  double hx, hy, hz;
+  gmg_options opt;
+  const double* a;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  Layout L;
+  size_t N;
+  bool mixed;
+  int nc;  // cells on the coarsest level
+  double* pinned;
+  hipError_t err;
+  Profiler prof;
+  // host Givens state
+  std::vector<double> R, cs, sn, g, y;
+};
+
+namespace {
+
+template <typename P>
+P* wsp(gmg_ctx* c, size_t off) {
+  return reinterpret_cast<P*>(c->ws + off);
+}
+
+double* scal_hcol(gmg_ctx* c, int j) { return wsp<double>(c, c->L.scal) + (size_t)j * (c->L.m + 2); }
+double* scal_vscale(gmg_ctx* c) { return wsp<double>(c, c->L.scal) + (size_t)c->L.m * (c->L.m + 2); }
+double* scal_misc(gmg_ctx* c) { return scal_vscale(c) + (c->L.m + 2); }
+
+struct ProfScope {
+  gmg_ctx* c;
+  const char* name;
+  hipEvent_t b = nullptr;
+  ProfScope(gmg_ctx* c_, const char* n) : c(c_), name(n) {
+    if (c->prof.on) {
+      hipEvent_t a = c->prof.get();
+      b = c->prof.get();
+      if (a && b) {
+        (void)hipEventRecord(a, c->stream);
+        c->prof.pending.push_back({name, a, b});
+      } else {
+        b = nullptr;
+      }
+    }
+  }
+  ~ProfScope() {
+    if (b) (void)hipEventRecord(b, c->stream);
+  }
+};
+
+#define GMG_LAUNCH(ctx, name, kern, L, ...)                                              \
+  do {                                                                                   \
+    ProfScope _ps((ctx), (name));                                                        \
+    hipLaunchKernelGGL(kern, (L).grid, (L).block, 0, (ctx)->stream, __VA_ARGS__);         \
+    hipError_t _e = hipGetLastError();                                                   \
+    if (_e != hipSuccess && (ctx)->err == hipSuccess) (ctx)->err = _e;                   \
+  } while (0)
+
+void note(gmg_ctx* c, hipError_t e) {
+  if (e != hipSuccess && c->err == hipSuccess) c->err = e;
+}
+
+// ---------------------------------------------------------------------------
+// Hierarchy set-up (per coefficient).
+// ---------------------------------------------------------------------------
+
+// Cholesky factor and inverse of the symmetric positive definite n x n
+// matrix M (row-major), in place; returns false if not positive definite.
+bool spd_inverse(std::vector<double>& M, int n) {
+  std::vector<double> Lf(M);
+  for (int j = 0; j < n; ++j) {
+    double d = Lf[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= Lf[(size_t)j * n + k] * Lf[(size_t)j * n + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    Lf[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = Lf[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= Lf[(size_t)i * n + k] * Lf[(size_t)j * n + k];
+      Lf[(size_t)i * n + j] = s / d;
+    }
+  }
+  // columns of the inverse: solve L L^T x = e_c
+  std::vector<double> col(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= Lf[(size_t)i * n + k] * col[k];
+      col[i] = s / Lf[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = col[i];
+      for (int k = i + 1; k < n; ++k) s -= Lf[(size_t)k * n + i] * col[k];
+      col[i] = s / Lf[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) M[(size_t)i * n + c] = col[i];
+  }
+  // symmetrise the rounding
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double v = 0.5 * (M[(size_t)i * n + j] + M[(size_t)j * n + i]);
+      M[(size_t)i * n + j] = M[(size_t)j * n + i] = v;
+    }
+  return true;
+}
+
+// Dense matrix of the coarsest level from its face coefficients (host).
+void assemble_coarsest(const LevelShape& s, const std::vector<double>& wx, const std::vector<double>& wy,
+                       const std::vector<double>& wz, const std::vector<double>& tp, const double* a_fine,
+                       bool fine_cells, std::vector<double>& M) {
+  const int nx = s.nx, ny = s.ny, nz = s.nz;
+  const int n = nx * ny * nz;
+  const double ix = 1.0 / (s.hx * s.hx), iy = 1.0 / (s.hy * s.hy), iz = 1.0 / (s.hz * s.hz);
+  M.assign((size_t)n * n, 0.0);
+  auto id = [&](int i, int j, int k) { return (k * ny + j) * nx + i; };
+  auto couple = [&](int p, int q, double w) {
+    M[(size_t)p * n + p] += w;
+    M[(size_t)q * n + q] += w;
+    M[(size_t)p * n + q] -= w;
+    M[(size_t)q * n + p] -= w;
+  };
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int c = id(i, j, k);
+        if (fine_cells) {  // single-level grid: faces from the cell coefficient
+          const double ac = a_fine[c];
+          if (i + 1 < nx) couple(c, id(i + 1, j, k), 0.5 * (ac + a_fine[id(i + 1, j, k)]) * ix);
+          if (j + 1 < ny) couple(c, id(i, j + 1, k), 0.5 * (ac + a_fine[id(i, j + 1, k)]) * iy);
+          if (k + 1 < nz) couple(c, id(i, j, k + 1), 0.5 * (ac + a_fine[id(i, j, k + 1)]) * iz);
+          if (k == 0) M[(size_t)c * n + c] += 2.0 * ac * iz;
+          if (k == nz - 1) M[(size_t)c * n + c] += 2.0 * ac * iz;
+        } else {
+          if (i + 1 < nx) couple(c, id(i + 1, j, k), wx[id(i + 1, j, k)] * ix);
+          if (j + 1 < ny) couple(c, id(i, j + 1, k), wy[id(i, j + 1, k)] * iy);
+          if (k + 1 < nz) couple(c, id(i, j, k + 1), wz[id(i, j, k + 1)] * iz);
+          if (k == 0) M[(size_t)c * n + c] += 2.0 * wz[c] * iz;
+          if (k == nz - 1) M[(size_t)c * n + c] += 2.0 * tp[j * nx + i] * iz;
+        }
+      }
+}
+
+int build_hierarchy(gmg_ctx* c) {
+  Layout& L = c->L;
+  const int nl = (int)L.shapes.size();
+  // check the coefficient: finite and positive
+  {
+    const Launch fl = flat_launch(c->N);
+    const int nb = std::min<int>(fl.grid.x, MAX_RED_BLOCKS);
+    Launch l2 = fl;
+    l2.grid.x = nb;
+    double* part = wsp<double>(c, L.partials);
+    GMG_LAUNCH(c, "check_coef", k_check_coef, l2, c->a, c->N, part);
+    std::vector<double> h(2 * (size_t)nb);
+    note(c, hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    note(c, hipStreamSynchronize(c->stream));
+    if (c->err != hipSuccess) return GMG_ERR_HIP;
+    double mn = 1e308, bad = 0;
+    for (int b = 0; b < nb; ++b) {
+      mn = std::min(mn, h[2 * b]);
+      bad += h[2 * b + 1];
+    }
+    if (bad > 0) return GMG_ERR_NONFINITE;
+    if (!(mn > 0.0)) return GMG_ERR_ARG;
+  }
+  if (c->mixed) {
+    const Launch fl = flat_launch(c->N);
+    GMG_LAUNCH(c, "convert_f64_f32", (k_convert<float, double>), fl, c->a, wsp<float>(c, L.a32), c->N);
+  }
+  for (int l = 1; l < nl; ++l) {
+    const LevelShape& f = L.shapes[l - 1];
+    const LevelShape& s = L.shapes[l];
+    const LevelOffsets& o = L.lv[l];
+    const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
+    if (l == 1) {
+      GMG_LAUNCH(c, "faces_from_cells", k_faces_from_cells, lc, c->a, f.geom(), wsp<double>(c, o.wx64),
+                 wsp<double>(c, o.wy64), wsp<double>(c, o.wz64), wsp<double>(c, o.tp64), lc.kc);
+    } else {
+      const LevelOffsets& p = L.lv[l - 1];
+      GMG_LAUNCH(c, "coarsen_faces", k_coarsen_faces, lc, wsp<double>(c, p.wx64), wsp<double>(c, p.wy64),
+                 wsp<double>(c, p.wz64), wsp<double>(c, p.tp64), f.geom(), wsp<double>(c, o.wx64),
+                 wsp<double>(c, o.wy64), wsp<double>(c, o.wz64), wsp<double>(c, o.tp64), lc.kc);
+    }
+    if (c->mixed) {
+      const size_t n = s.n(), nxy = (size_t)s.nx * s.ny;
+      const Launch fl = flat_launch(n);
+      GMG_LAUNCH(c, "convert_f64_f32", (k_convert<float, double>), fl, wsp<double>(c, o.wx64),
+                 wsp<float>(c, o.wx), n);
+      GMG_LAUNCH(c, "convert_f64_f32", (k_convert<float, double>), fl, wsp<double>(c, o.wy64),
+                 wsp<float>(c, o.wy), n);
+      GMG_LAUNCH(c, "convert_f64_f32", (k_convert<float, double>), fl, wsp<double>(c, o.wz64),
+                 wsp<float>(c, o.wz), n);
+      GMG_LAUNCH(c, "convert_f64_f32", (k_convert<float, double>), flat_launch(nxy), wsp<double>(c, o.tp64),
+                 wsp<float>(c, o.tp), nxy);
+    }
+  }
+  // coarsest level: dense matrix on the host, Cholesky inverse, upload
+  const LevelShape& s = L.shapes.back();
+  const int n = (int)s.n();
+  std::vector<double> wx, wy, wz, tp, afine, M;
+  if (nl == 1) {
+    afine.resize(n);
+    note(c, hipMemcpyAsync(afine.data(), c->a, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  } else {
+    const LevelOffsets& o = L.lv[nl - 1];
+    const size_t nxy = (size_t)s.nx * s.ny;
+    wx.resize(n);
+    wy.resize(n);
+    wz.resize(n);
+    tp.resize(nxy);
+    note(c, hipMemcpyAsync(wx.data(), wsp<double>(c, o.wx64), (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    note(c, hipMemcpyAsync(wy.data(), wsp<double>(c, o.wy64), (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    note(c, hipMemcpyAsync(wz.data(), wsp<double>(c, o.wz64), (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    note(c, hipMemcpyAsync(tp.data(), wsp<double>(c, o.tp64), nxy * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  note(c, hipStreamSynchronize(c->stream));
+  if (c->err != hipSuccess) return GMG_ERR_HIP;
+  assemble_coarsest(s, wx, wy, wz, tp, afine.data(), nl == 1, M);
+  if (!spd_inverse(M, n)) return GMG_ERR_NONFINITE;
+  if (c->mixed) {
+    std::vector<float> Mf(M.begin(), M.end());
+    note(c, hipMemcpyAsync(wsp<float>(c, L.cinv), Mf.data(), Mf.size() * 4, hipMemcpyHostToDevice, c->stream));
+    note(c, hipStreamSynchronize(c->stream));
+  } else {
+    note(c, hipMemcpyAsync(wsp<double>(c, L.cinv), M.data(), M.size() * 8, hipMemcpyHostToDevice, c->stream));
+    note(c, hipStreamSynchronize(c->stream));
+  }
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (Sec. 3.2): zero initial guess, red-black symmetric Gauss-Seidel.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+FaceCoef<T> face_coef(gmg_ctx* c, int l) {
+  const LevelOffsets& o = c->L.lv[l];
+  return FaceCoef<T>{wsp<T>(c, o.wx), wsp<T>(c, o.wy), wsp<T>(c, o.wz), wsp<T>(c, o.tp)};
+}
+
+template <typename T>
+const char* tname(const char* f32, const char* f64) {
+  return sizeof(T) == 4 ? f32 : f64;
+}
+
+// Smoothing and residual on one level, for any coefficient storage.
+template <typename T, typename TB, typename Coef>
+void smooth_pre(gmg_ctx* c, int l, T* x, const TB* b, const double* bscale, T* b_out, Coef co) {
+  const LevelShape& s = c->L.shapes[l];
+  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
+  const Geom g = s.geom();
+  const int nu = c->opt.nu_pre;
+  GMG_LAUNCH(c, tname<T>("gs_first_f32", "gs_first_f64"), (k_gs_first<T, TB, Coef>), lc, x, b, bscale, b_out,
+             co, g, lc.kc, nu > 0 ? 1 : 0);
+  if (nu == 0) return;
+  // b_out holds the scaled right side from now on
+  if (b_out) {
+    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
+               (const double*)nullptr, co, g, lc.kc, 1);
+    for (int it = 1; it < nu; ++it) {
+      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
+                 (const double*)nullptr, co, g, lc.kc, 0);
+      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
+                 (const double*)nullptr, co, g, lc.kc, 1);
+    }
+  } else {
+    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
+    for (int it = 1; it < nu; ++it) {
+      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
+      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
+    }
+  }
+}
+
+template <typename T, typename TB, typename Coef>
+void smooth_post(gmg_ctx* c, int l, T* x, const TB* b, const double* bscale, Coef co) {
+  const LevelShape& s = c->L.shapes[l];
+  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
+  const Geom g = s.geom();
+  for (int it = 0; it < c->opt.nu_post; ++it) {
+    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
+    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
+  }
+}
+
+template <typename T, typename TB, typename Coef>
+void resid_restrict(gmg_ctx* c, int l, const T* x, const TB* b, const double* bscale, Coef co, T* bc) {
+  const LevelShape& s = c->L.shapes[l];
+  const LevelShape& cs = c->L.shapes[l + 1];
+  const Launch lc = col_launch(cs.nx, cs.ny, cs.nz, 1 << 16);
+  GMG_LAUNCH(c, tname<T>("resid_restrict_f32", "resid_restrict_f64"), (k_resid_restrict<T, TB, Coef>), lc, x, b,
+             bscale, co, s.geom(), bc, lc.kc);
+}
+
+template <typename T>
+void prolong_add(gmg_ctx* c, int l, T* x, const T* xc) {
+  const LevelShape& s = c->L.shapes[l];
+  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
+  GMG_LAUNCH(c, tname<T>("prolong_add_f32", "prolong_add_f64"), k_prolong_add<T>, lc, x, xc, s.geom(), lc.kc);
+}
+
+template <typename T>
+void coarse_solve(gmg_ctx* c, const T* b, T* x) {
+  const int n = c->nc;
+  const Launch lc{dim3((n + NTHREADS - 1) / NTHREADS), dim3(BX, BY, 1), 0};
+  GMG_LAUNCH(c, tname<T>("coarse_solve_f32", "coarse_solve_f64"), k_coarse_solve<T>, lc,
+             wsp<const T>(c, c->L.cinv), b, x, n);
+}
+
+// Levels >= 1 (face coefficients), right side in lv[l].b, result in lv[l].x.
+template <typename T>
+void vcycle_coarse(gmg_ctx* c, int l) {
+  const int nl = (int)c->L.shapes.size();
+  const LevelOffsets& o = c->L.lv[l];
+  T* x = wsp<T>(c, o.x);
+  const T* b = wsp<T>(c, o.b);
+  if (l == nl - 1) {
+    coarse_solve<T>(c, b, x);
+    return;
+  }
+  const FaceCoef<T> co = face_coef<T>(c, l);
+  smooth_pre<T, T>(c, l, x, b, nullptr, (T*)nullptr, co);
+  resid_restrict<T, T>(c, l, x, b, nullptr, co, wsp<T>(c, c->L.lv[l + 1].b));
+  vcycle_coarse<T>(c, l + 1);
+  prolong_add<T>(c, l, x, wsp<T>(c, c->L.lv[l + 1].x));
+  smooth_post<T, T>(c, l, x, b, nullptr, co);
+}
+
+// z = M (s * u): one V-cycle on the finest level with right side u scaled by
+// *bscale (null = 1); z in the V-cycle precision.
+template <typename T>
+void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
+  const int nl = (int)c->L.shapes.size();
+  const LevelShape& s = c->L.shapes[0];
+  if (nl == 1) {
+    T* b0 = wsp<T>(c, c->L.b0);
+    // scaled copy of the right side, then the direct solve
+    const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
+    if (c->mixed) {
+      GMG_LAUNCH(c, "gs_first_f32", (k_gs_first<float, double, CellCoef<float>>), lc, (float*)z, u, bscale,
+                 (float*)b0, CellCoef<float>{wsp<float>(c, c->L.a32)}, s.geom(), lc.kc, 0);
+    } else {
+      GMG_LAUNCH(c, "gs_first_f64", (k_gs_first<double, double, CellCoef<double>>), lc, (double*)z, u, bscale,
+                 (double*)b0, CellCoef<double>{c->a}, s.geom(), lc.kc, 0);
+    }
+    coarse_solve<T>(c, b0, z);
+    return;
+  }
+  const CellCoef<T> co{c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a};
+  T* bc = wsp<T>(c, c->L.lv[1].b);
+  if (c->mixed) {
+    T* b0 = wsp<T>(c, c->L.b0);
+    smooth_pre<T, double>(c, 0, z, u, bscale, b0, co);
+    resid_restrict<T, T>(c, 0, z, (const T*)b0, nullptr, co, bc);
+    vcycle_coarse<T>(c, 1);
+    prolong_add<T>(c, 0, z, wsp<T>(c, c->L.lv[1].x));
+    smooth_post<T, T>(c, 0, z, (const T*)b0, nullptr, co);
+  } else {
+    smooth_pre<T, double>(c, 0, z, u, bscale, (T*)nullptr, co);
+    resid_restrict<T, double>(c, 0, z, u, bscale, co, bc);
+    vcycle_coarse<T>(c, 1);
+    prolong_add<T>(c, 0, z, wsp<T>(c, c->L.lv[1].x));
+    smooth_post<T, double>(c, 0, z, u, bscale, co);
+  }
+}
+
+void vcycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z) {
+  if (c->mixed)
+    vcycle_fine<float>(c, u, bscale, (float*)z);
+  else
+    vcycle_fine<double>(c, u, bscale, (double*)z);
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES pieces.
+// ---------------------------------------------------------------------------
+
+Launch red_launch(gmg_ctx* c) { return col_launch(c->nx, c->ny, c->nz, MAX_RED_BLOCKS); }
+
+void finalize(gmg_ctx* c, int nblocks, int nv, int mode, double* out, const double* scale, double* out2) {
+  const Launch one{dim3(1), dim3(BX, BY, 1), 0};
+  GMG_LAUNCH(c, "finalize", k_finalize, one, wsp<const double>(c, c->L.partials), nblocks, nv, mode, out, scale,
+             out2);
+}
+
+// r0 = b - A x (x may be null), ||b||^2 and ||r0||^2 into misc[0..1],
+// v_1 scale 1/||r0|| into vscale[0]; r0 stored into V[0] when store.
+void init_residual(gmg_ctx* c, const double* f, const double* x, double pb, double pt, bool store) {
+  const Launch rl = red_launch(c);
+  double* misc = scal_misc(c);
+  GMG_LAUNCH(c, "init_residual", k_init_residual, rl, f, c->a, x, c->L.shapes[0].geom(), pb, pt,
+             store ? wsp<double>(c, c->L.V) : (double*)nullptr, wsp<double>(c, c->L.partials), rl.kc);
+  finalize(c, rl.nblocks(), 2, 0, misc, nullptr, nullptr);
+  // misc[2] = ||r0||, vscale[0] = 1/||r0||
+  const Launch one{dim3(1), dim3(BX, BY, 1), 0};
+  GMG_LAUNCH(c, "finalize", k_finalize, one, wsp<const double>(c, c->L.partials) + rl.nblocks(), rl.nblocks(), 1,
+             2, misc + 2, nullptr, scal_vscale(c));
+}
+
+// One Arnoldi step j: z_j = M v_j, w = A z_j, classical Gram-Schmidt against
+// v_0..v_j (dots fused into the operator pass), ||w||; results in hcol(j).
+void arnoldi_step(gmg_ctx* c, int j) {
+  const size_t N = c->N;
+  double* V = wsp<double>(c, c->L.V);
+  char* Zb = c->ws + c->L.Z + (size_t)j * N * c->L.tsize;
+  double* vs = scal_vscale(c);
+  double* hc = scal_hcol(c, j);
+  vcycle_any(c, V + (size_t)j * N, vs + j, Zb);
+  const Launch rl = red_launch(c);
+  const Geom g = c->L.shapes[0].geom();
+  double* w = V + (size_t)(j + 1) * N;
+  const int nv = j + 1;
+  for (int q0 = 0; q0 < nv; q0 += MAXV) {
+    const int nq = std::min(MAXV, nv - q0);
+    if (q0 == 0) {
+      if (c->mixed)
+        GMG_LAUNCH(c, "op_multidot_zf32", k_op_multidot<float>, rl, (const float*)Zb, c->a, g, w, V, N, nq,
+                   wsp<double>(c, c->L.partials), rl.kc);
+      else
+        GMG_LAUNCH(c, "op_multidot_zf64", k_op_multidot<double>, rl, (const double*)Zb, c->a, g, w, V, N, nq,
+                   wsp<double>(c, c->L.partials), rl.kc);
+    } else {
+      GMG_LAUNCH(c, "multidot", k_multidot, rl, (const double*)w, g, V + (size_t)q0 * N, N, nq,
+                 wsp<double>(c, c->L.partials), rl.kc);
+    }
+    finalize(c, rl.nblocks(), nq, 1, hc + q0, vs + q0, nullptr);
+  }
+  for (int q0 = 0; q0 < nv; q0 += MAXV) {
+    const int nq = std::min(MAXV, nv - q0);
+    const int last = q0 + nq >= nv;
+    GMG_LAUNCH(c, "axpy_norm", k_axpy_norm, rl, w, g, (const double*)(V + (size_t)q0 * N), N, nq,
+               (const double*)(hc + q0), (const double*)(vs + q0), last, wsp<double>(c, c->L.partials), rl.kc);
+  }
+  finalize(c, rl.nblocks(), 1, 2, hc + (j + 1), nullptr, vs + (j + 1));
+}
+
+// phi += sum_{i<k} y_i z_i
+void update_solution(gmg_ctx* c, double* phi, int k) {
+  const Launch lc = col_launch(c->nx, c->ny, c->nz, 1 << 16);
+  const Geom g = c->L.shapes[0].geom();
+  for (int q0 = 0; q0 < k; q0 += MAXV) {
+    const int nq = std::min(MAXV, k - q0);
+    Coeffs16 y{};
+    for (int q = 0; q < nq; ++q) y.v[q] = c->y[q0 + q];
+    char* Zb = c->ws + c->L.Z + (size_t)q0 * c->N * c->L.tsize;
+    if (c->mixed)
+      GMG_LAUNCH(c, "update_zf32", k_update<float>, lc, phi, g, (const float*)Zb, c->N, nq, y, lc.kc);
+    else
+      GMG_LAUNCH(c, "update_zf64", k_update<double>, lc, phi, g, (const double*)Zb, c->N, nq, y, lc.kc);
+  }
+}
+
+int read_back(gmg_ctx* c, const double* dev, int n) {
+  note(c, hipMemcpyAsync(c->pinned, dev, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  note(c, hipStreamSynchronize(c->stream));
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+bool valid_ctx(gmg_ctx* c) { return c != nullptr; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void gmg_default_options(gmg_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->restart = 10;
+  opt->max_iter = 200;
+  opt->nu_pre = 2;
+  opt->nu_post = 2;
+  opt->precision = GMG_MIXED;
+  opt->coarse_max_cells = 4096;
+}
+
+size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt) {
+  Layout L;
+  if (make_layout(nx, ny, nz, 1.0, 1.0, 1.0, opt, &L) != GMG_OK) return 0;
+  return L.total;
+}
+
+int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const double* a_dev,
+              const gmg_options* opt, void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+              gmg_ctx** out) {
+  if (!out || !a_dev || !opt) return GMG_ERR_ARG;
+  *out = nullptr;
+  if (!(hx > 0) || !(hy > 0) || !(hz > 0) || !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz))
+    return GMG_ERR_ARG;
+  Layout L;
+  const int st = make_layout(nx, ny, nz, hx, hy, hz, opt, &L);
+  if (st != GMG_OK) return st;
+  if (!workspace_dev || workspace_bytes < L.total || ((uintptr_t)workspace_dev % ALIGN) != 0)
+    return GMG_ERR_WORKSPACE;
+  gmg_ctx* c = new (std::nothrow) gmg_ctx();
+  if (!c) return GMG_ERR_ARG;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->hx = hx;
+  c->hy = hy;
+  c->hz = hz;
+  c->opt = *opt;
+  c->a = a_dev;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace_dev;
+  c->ws_bytes = workspace_bytes;
+  c->L = L;
+  c->N = L.shapes[0].n();
+  c->mixed = opt->precision == GMG_MIXED;
+  c->nc = (int)L.shapes.back().n();
+  c->err = hipSuccess;
+  c->pinned = nullptr;
+  const int m = opt->restart;
+  c->R.assign((size_t)m * m, 0.0);
+  c->cs.assign(m, 0.0);
+  c->sn.assign(m, 0.0);
+  c->g.assign(m + 1, 0.0);
+  c->y.assign(m, 0.0);
+  if (hipHostMalloc((void**)&c->pinned, (size_t)(MAX_RESTART + 8) * 8, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return GMG_ERR_HIP;
+  }
+  const int r = build_hierarchy(c);
+  if (r != GMG_OK) {
+    gmg_destroy(c);
+    return r;
+  }
+  *out = c;
+  return GMG_OK;
+}
+
+int gmg_update_coefficient(gmg_ctx* c, const double* a_dev) {
+  if (!valid_ctx(c) || !a_dev) return GMG_ERR_ARG;
+  c->a = a_dev;
+  return build_hierarchy(c);
+}
+
+int gmg_set_stream(gmg_ctx* c, void* hip_stream) {
+  if (!valid_ctx(c)) return GMG_ERR_ARG;
+  c->stream = (hipStream_t)hip_stream;
+  return GMG_OK;
+}
+
+int fgmres_solve(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top, double tol, double* phi_dev,
+                 int use_x0, int* iterations, double* res_hist, int res_hist_cap, int* res_hist_len,
+                 double* final_true_relres) {
+  if (!valid_ctx(c) || !f_dev || !phi_dev) return GMG_ERR_ARG;
+  if (!(tol >= 0.0) || !std::isfinite(phi_bot) || !std::isfinite(phi_top)) return GMG_ERR_ARG;
+  if (res_hist_cap < 0 || (res_hist_cap > 0 && !res_hist)) return GMG_ERR_ARG;
+  const int m = c->opt.restart;
+  int it = 0, nhist = 0;
+  auto push_hist = [&](double v) {
+    if (nhist < res_hist_cap) res_hist[nhist] = v;
+    ++nhist;
+  };
+  auto finish = [&](int status, double relres) {
+    if (iterations) *iterations = it;
+    if (res_hist_len) *res_hist_len = std::min(nhist, res_hist_cap);
+    if (final_true_relres) *final_true_relres = relres;
+    return status;
+  };
+  if (!use_x0) {
+    const Launch fl = flat_launch(c->N);
+    GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
+  }
+  double* misc = scal_misc(c);
+  bool first = true;
+  double bnorm = 0.0;
+  while (true) {
+    // r_0 = b - A x_0 into V[0] (the true residual at every restart)
+    init_residual(c, f_dev, (first && !use_x0) ? nullptr : phi_dev, phi_bot, phi_top, true);
+    if (read_back(c, misc, 3) != GMG_OK) return finish(GMG_ERR_HIP, NAN);
+    const double bn2 = c->pinned[0], beta = c->pinned[2];
+    if (!std::isfinite(bn2) || !std::isfinite(beta)) return finish(GMG_ERR_NONFINITE, NAN);
+    if (first) {
+      bnorm = std::sqrt(bn2);
+      if (bnorm == 0.0) {
+        const Launch fl = flat_launch(c->N);
+        GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
+        note(c, hipStreamSynchronize(c->stream));
+        push_hist(0.0);
+        return finish(c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP, 0.0);
+      }
+      push_hist(beta / bnorm);
+      first = false;
+    }
+    if (beta < tol * bnorm) return finish(GMG_OK, beta / bnorm);
+    if (it >= c->opt.max_iter) return finish(GMG_NOT_CONVERGED, beta / bnorm);
+    // Arnoldi cycle
+    std::fill(c->g.begin(), c->g.end(), 0.0);
+    c->g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      if (it >= c->opt.max_iter) break;
+      arnoldi_step(c, j);
+      if (read_back(c, scal_hcol(c, j), j + 2) != GMG_OK) return finish(GMG_ERR_HIP, NAN);
+      std::vector<double> h(c->pinned, c->pinned + j + 2);
+      double colnorm = 0.0;
+      for (double v : h) {
+        if (!std::isfinite(v)) return finish(GMG_ERR_NONFINITE, NAN);
+        colnorm += v * v;
+      }
+      colnorm = std::sqrt(colnorm);
+      const bool breakdown = h[j + 1] <= BREAKDOWN_TOL * colnorm;
+      // apply the previous Givens rotations to the new column, then a new
+      // rotation that zeroes h_{j+1,j}
+      for (int i = 0; i < j; ++i) {
+        const double t = c->cs[i] * h[i] + c->sn[i] * h[i + 1];
+        h[i + 1] = -c->sn[i] * h[i] + c->cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double d = std::hypot(h[j], h[j + 1]);
+      c->cs[j] = d > 0 ? h[j] / d : 1.0;
+      c->sn[j] = d > 0 ? h[j + 1] / d : 0.0;
+      h[j] = d;
+      for (int i = 0; i <= j; ++i) c->R[(size_t)i * m + j] = h[i];
+      c->g[j + 1] = -c->sn[j] * c->g[j];
+      c->g[j] = c->cs[j] * c->g[j];
+      ++it;
+      k = j + 1;
+      const double est = std::fabs(c->g[j + 1]);
+      push_hist(est / bnorm);
+      if (est < tol * bnorm || breakdown) break;
+    }
+    // y = R_k^{-1} g_k, phi += Z_k y
+    for (int i = k - 1; i >= 0; --i) {
+      double s = c->g[i];
+      for (int q = i + 1; q < k; ++q) s -= c->R[(size_t)i * m + q] * c->y[q];
+      const double rii = c->R[(size_t)i * m + i];
+      c->y[i] = rii != 0.0 ? s / rii : 0.0;
+    }
+    if (k > 0) update_solution(c, phi_dev, k);
+  }
+}
+
+int gmg_apply_operator(gmg_ctx* c, const double* x_dev, double* y_dev, double phi_bot, double phi_top) {
+  if (!valid_ctx(c) || !x_dev || !y_dev) return GMG_ERR_ARG;
+  const Launch lc = col_launch(c->nx, c->ny, c->nz, 1 << 16);
+  GMG_LAUNCH(c, "apply_bc", k_apply_bc, lc, x_dev, c->a, c->L.shapes[0].geom(), phi_bot, phi_top, y_dev, lc.kc);
+  note(c, hipStreamSynchronize(c->stream));
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+int gmg_vcycle(gmg_ctx* c, const double* v_dev, double* z_dev) {
+  if (!valid_ctx(c) || !v_dev || !z_dev) return GMG_ERR_ARG;
+  if (c->mixed) {
+    float* z32 = wsp<float>(c, c->L.Z);
+    vcycle_fine<float>(c, v_dev, nullptr, z32);
+    const Launch fl = flat_launch(c->N);
+    GMG_LAUNCH(c, "convert_f32_f64", (k_convert<double, float>), fl, (const float*)z32, z_dev, c->N);
+  } else {
+    vcycle_fine<double>(c, v_dev, nullptr, z_dev);
+  }
+  note(c, hipStreamSynchronize(c->stream));
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+int gmg_face_flux_grad(gmg_ctx* c, const double* phi_dev, const double* lam_dev, double phi_bot, double phi_top,
+                       double* dLda_dev) {
+  if (!valid_ctx(c) || !phi_dev || !lam_dev || !dLda_dev) return GMG_ERR_ARG;
+  const Launch lc = col_launch(c->nx, c->ny, c->nz, 1 << 16);
+  GMG_LAUNCH(c, "face_grad", k_face_grad, lc, phi_dev, lam_dev, c->L.shapes[0].geom(), phi_bot, phi_top,
+             dLda_dev, lc.kc);
+  note(c, hipStreamSynchronize(c->stream));
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+int gmg_get_levels(gmg_ctx* c, int* nlevels, int* shapes, int cap) {
+  if (!valid_ctx(c) || !nlevels) return GMG_ERR_ARG;
+  *nlevels = (int)c->L.shapes.size();
+  for (int l = 0; l < std::min(cap, *nlevels); ++l) {
+    shapes[3 * l] = c->L.shapes[l].nx;
+    shapes[3 * l + 1] = c->L.shapes[l].ny;
+    shapes[3 * l + 2] = c->L.shapes[l].nz;
+  }
+  return GMG_OK;
+}
+
+int gmg_profile_enable(gmg_ctx* c, int enable) {
+  if (!valid_ctx(c)) return GMG_ERR_ARG;
+  c->prof.on = enable != 0;
+  return GMG_OK;
+}
+
+static void profile_collect(gmg_ctx* c) {
+  note(c, hipStreamSynchronize(c->stream));
+  for (auto& r : c->prof.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& t = c->prof.totals[r.name];
+      t.first += ms;
+      t.second += 1;
+      c->prof.names[r.name] = r.name;
+    }
+    c->prof.pool.push_back(r.a);
+    c->prof.pool.push_back(r.b);
+  }
+  c->prof.pending.clear();
+}
+
+int gmg_profile_reset(gmg_ctx* c) {
+  if (!valid_ctx(c)) return GMG_ERR_ARG;
+  profile_collect(c);
+  c->prof.totals.clear();
+  return GMG_OK;
+}
+
+int gmg_profile_read(gmg_ctx* c, const char** names, double* total_ms, long long* launches, int cap, int* count) {
+  if (!valid_ctx(c) || !count) return GMG_ERR_ARG;
+  profile_collect(c);
+  int i = 0;
+  for (auto& kv : c->prof.totals) {
+    if (i < cap) {
+      if (names) names[i] = c->prof.names[kv.first];
+      if (total_ms) total_ms[i] = kv.second.first;
+      if (launches) launches[i] = kv.second.second;
+    }
+    ++i;
+  }
+  *count = i;
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+void gmg_destroy(gmg_ctx* c) {
+  if (!c) return;
+  if (c->prof.on || !c->prof.pending.empty()) (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->prof.pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+const char* gmg_status_string(int s) {
+  switch (s) {
+    case GMG_OK: return "ok";
+    case GMG_NOT_CONVERGED: return "not converged within max_iter Arnoldi steps";
+    case GMG_ERR_ARG: return "invalid argument (null pointer, bad option, non-positive coefficient or tolerance)";
+    case GMG_ERR_SHAPE: return "grid does not coarsen to at most coarse_max_cells cells";
+    case GMG_ERR_NONFINITE: return "non-finite value in the coefficient, right side, initial guess or iteration";
+    case GMG_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case GMG_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

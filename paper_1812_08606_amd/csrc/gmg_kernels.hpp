@@ -1,0 +1,628 @@
+// gmg_kernels.hpp -- gfx950 kernels of the GMG-preconditioned FGMRES solve.
+//
+// Grid layout: (nz, ny, nx), x fastest.  Every stencil kernel maps a block
+// of 64 x 4 threads onto 64 consecutive x-cells of 4 rows and marches each
+// thread along z over a chunk of planes; loads along x are coalesced and the
+// rows above/below come from the same or neighbouring blocks through L2.
+//
+// Discrete operator (eq. e18, Sec. 2.2): (A x)_c = sum_f w_f (x_c - x_nb)/h^2.
+// On the finest level w_f is the arithmetic mean of the two cells' a; on a
+// plate the face coefficient is a_c and the neighbour is the mirrored ghost
+// 2 phi_b - x_c; the Neumann sides carry w = 0.  Coarse levels store their
+// face coefficients: wx[c] is the face on the -x side of cell c (0 at i = 0),
+// wy[c] the -y side (0 at j = 0), wz[c] the -z side (the bottom plate's
+// coefficient at k = 0), and tp[j*nx+i] the top plate's coefficient.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmg {
+
+constexpr int BX = 64;
+constexpr int BY = 4;
+constexpr int NTHREADS = BX * BY;
+constexpr int NWAVES = NTHREADS / 64;
+constexpr int MAXV = 16;             // vectors per multi-dot / multi-axpy launch
+constexpr int MAX_RED_BLOCKS = 4096; // blocks of a reduction launch
+
+struct Geom {
+  int nx, ny, nz;
+  double ihx2, ihy2, ihz2;  // 1 / h^2 per direction
+};
+
+struct Coeffs16 {
+  double v[MAXV];
+};
+
+__device__ __forceinline__ size_t cidx(const Geom& g, int i, int j, int k) {
+  return ((size_t)k * g.ny + j) * g.nx + i;
+}
+
+// Face weights of one cell, already divided by h_d^2.
+template <typename T>
+struct Stencil {
+  T ww, we, ws, wn, wb, wt;
+};
+
+// Finest level: coefficient per cell, face = arithmetic mean.
+template <typename T>
+struct CellCoef {
+  const T* __restrict__ a;
+  __device__ __forceinline__ Stencil<T> load(const Geom& g, int i, int j, int k, size_t c) const {
+    const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+    const T ac = a[c];
+    const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2);
+    Stencil<T> s;
+    s.ww = i > 0 ? (ac + a[c - 1]) * hx : T(0);
+    s.we = i < g.nx - 1 ? (ac + a[c + 1]) * hx : T(0);
+    s.ws = j > 0 ? (ac + a[c - sy]) * hy : T(0);
+    s.wn = j < g.ny - 1 ? (ac + a[c + sy]) * hy : T(0);
+    s.wb = k > 0 ? (ac + a[c - sz]) * hz : ac * (T)g.ihz2;
+    s.wt = k < g.nz - 1 ? (ac + a[c + sz]) * hz : ac * (T)g.ihz2;
+    return s;
+  }
+};
+
+// Coarse levels: stored face coefficients.
+template <typename T>
+struct FaceCoef {
+  const T* __restrict__ wx;
+  const T* __restrict__ wy;
+  const T* __restrict__ wz;
+  const T* __restrict__ tp;
+  __device__ __forceinline__ Stencil<T> load(const Geom& g, int i, int j, int k, size_t c) const {
+    const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+    const T ix = (T)g.ihx2, iy = (T)g.ihy2, iz = (T)g.ihz2;
+    Stencil<T> s;
+    s.ww = wx[c] * ix;
+    s.we = i < g.nx - 1 ? wx[c + 1] * ix : T(0);
+    s.ws = wy[c] * iy;
+    s.wn = j < g.ny - 1 ? wy[c + sy] * iy : T(0);
+    s.wb = wz[c] * iz;
+    s.wt = k < g.nz - 1 ? wz[c + sz] * iz : tp[(size_t)j * g.nx + i] * iz;
+    return s;
+  }
+};
+
+// Values of x at the 6 neighbours (x_c where the face has weight 0; the
+// mirrored ghost 2 pb - x_c / 2 pt - x_c through the plates).
+template <typename T>
+struct Nbrs {
+  T c, w, e, s, n, b, t;
+};
+
+template <typename T, typename TX>
+__device__ __forceinline__ Nbrs<T> load_nbrs(const TX* __restrict__ x, const Geom& g, int i, int j,
+                                             int k, size_t c, T pb2, T pt2) {
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  Nbrs<T> v;
+  v.c = (T)x[c];
+  v.w = i > 0 ? (T)x[c - 1] : v.c;
+  v.e = i < g.nx - 1 ? (T)x[c + 1] : v.c;
+  v.s = j > 0 ? (T)x[c - sy] : v.c;
+  v.n = j < g.ny - 1 ? (T)x[c + sy] : v.c;
+  v.b = k > 0 ? (T)x[c - sz] : pb2 - v.c;
+  v.t = k < g.nz - 1 ? (T)x[c + sz] : pt2 - v.c;
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_cell(const Stencil<T>& s, const Nbrs<T>& v) {
+  return s.ww * (v.c - v.w) + s.we * (v.c - v.e) + s.ws * (v.c - v.s) + s.wn * (v.c - v.n) +
+         s.wb * (v.c - v.b) + s.wt * (v.c - v.t);
+}
+
+// Diagonal of A (a plate face counts twice through its mirrored ghost).
+template <typename T>
+__device__ __forceinline__ T diag_cell(const Stencil<T>& s, const Geom& g, int k) {
+  return s.ww + s.we + s.ws + s.wn + (k > 0 ? s.wb : T(2) * s.wb) + (k < g.nz - 1 ? s.wt : T(2) * s.wt);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions: 64-lane wavefront shuffles, then the 4
+// wave sums in a fixed order; one partial per block and vector.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_store_partials(double (&acc)[NV], int nv, double* __restrict__ partials,
+                                                     int nblocks) {
+  __shared__ double sm[NV][NWAVES];
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (v < nv) {
+      const double s = wave_sum(acc[v]);
+      if (lane == 0) sm[v][wave] = s;
+    }
+  }
+  __syncthreads();
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  if (tid < nv) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w) s += sm[tid][w];
+    partials[(size_t)tid * nblocks + bid] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle kernels (T = float for the mixed-precision preconditioner, double
+// otherwise).
+// ---------------------------------------------------------------------------
+
+// First pre-smoothing half-sweep from x = 0: red cells x = b / D, black cells
+// x = 0 (a red Gauss-Seidel step on a zero guess); with red == 0 (no
+// pre-smoothing) x = 0 everywhere.  b is read as b_in * (*bscale) (the lazily
+// normalised Krylov vector on the finest level) and, when b_out is given,
+// stored there in T (the float32 copy of v_j).
+template <typename T, typename TIn, typename Coef>
+__global__ __launch_bounds__(NTHREADS) void k_gs_first(T* __restrict__ x, const TIn* __restrict__ b_in,
+                                                       const double* __restrict__ bscale,
+                                                       T* __restrict__ b_out, Coef co, Geom g, int kc,
+                                                       int red) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i >= g.nx) return;
+  const double s = bscale ? *bscale : 1.0;
+  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    for (int k = k0; k < k1; ++k) {
+      const size_t c = cidx(g, i, j, k);
+      const T bv = (T)((double)b_in[c] * s);
+      if (b_out) b_out[c] = bv;
+      if (((i + j + k) & 1) || !red) {
+        x[c] = T(0);
+      } else {
+        const Stencil<T> st = co.load(g, i, j, k, c);
+        x[c] = bv / diag_cell(st, g, k);
+      }
+    }
+  }
+}
+
+// Gauss-Seidel half-sweep over the cells of one colour ((i+j+k)%2 ==
+// colour), in place: x_c = (b_c + sum_f w_f x_nb / h^2) / D_c.  Cells of one
+// colour are never neighbours, so the update is order-free.
+template <typename T, typename TB, typename Coef>
+__global__ __launch_bounds__(NTHREADS) void k_gs(T* __restrict__ x, const TB* __restrict__ b,
+                                                 const double* __restrict__ bscale, Coef co, Geom g, int kc,
+                                                 int colour) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i >= g.nx) return;
+  const T s = (T)(bscale ? *bscale : 1.0);
+  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    for (int k = k0 + ((i + j + k0 + colour) & 1); k < k1; k += 2) {
+      const size_t c = cidx(g, i, j, k);
+      const Stencil<T> st = co.load(g, i, j, k, c);
+      const Nbrs<T> v = load_nbrs<T>(x, g, i, j, k, c, T(0), T(0));
+      T off = st.ww * v.w + st.we * v.e + st.ws * v.s + st.wn * v.n;
+      if (k > 0) off += st.wb * v.b;
+      if (k < g.nz - 1) off += st.wt * v.t;
+      x[c] = ((T)b[c] * s + off) / diag_cell(st, g, k);
+    }
+  }
+}
+
+// Residual and restriction: b_coarse(I) = mean over the 8 children of
+// (b - A x).  g is the fine grid (all dimensions even); kc chunks coarse z.
+template <typename T, typename TB, typename Coef>
+__global__ __launch_bounds__(NTHREADS) void k_resid_restrict(const T* __restrict__ x, const TB* __restrict__ b,
+                                                             const double* __restrict__ bscale, Coef co, Geom g,
+                                                             T* __restrict__ bc, int kc) {
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int I = blockIdx.x * BX + threadIdx.x;
+  if (I >= NX) return;
+  const T s = (T)(bscale ? *bscale : 1.0);
+  const int K0 = blockIdx.z * kc, K1 = min(NZ, K0 + kc);
+  for (int J = blockIdx.y * BY + threadIdx.y; J < NY; J += gridDim.y * BY) {
+    for (int K = K0; K < K1; ++K) {
+      T sum = T(0);
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
+        const size_t c = cidx(g, i, j, k);
+        const Stencil<T> st = co.load(g, i, j, k, c);
+        const Nbrs<T> v = load_nbrs<T>(x, g, i, j, k, c, T(0), T(0));
+        sum += (T)b[c] * s - apply_cell(st, v);
+      }
+      bc[((size_t)K * NY + J) * NX + I] = sum * T(0.125);
+    }
+  }
+}
+
+// x_fine += P x_coarse, cell-centred trilinear: per dimension 3/4 of the
+// parent and 1/4 of the nearer coarse neighbour; outside the grid the
+// neighbour is the parent (x, y: Neumann) or minus the parent (z: plates).
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_prolong_add(T* __restrict__ x, const T* __restrict__ xc, Geom g,
+                                                          int kc) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i >= g.nx) return;
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int I = i >> 1;
+  int I2 = I + ((i & 1) ? 1 : -1);
+  if (I2 < 0 || I2 >= NX) I2 = I;
+  const T q3 = T(0.75), q1 = T(0.25);
+  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    const int J = j >> 1;
+    int J2 = J + ((j & 1) ? 1 : -1);
+    if (J2 < 0 || J2 >= NY) J2 = J;
+    for (int k = k0; k < k1; ++k) {
+      const int K = k >> 1;
+      int K2 = K + ((k & 1) ? 1 : -1);
+      T sk = T(1);
+      if (K2 < 0 || K2 >= NZ) {
+        K2 = K;
+        sk = T(-1);
+      }
+      const T* p = xc + (size_t)K * NY * NX;
+      const T* q = xc + (size_t)K2 * NY * NX;
+      const T pl = q3 * (q3 * p[(size_t)J * NX + I] + q1 * p[(size_t)J * NX + I2]) +
+                   q1 * (q3 * p[(size_t)J2 * NX + I] + q1 * p[(size_t)J2 * NX + I2]);
+      const T ql = q3 * (q3 * q[(size_t)J * NX + I] + q1 * q[(size_t)J * NX + I2]) +
+                   q1 * (q3 * q[(size_t)J2 * NX + I] + q1 * q[(size_t)J2 * NX + I2]);
+      const size_t c = cidx(g, i, j, k);
+      x[c] += q3 * pl + q1 * sk * ql;
+    }
+  }
+}
+
+// Coarsest level: x = A_L^{-1} b with the precomputed (symmetric) inverse;
+// thread r forms row r, reading column r of the symmetric inverse so that a
+// wavefront's loads are contiguous.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_coarse_solve(const T* __restrict__ Ainv, const T* __restrict__ b,
+                                                           T* __restrict__ x, int n) {
+  const int r = blockIdx.x * NTHREADS + threadIdx.y * BX + threadIdx.x;
+  if (r >= n) return;
+  T acc = T(0);
+  for (int c = 0; c < n; ++c) acc += Ainv[(size_t)c * n + r] * b[c];
+  x[r] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Outer FGMRES kernels (float64).
+// ---------------------------------------------------------------------------
+
+// b = f + lifting, r = b - A x0 (r = b without x0); partial sums of ||b||^2
+// and ||r||^2; r stored when r_out is given.
+__global__ __launch_bounds__(NTHREADS) void k_init_residual(const double* __restrict__ f,
+                                                            const double* __restrict__ a,
+                                                            const double* __restrict__ x0, Geom g, double pb,
+                                                            double pt, double* __restrict__ r_out,
+                                                            double* __restrict__ partials, int kc) {
+  double acc[2] = {0.0, 0.0};
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const CellCoef<double> co{a};
+  if (i < g.nx) {
+    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+      for (int k = k0; k < k1; ++k) {
+        const size_t c = cidx(g, i, j, k);
+        const double ac = a[c];
+        double bv = f[c];
+        if (k == 0) bv += 2.0 * ac * pb * g.ihz2;
+        if (k == g.nz - 1) bv += 2.0 * ac * pt * g.ihz2;
+        double r = bv;
+        if (x0) {
+          const Stencil<double> st = co.load(g, i, j, k, c);
+          const Nbrs<double> v = load_nbrs<double>(x0, g, i, j, k, c, 0.0, 0.0);
+          r -= apply_cell(st, v);
+        }
+        if (r_out) r_out[c] = r;
+        acc[0] += bv * bv;
+        acc[1] += r * r;
+      }
+    }
+  }
+  block_store_partials<2>(acc, 2, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// w = A z (z promoted to float64) and the dots (w, u_v), v < nv.
+template <typename TZ>
+__global__ __launch_bounds__(NTHREADS) void k_op_multidot(const TZ* __restrict__ z, const double* __restrict__ a,
+                                                          Geom g, double* __restrict__ w,
+                                                          const double* __restrict__ U, size_t stride, int nv,
+                                                          double* __restrict__ partials, int kc) {
+  double acc[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const CellCoef<double> co{a};
+  if (i < g.nx) {
+    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+      for (int k = k0; k < k1; ++k) {
+        const size_t c = cidx(g, i, j, k);
+        const Stencil<double> st = co.load(g, i, j, k, c);
+        const Nbrs<double> v = load_nbrs<double>(z, g, i, j, k, c, 0.0, 0.0);
+        const double az = apply_cell(st, v);
+        w[c] = az;
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+          if (q < nv) acc[q] += az * U[(size_t)q * stride + c];
+      }
+    }
+  }
+  block_store_partials<MAXV>(acc, nv, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// Dots (w, u_v), v < nv.
+__global__ __launch_bounds__(NTHREADS) void k_multidot(const double* __restrict__ w, Geom g,
+                                                       const double* __restrict__ U, size_t stride, int nv,
+                                                       double* __restrict__ partials, int kc) {
+  double acc[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i < g.nx) {
+    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+      for (int k = k0; k < k1; ++k) {
+        const size_t c = cidx(g, i, j, k);
+        const double wv = w[c];
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+          if (q < nv) acc[q] += wv * U[(size_t)q * stride + c];
+      }
+    }
+  }
+  block_store_partials<MAXV>(acc, nv, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// w -= sum_v (h_v * s_v) u_v (h_v = (w, v_v) with v_v = s_v u_v), and the
+// partial sums of ||w||^2 when want_norm.
+__global__ __launch_bounds__(NTHREADS) void k_axpy_norm(double* __restrict__ w, Geom g,
+                                                        const double* __restrict__ U, size_t stride, int nv,
+                                                        const double* __restrict__ hcol,
+                                                        const double* __restrict__ vscale, int want_norm,
+                                                        double* __restrict__ partials, int kc) {
+  double cf[MAXV];
+#pragma unroll
+  for (int q = 0; q < MAXV; ++q) cf[q] = q < nv ? hcol[q] * vscale[q] : 0.0;
+  double acc[1] = {0.0};
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i < g.nx) {
+    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+      for (int k = k0; k < k1; ++k) {
+        const size_t c = cidx(g, i, j, k);
+        double wv = w[c];
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+          if (q < nv) wv -= cf[q] * U[(size_t)q * stride + c];
+        w[c] = wv;
+        acc[0] += wv * wv;
+      }
+    }
+  }
+  if (want_norm) block_store_partials<1>(acc, 1, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// phi += sum_v y_v z_v (z promoted to float64).
+template <typename TZ>
+__global__ __launch_bounds__(NTHREADS) void k_update(double* __restrict__ phi, Geom g, const TZ* __restrict__ Z,
+                                                     size_t stride, int nv, Coeffs16 y, int kc) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i >= g.nx) return;
+  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    for (int k = k0; k < k1; ++k) {
+      const size_t c = cidx(g, i, j, k);
+      double p = phi[c];
+#pragma unroll
+      for (int q = 0; q < MAXV; ++q)
+        if (q < nv) p += y.v[q] * (double)Z[(size_t)q * stride + c];
+      phi[c] = p;
+    }
+  }
+}
+
+// Second reduction stage, one block: sum the per-block partials of nv
+// vectors in a fixed order.  mode 0: out[v] = sum; mode 1: out[v] = sum *
+// scale[v] (dots against lazily normalised vectors); mode 2 (nv = 1):
+// out[0] = sqrt(sum), out2[0] = 1 / sqrt(sum) (0 if the sum is 0).
+__global__ __launch_bounds__(NTHREADS) void k_finalize(const double* __restrict__ partials, int nblocks, int nv,
+                                                       int mode, double* __restrict__ out,
+                                                       const double* __restrict__ scale,
+                                                       double* __restrict__ out2) {
+  __shared__ double sm[NWAVES];
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int b = tid; b < nblocks; b += NTHREADS) s += partials[(size_t)v * nblocks + b];
+    s = wave_sum(s);
+    if ((tid & 63) == 0) sm[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NWAVES; ++w) t += sm[w];
+      if (mode == 0) {
+        out[v] = t;
+      } else if (mode == 1) {
+        out[v] = t * scale[v];
+      } else {
+        const double r = sqrt(t);
+        out[0] = r;
+        out2[0] = r > 0.0 ? 1.0 / r : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// y = A x - lifting (left side of e18 with plate values pb, pt).
+__global__ __launch_bounds__(NTHREADS) void k_apply_bc(const double* __restrict__ x, const double* __restrict__ a,
+                                                       Geom g, double pb, double pt, double* __restrict__ y,
+                                                       int kc) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i >= g.nx) return;
+  const CellCoef<double> co{a};
+  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    for (int k = k0; k < k1; ++k) {
+      const size_t c = cidx(g, i, j, k);
+      const Stencil<double> st = co.load(g, i, j, k, c);
+      const Nbrs<double> v = load_nbrs<double>(x, g, i, j, k, c, 2.0 * pb, 2.0 * pt);
+      y[c] = apply_cell(st, v);
+    }
+  }
+}
+
+// dL/da_c = -1/2 sum_faces (d phi)_f (d lam)_f (see gmg_face_flux_grad).
+__global__ __launch_bounds__(NTHREADS) void k_face_grad(const double* __restrict__ phi,
+                                                        const double* __restrict__ lam, Geom g, double pb,
+                                                        double pt, double* __restrict__ out, int kc) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  if (i >= g.nx) return;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    for (int k = k0; k < k1; ++k) {
+      const size_t c = cidx(g, i, j, k);
+      const double pc = phi[c], lc = lam[c];
+      double s = 0.0;
+      if (i > 0) s += (phi[c - 1] - pc) * (lam[c - 1] - lc) * g.ihx2;
+      if (i < g.nx - 1) s += (phi[c + 1] - pc) * (lam[c + 1] - lc) * g.ihx2;
+      if (j > 0) s += (phi[c - sy] - pc) * (lam[c - sy] - lc) * g.ihy2;
+      if (j < g.ny - 1) s += (phi[c + sy] - pc) * (lam[c + sy] - lc) * g.ihy2;
+      if (k > 0) s += (phi[c - sz] - pc) * (lam[c - sz] - lc) * g.ihz2;
+      if (k < g.nz - 1) s += (phi[c + sz] - pc) * (lam[c + sz] - lc) * g.ihz2;
+      double gsum = -0.5 * s;
+      if (k == 0) gsum -= 2.0 * (pc - pb) * lc * g.ihz2;
+      if (k == g.nz - 1) gsum -= 2.0 * (pc - pt) * lc * g.ihz2;
+      out[c] = gsum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Setup kernels (hierarchy of face coefficients, float64).
+// ---------------------------------------------------------------------------
+
+// Level-1 faces from the finest cell coefficient: mean of the 4 finest faces
+// (each the arithmetic mean of its two cells) on every coarse face; plate
+// faces from the plate coefficients a_c of the first / last layer.
+__global__ __launch_bounds__(NTHREADS) void k_faces_from_cells(const double* __restrict__ a, Geom g,
+                                                               double* __restrict__ wx, double* __restrict__ wy,
+                                                               double* __restrict__ wz, double* __restrict__ tp,
+                                                               int kc) {
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int I = blockIdx.x * BX + threadIdx.x;
+  if (I >= NX) return;
+  const int K0 = blockIdx.z * kc, K1 = min(NZ, K0 + kc);
+  auto A = [&](int i, int j, int k) { return a[cidx(g, i, j, k)]; };
+  for (int J = blockIdx.y * BY + threadIdx.y; J < NY; J += gridDim.y * BY) {
+    for (int K = K0; K < K1; ++K) {
+      const size_t C = ((size_t)K * NY + J) * NX + I;
+      double sx = 0.0, sy = 0.0, sz = 0.0;
+      for (int p = 0; p < 2; ++p) {
+        for (int q = 0; q < 2; ++q) {
+          if (I > 0) sx += 0.5 * (A(2 * I - 1, 2 * J + p, 2 * K + q) + A(2 * I, 2 * J + p, 2 * K + q));
+          if (J > 0) sy += 0.5 * (A(2 * I + p, 2 * J - 1, 2 * K + q) + A(2 * I + p, 2 * J, 2 * K + q));
+          if (K > 0)
+            sz += 0.5 * (A(2 * I + p, 2 * J + q, 2 * K - 1) + A(2 * I + p, 2 * J + q, 2 * K));
+          else
+            sz += A(2 * I + p, 2 * J + q, 0);
+        }
+      }
+      wx[C] = 0.25 * sx;
+      wy[C] = 0.25 * sy;
+      wz[C] = 0.25 * sz;
+      if (K == NZ - 1) {
+        double st = 0.0;
+        for (int p = 0; p < 2; ++p)
+          for (int q = 0; q < 2; ++q) st += A(2 * I + p, 2 * J + q, g.nz - 1);
+        tp[(size_t)J * NX + I] = 0.25 * st;
+      }
+    }
+  }
+}
+
+// Level l+1 faces from level l faces (g = level l grid).
+__global__ __launch_bounds__(NTHREADS) void k_coarsen_faces(const double* __restrict__ wx,
+                                                            const double* __restrict__ wy,
+                                                            const double* __restrict__ wz,
+                                                            const double* __restrict__ tp, Geom g,
+                                                            double* __restrict__ cwx, double* __restrict__ cwy,
+                                                            double* __restrict__ cwz, double* __restrict__ ctp,
+                                                            int kc) {
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int I = blockIdx.x * BX + threadIdx.x;
+  if (I >= NX) return;
+  const int K0 = blockIdx.z * kc, K1 = min(NZ, K0 + kc);
+  for (int J = blockIdx.y * BY + threadIdx.y; J < NY; J += gridDim.y * BY) {
+    for (int K = K0; K < K1; ++K) {
+      const size_t C = ((size_t)K * NY + J) * NX + I;
+      double sx = 0.0, sy = 0.0, sz = 0.0;
+      for (int p = 0; p < 2; ++p) {
+        for (int q = 0; q < 2; ++q) {
+          sx += wx[cidx(g, 2 * I, 2 * J + p, 2 * K + q)];
+          sy += wy[cidx(g, 2 * I + p, 2 * J, 2 * K + q)];
+          sz += wz[cidx(g, 2 * I + p, 2 * J + q, 2 * K)];
+        }
+      }
+      cwx[C] = 0.25 * sx;
+      cwy[C] = 0.25 * sy;
+      cwz[C] = 0.25 * sz;
+      if (K == NZ - 1) {
+        double st = 0.0;
+        for (int p = 0; p < 2; ++p)
+          for (int q = 0; q < 2; ++q) st += tp[(size_t)(2 * J + p) * g.nx + 2 * I + q];
+        ctp[(size_t)J * NX + I] = 0.25 * st;
+      }
+    }
+  }
+}
+
+// Per-block minimum of a and count of non-finite entries (flat grid-stride).
+__global__ __launch_bounds__(NTHREADS) void k_check_coef(const double* __restrict__ a, size_t n,
+                                                         double* __restrict__ partials) {
+  __shared__ double smin[NTHREADS];
+  __shared__ double sbad[NTHREADS];
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  double mn = 1.0e308, bad = 0.0;
+  for (size_t c = (size_t)blockIdx.x * NTHREADS + tid; c < n; c += (size_t)gridDim.x * NTHREADS) {
+    const double v = a[c];
+    if (!isfinite(v)) bad += 1.0;
+    else mn = fmin(mn, v);
+  }
+  smin[tid] = mn;
+  sbad[tid] = bad;
+  __syncthreads();
+  for (int s = NTHREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      smin[tid] = fmin(smin[tid], smin[tid + s]);
+      sbad[tid] += sbad[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    partials[2 * blockIdx.x] = smin[0];
+    partials[2 * blockIdx.x + 1] = sbad[0];
+  }
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(NTHREADS) void k_convert(const TI* __restrict__ in, TO* __restrict__ out, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * NTHREADS + threadIdx.y * BX + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * NTHREADS)
+    out[c] = (TO)in[c];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_fill(T* __restrict__ out, T v, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * NTHREADS + threadIdx.y * BX + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * NTHREADS)
+    out[c] = v;
+}
+
+}  // namespace gmg

@@ -1,0 +1,253 @@
+"""Python binding of the C ABI (include/gmg.h): argument marshalling only.
+
+PyTorch provides device memory (the caller's tensors and the solver's
+workspace) and the stream; every step of the solve runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+
+FP64, MIXED = 0, 1
+_PRECISION = {"fp64": FP64, "mixed": MIXED}
+OK, NOT_CONVERGED = 0, 1
+
+
+class GMGError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.load().gmg_status_string(status).decode()
+        super().__init__(f"{where}: status {status}: {msg}")
+
+
+@dataclass
+class SolveResult:
+    phi: torch.Tensor
+    status: int
+    iterations: int
+    res_hist: list = field(default_factory=list)
+    final_relres: float = float("nan")
+
+    @property
+    def converged(self) -> bool:
+        return self.status == OK
+
+
+def _check_field(t: torch.Tensor, shape, name: str, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device, got {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the solver on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class GMGPoisson:
+    """Hierarchy and workspace for -div(a grad phi) = f on a (nz, ny, nx) grid
+    (eq. e18), solved by FGMRES(restart) with one V-cycle per step.
+
+    a: float64 CUDA/HIP tensor (nz, ny, nx), > 0.  h: (hx, hy, hz), default
+    unit cube.  precision: "mixed" (float32 V-cycle) or "fp64"."""
+
+    def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
+                 max_iter: int = 200, nu_pre: int = 2, nu_post: int = 2,
+                 coarse_max_cells: int = 4096):
+        self._lib = _lib.load()
+        if a.dim() != 3:
+            raise ValueError("a must be 3-D (nz, ny, nx)")
+        self.shape = tuple(a.shape)
+        nz, ny, nx = self.shape
+        _check_field(a, self.shape, "a")
+        self.device = a.device
+        self.h = tuple(float(v) for v in (h if h is not None else (1.0 / nx, 1.0 / ny, 1.0 / nz)))
+        if precision not in _PRECISION:
+            raise ValueError(f"precision must be one of {sorted(_PRECISION)}")
+        self.precision = precision
+        opt = _lib.Options()
+        self._lib.gmg_default_options(ctypes.byref(opt))
+        opt.restart, opt.max_iter = int(restart), int(max_iter)
+        opt.nu_pre, opt.nu_post = int(nu_pre), int(nu_post)
+        opt.precision = _PRECISION[precision]
+        opt.coarse_max_cells = int(coarse_max_cells)
+        self.options = opt
+        nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
+        if nbytes == 0:
+            raise GMGError(-2, "gmg_workspace_bytes")
+        self.workspace_bytes = int(nbytes)
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self._ws = raw[off:off + nbytes]
+        self._a = a
+        self._stream = None
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            st = self._lib.gmg_setup(nx, ny, nz, *self.h, _ptr(a), ctypes.byref(opt),
+                                     _ptr(self._ws), ctypes.c_size_t(nbytes),
+                                     ctypes.c_void_p(stream), ctypes.byref(self._ctx))
+        if st != OK:
+            self._ctx = ctypes.c_void_p()
+            raise GMGError(st, "gmg_setup")
+        self._stream = stream
+
+    # -- plumbing ---------------------------------------------------------
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            self._lib.gmg_set_stream(self._ctx, ctypes.c_void_p(s))
+            self._stream = s
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            self._lib.gmg_destroy(ctx)
+            self._ctx = ctypes.c_void_p()
+
+    close = __del__
+
+    @property
+    def levels(self):
+        n = ctypes.c_int()
+        shapes = (ctypes.c_int * 96)()
+        self._lib.gmg_get_levels(self._ctx, ctypes.byref(n), shapes, 32)
+        return [tuple(shapes[3 * i:3 * i + 3]) for i in range(min(n.value, 32))]
+
+    # -- operations -------------------------------------------------------
+    def update_coefficient(self, a: torch.Tensor):
+        _check_field(a, self.shape, "a", self.device)
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.gmg_update_coefficient(self._ctx, _ptr(a))
+        if st != OK:
+            raise GMGError(st, "gmg_update_coefficient")
+        self._a = a
+
+    def solve(self, f: torch.Tensor, phi_bot: float = 0.0, phi_top: float = 1.0, tol: float = 1e-8,
+              x0: torch.Tensor | None = None, out: torch.Tensor | None = None,
+              raise_on_error: bool = True) -> SolveResult:
+        _check_field(f, self.shape, "f", self.device)
+        if out is None:
+            out = torch.empty_like(f)
+        _check_field(out, self.shape, "out", self.device)
+        use_x0 = 0
+        if x0 is not None:
+            _check_field(x0, self.shape, "x0", self.device)
+            if x0.data_ptr() != out.data_ptr():
+                out.copy_(x0)
+            use_x0 = 1
+        cap = int(self.options.max_iter) + 2
+        hist = (ctypes.c_double * cap)()
+        its, nh = ctypes.c_int(0), ctypes.c_int(0)
+        rel = ctypes.c_double(float("nan"))
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.fgmres_solve(self._ctx, _ptr(f), float(phi_bot), float(phi_top), float(tol),
+                                        _ptr(out), use_x0, ctypes.byref(its), hist, cap,
+                                        ctypes.byref(nh), ctypes.byref(rel))
+        if st < 0 and raise_on_error:
+            raise GMGError(st, "fgmres_solve")
+        return SolveResult(phi=out, status=st, iterations=its.value,
+                           res_hist=list(hist[:nh.value]), final_relres=rel.value)
+
+    def apply(self, x: torch.Tensor, phi_bot: float = 0.0, phi_top: float = 0.0) -> torch.Tensor:
+        """A x - lifting (left side of e18 with the given plate values)."""
+        _check_field(x, self.shape, "x", self.device)
+        y = torch.empty_like(x)
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.gmg_apply_operator(self._ctx, _ptr(x), _ptr(y), float(phi_bot), float(phi_top))
+        if st != OK:
+            raise GMGError(st, "gmg_apply_operator")
+        return y
+
+    def vcycle(self, v: torch.Tensor) -> torch.Tensor:
+        """One V-cycle from a zero guess: z = M v."""
+        _check_field(v, self.shape, "v", self.device)
+        z = torch.empty_like(v)
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.gmg_vcycle(self._ctx, _ptr(v), _ptr(z))
+        if st != OK:
+            raise GMGError(st, "gmg_vcycle")
+        return z
+
+    def face_flux_grad(self, phi: torch.Tensor, lam: torch.Tensor, phi_bot: float, phi_top: float):
+        _check_field(phi, self.shape, "phi", self.device)
+        _check_field(lam, self.shape, "lam", self.device)
+        out = torch.empty_like(phi)
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.gmg_face_flux_grad(self._ctx, _ptr(phi), _ptr(lam), float(phi_bot),
+                                              float(phi_top), _ptr(out))
+        if st != OK:
+            raise GMGError(st, "gmg_face_flux_grad")
+        return out
+
+    # -- profiling --------------------------------------------------------
+    def profile(self, enable: bool = True):
+        self._lib.gmg_profile_enable(self._ctx, int(bool(enable)))
+
+    def profile_reset(self):
+        self._lib.gmg_profile_reset(self._ctx)
+
+    def profile_read(self) -> dict:
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_longlong * cap)()
+        n = ctypes.c_int()
+        with torch.cuda.device(self.device):
+            self._lib.gmg_profile_read(self._ctx, names, ms, cnt, cap, ctypes.byref(n))
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(n.value, cap))}
+
+
+class _PoissonSolve(torch.autograd.Function):
+    """phi = A(a)^{-1} (f + lifting(a)); the backward solves the adjoint with
+    the same (self-adjoint) operator and hierarchy: lambda = A^{-1} dL/dphi,
+    dL/df = lambda, dL/da from the face products of grad phi and grad lambda."""
+
+    @staticmethod
+    def forward(ctx, f, a, phi_bot, phi_top, tol, precision, kwargs):
+        solver = GMGPoisson(a.detach(), precision=precision, **kwargs)
+        res = solver.solve(f.detach().contiguous(), phi_bot, phi_top, tol)
+        if res.status != OK:
+            raise GMGError(res.status, "poisson_solve forward")
+        ctx.solver = solver
+        ctx.bc = (float(phi_bot), float(phi_top))
+        ctx.tol = tol
+        ctx.iterations = res.iterations
+        ctx.save_for_backward(res.phi)
+        return res.phi
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        (phi,) = ctx.saved_tensors
+        solver = ctx.solver
+        adj = solver.solve(grad_phi.contiguous(), 0.0, 0.0, ctx.tol)
+        if adj.status != OK:
+            raise GMGError(adj.status, "poisson_solve backward (adjoint)")
+        lam = adj.phi
+        dLda = solver.face_flux_grad(phi, lam, *ctx.bc) if ctx.needs_input_grad[1] else None
+        dLdf = lam if ctx.needs_input_grad[0] else None
+        return dLdf, dLda, None, None, None, None, None
+
+
+def poisson_solve(f: torch.Tensor, a: torch.Tensor, phi_bot: float = 0.0, phi_top: float = 1.0,
+                  tol: float = 1e-8, precision: str = "mixed", **kwargs) -> torch.Tensor:
+    """Differentiable solve of e18: returns phi; gradients flow to f and a."""
+    return _PoissonSolve.apply(f, a, phi_bot, phi_top, tol, precision, kwargs)

@@ -1,0 +1,416 @@
+"""GPU path (HIP library through the C ABI) against the CPU oracle.
+
+FP64: element-wise relative agreement 1e-10 in phi at a fixed step count
+(tol = 0, max_iter = k), 1e-12..1e-13 for the single operations.  Mixed
+precision: the float32 V-cycle against the oracle's float32 V-cycle, and the
+converged phi against the FP64 oracle within the residual bound."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import coefficient_gradient
+from oracle.exact import spectral_eigenvalues
+from oracle.fgmres import solve_poisson
+from oracle.multigrid import build_hierarchy, vcycle
+from oracle.operator import apply_operator, rhs
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+import paper_1812_08606_amd as gm  # noqa: E402  (fails loudly if the library is missing)
+DEV = torch.device("cuda:0")
+
+
+def T(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def npy(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _rand_problem(shape_xyz, seed, contrast=1e2):
+    nx, ny, nz = shape_xyz
+    rng = np.random.default_rng(seed)
+    a = np.exp(rng.uniform(-0.5, 0.5, (nz, ny, nx)) * np.log(contrast))
+    f = rng.standard_normal((nz, ny, nx))
+    h = (1.0 / nx, 1.3 / ny, 0.9 / nz)
+    return a, f, h
+
+
+# shapes (nx, ny, nz): ragged x tail, odd sizes, single-level grids, several
+# coarsening levels
+OP_SHAPES = [(70, 12, 8), (5, 3, 2), (1, 1, 1), (33, 17, 7), (128, 4, 6), (64, 64, 64)]
+VC_SHAPES = [(48, 40, 36), (70, 12, 8), (64, 64, 64), (6, 4, 10), (3, 5, 7), (130, 8, 4)]
+
+
+@pytest.mark.parametrize("shape", OP_SHAPES)
+def test_operator_matches_oracle(shape):
+    print(f"operator {shape}", flush=True)
+    a, f, h = _rand_problem(shape, 1)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(a.shape)
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64")
+    y = npy(s.apply(T(x), 0.3, -1.2))
+    ref = apply_operator(x, a, h, 0.3, -1.2)
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape", VC_SHAPES)
+def test_vcycle_fp64_matches_oracle(shape):
+    print(f"vcycle fp64 {shape}", flush=True)
+    a, f, h = _rand_problem(shape, 3)
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64")
+    hier = build_hierarchy(a, h, nu_pre=2, nu_post=2)
+    assert [tuple(l.shape) for l in hier.levels] == s.levels
+    z = npy(s.vcycle(T(f)))
+    ref = vcycle(hier, f)
+    assert rel(z, ref) < 1e-12
+    np.testing.assert_allclose(z, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape", VC_SHAPES)
+def test_vcycle_mixed_matches_float32_oracle(shape):
+    print(f"vcycle mixed {shape}", flush=True)
+    a, f, h = _rand_problem(shape, 4)
+    s = gm.GMGPoisson(T(a), h=h, precision="mixed")
+    hier = build_hierarchy(a, h, nu_pre=2, nu_post=2, dtype=np.float32)
+    z = npy(s.vcycle(T(f)))
+    ref = vcycle(hier, f.astype(np.float32)).astype(np.float64)
+    assert rel(z, ref) < 2e-5
+
+
+@pytest.mark.parametrize("nu", [(0, 1), (1, 0), (1, 1), (3, 2)])
+def test_vcycle_sweep_counts(nu):
+    a, f, h = _rand_problem((16, 16, 16), 5)
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64", nu_pre=nu[0], nu_post=nu[1])
+    hier = build_hierarchy(a, h, nu_pre=nu[0], nu_post=nu[1])
+    assert rel(npy(s.vcycle(T(f))), vcycle(hier, f)) < 1e-12
+
+
+CASES = [  # (workload, n, k steps, restart)
+    (1, 32, 5, 10),
+    (2, 32, 8, 5),   # crosses two restarts
+    (3, 64, 10, 10),
+    (5, 32, 6, 10),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fgmres_fp64_fixed_steps_matches_oracle(case):
+    cfg, n, k, m = case
+    print(f"fgmres fp64 workload {cfg} n={n} k={k}", flush=True)
+    p = make_config(cfg, n=n)
+    s = gm.GMGPoisson(T(p.a), precision="fp64", restart=m, max_iter=k)
+    res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=0.0)
+    ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=0.0, max_iter=k, restart=m)
+    assert res.status == gm.solver.NOT_CONVERGED and res.iterations == k == ref.iterations
+    assert rel(npy(res.phi), ref.x) < 1e-10
+    gh, oh = np.array(res.res_hist), np.array(ref.res_hist)
+    assert len(gh) == len(oh) == k + 1
+    np.testing.assert_allclose(gh, oh, rtol=1e-6)
+
+
+def _converged_pair(p, precision, tol=1e-8, **kw):
+    s = gm.GMGPoisson(T(p.a), precision=precision, **kw)
+    return s, s.solve(T(p.f), p.phi_bot, p.phi_top, tol=tol)
+
+
+def test_config1_fp64_converged_matches_oracle():
+    p = make_config(1)  # 64^3, a = 1
+    s, res = _converged_pair(p, "fp64")
+    ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8)
+    print(f"config1 fp64: gpu {res.iterations} steps, oracle {ref.iterations}", flush=True)
+    assert res.converged and ref.converged
+    assert abs(res.iterations - ref.iterations) <= 1
+    if res.iterations != ref.iterations:
+        ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=0.0, max_iter=res.iterations)
+        res = gm.GMGPoisson(T(p.a), precision="fp64", max_iter=res.iterations).solve(
+            T(p.f), p.phi_bot, p.phi_top, tol=0.0)
+    assert rel(npy(res.phi), ref.x) < 1e-10
+
+
+def test_config1_mixed_within_residual_bound():
+    p = make_config(1)
+    s, res = _converged_pair(p, "mixed")
+    ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8)
+    assert res.converged and res.final_relres < 1e-8
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    phi = npy(res.phi)
+    r_gpu = np.linalg.norm(b - apply_operator(phi, p.a, p.h)) / np.linalg.norm(b)
+    assert r_gpu < 1e-8
+    lam_min = spectral_eigenvalues(p.a.shape, p.h).min()
+    bound = (r_gpu + ref.true_relres) * np.linalg.norm(b) / lam_min
+    err = np.linalg.norm(phi - ref.x)
+    print(f"config1 mixed: {res.iterations} steps (fp64 oracle {ref.iterations}), "
+          f"|phi - phi_fp64| / |phi_fp64| = {err / np.linalg.norm(ref.x):.2e}", flush=True)
+    assert err <= bound
+    assert res.iterations <= ref.iterations + 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_filament_full_size_residual(precision):
+    """256^3, max(a) = 1e3: converged phi checked by the oracle's operator."""
+    p = make_config(2)
+    s, res = _converged_pair(p, precision)
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    r = np.linalg.norm(b - apply_operator(npy(res.phi), p.a, p.h)) / np.linalg.norm(b)
+    print(f"filament 256^3 {precision}: {res.iterations} steps, true relres {r:.2e} "
+          f"(reported {res.final_relres:.2e})", flush=True)
+    assert res.converged and r < 1e-8
+    assert abs(r - res.final_relres) <= 1e-3 * r + 1e-15
+
+
+def test_operator_full_size_sampled():
+    """512^3 (the headline grid): A x at 2000 sampled cells, stencil written
+    out per cell from e18."""
+    n = 512
+    p = make_config(3, n=n)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(p.a.shape)
+    s = gm.GMGPoisson(T(p.a), precision="mixed")
+    y = npy(s.apply(T(x), p.phi_bot, p.phi_top))
+    h2 = (1.0 / n) ** 2
+    a = p.a
+    for _ in range(2000):
+        k, j, i = (int(v) for v in rng.integers(0, n, 3))
+        acc = 0.0
+        for dk, dj, di in ((0, 0, 1), (0, 0, -1), (0, 1, 0), (0, -1, 0), (1, 0, 0), (-1, 0, 0)):
+            kk, jj, ii = k + dk, j + dj, i + di
+            if not (0 <= jj < n and 0 <= ii < n):
+                continue
+            if kk < 0 or kk >= n:
+                pb = p.phi_bot if kk < 0 else p.phi_top
+                acc += a[k, j, i] * (x[k, j, i] - (2 * pb - x[k, j, i])) / h2
+            else:
+                acc += 0.5 * (a[k, j, i] + a[kk, jj, ii]) * (x[k, j, i] - x[kk, jj, ii]) / h2
+        assert abs(y[k, j, i] - acc) <= 1e-12 * (abs(acc) + a[k, j, i] / h2)
+
+
+def test_warm_start_time_loop_matches_oracle():
+    """Per-step coefficient renewal and warm start (Sec. 2.1; Sec. 3.2): the
+    two-filament workload advected one cell per step, 64^3, FP64."""
+    n = 64
+    prev_g = prev_o = None
+    s = None
+    for step in range(3):
+        p = make_config(5, n=n, step=step)
+        a = T(p.a)
+        if s is None:
+            s = gm.GMGPoisson(a, precision="fp64")
+        else:
+            s.update_coefficient(a)
+        res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8, x0=prev_g)
+        ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=prev_o)
+        print(f"time step {step}: gpu {res.iterations}, oracle {ref.iterations}", flush=True)
+        assert res.converged and res.iterations == ref.iterations
+        assert rel(npy(res.phi), ref.x) < 1e-10
+        prev_g, prev_o = res.phi.clone(), ref.x
+
+
+def test_determinism():
+    p = make_config(2, n=32)
+    s = gm.GMGPoisson(T(p.a), precision="mixed")
+    r1 = npy(s.solve(T(p.f), p.phi_bot, p.phi_top).phi)
+    r2 = npy(s.solve(T(p.f), p.phi_bot, p.phi_top).phi)
+    assert np.array_equal(r1, r2)
+
+
+# ---------------------------------------------------------------- edge cases
+def test_zero_right_side_gives_zero():
+    p = make_config(1, n=16)
+    s = gm.GMGPoisson(T(p.a), precision="fp64")
+    x0 = torch.ones(p.a.shape, dtype=torch.float64, device=DEV)
+    res = s.solve(torch.zeros_like(x0), 0.0, 0.0, x0=x0)
+    assert res.status == 0 and res.iterations == 0 and not res.phi.abs().max().item()
+
+
+def test_max_iter_exhausted():
+    p = make_config(3, n=16)
+    s = gm.GMGPoisson(T(p.a), precision="fp64", max_iter=2)
+    res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-14)
+    assert res.status == gm.solver.NOT_CONVERGED and res.iterations == 2 and len(res.res_hist) == 3
+
+
+def test_exact_initial_guess_takes_no_steps():
+    p = make_config(1, n=16)
+    s = gm.GMGPoisson(T(p.a), precision="fp64")
+    phi = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-12).phi
+    res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8, x0=phi.clone())
+    assert res.status == 0 and res.iterations == 0
+
+
+def test_single_level_grid_breaks_down_happily():
+    """No coarsening (odd sizes): the V-cycle is the exact inverse, so A z_1 =
+    v_1 and the first step ends the solve exactly."""
+    a, f, h = _rand_problem((3, 5, 7), 8)
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64")
+    res = s.solve(T(f), 0.2, 0.7, tol=1e-12)
+    assert res.status == 0 and res.iterations == 1
+    b = rhs(f, a, h, 0.2, 0.7)
+    assert np.linalg.norm(b - apply_operator(npy(res.phi), a, h)) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_error_statuses():
+    p = make_config(1, n=16)
+    a = T(p.a)
+    f = T(p.f)
+    s = gm.GMGPoisson(a, precision="mixed")
+    bad = f.clone()
+    bad[3, 4, 5] = float("nan")
+    assert s.solve(bad, 0.0, 1.0, raise_on_error=False).status == -3
+    with pytest.raises(gm.GMGError) as e:
+        gm.GMGPoisson(-a)
+    assert e.value.status == -1
+    an = a.clone()
+    an[0, 0, 0] = float("inf")
+    with pytest.raises(gm.GMGError) as e:
+        gm.GMGPoisson(an)
+    assert e.value.status == -3
+    with pytest.raises(gm.GMGError) as e:
+        gm.GMGPoisson(torch.ones((50, 50, 50), dtype=torch.float64, device=DEV))  # 25^3 coarsest
+    assert e.value.status == -2
+    assert s.solve(f, 0.0, 1.0, tol=-1.0, raise_on_error=False).status == -1
+
+
+def test_workspace_too_small_rejected():
+    import ctypes
+    from paper_1812_08606_amd import _lib
+    lib = _lib.load()
+    opt = _lib.Options()
+    lib.gmg_default_options(ctypes.byref(opt))
+    a = torch.ones((16, 16, 16), dtype=torch.float64, device=DEV)
+    need = lib.gmg_workspace_bytes(16, 16, 16, ctypes.byref(opt))
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    ctx = ctypes.c_void_p()
+    st = lib.gmg_setup(16, 16, 16, 1 / 16, 1 / 16, 1 / 16, ctypes.c_void_p(a.data_ptr()), ctypes.byref(opt),
+                       ctypes.c_void_p(ws.data_ptr()), need - 256, None, ctypes.byref(ctx))
+    assert st == -4 and not ctx.value
+
+
+# ---------------------------------------------------------------- gradients
+def test_face_flux_grad_matches_oracle():
+    a, f, h = _rand_problem((70, 12, 8), 9)
+    rng = np.random.default_rng(10)
+    phi, lam = rng.standard_normal((2,) + a.shape)
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64")
+    g = npy(s.face_flux_grad(T(phi), T(lam), 0.4, 1.5))
+    ref = coefficient_gradient(phi, lam, h, 0.4, 1.5)
+    np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+
+
+def _probe_loss(phi, mask, h):
+    idx = torch.nonzero(mask)
+    k, j, i = idx[:, 0], idx[:, 1], idx[:, 2]
+    gx = (phi[k, j, i + 1] - phi[k, j, i - 1]) / (2 * h)
+    gy = (phi[k, j + 1, i] - phi[k, j - 1, i]) / (2 * h)
+    gz = (phi[k + 1, j, i] - phi[k - 1, j, i]) / (2 * h)
+    return ((gx ** 2 + gy ** 2 + gz ** 2) * h ** 3).sum()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autograd_matches_oracle_adjoint(precision):
+    """Backward of poisson_solve against the oracle's adjoint gradient
+    (pinned itself by a dense autograd solve and by finite differences)."""
+    from oracle.adjoint import solve_and_gradient
+    p = make_config(4, n=16)
+    n = 16
+    from workloads import probe_box_mask
+    mask = torch.tensor(probe_box_mask(n, box=((0.3, 0.7), (0.3, 0.7), (0.3, 0.7))), device=DEV)
+    a = T(p.a).requires_grad_(True)
+    f = T(p.f).requires_grad_(True)
+    phi = gm.poisson_solve(f, a, p.phi_bot, p.phi_top, tol=1e-13, precision=precision)
+    L = _probe_loss(phi, mask, 1.0 / n)
+    L.backward()
+    phi_leaf = phi.detach().clone().requires_grad_(True)
+    _probe_loss(phi_leaf, mask, 1.0 / n).backward()
+    gphi = npy(phi_leaf.grad)
+    _, lam, dLda, fwd, adj = solve_and_gradient(p.a, p.f, p.h, p.phi_bot, p.phi_top, gphi, tol=1e-13)
+    np.testing.assert_allclose(npy(f.grad), lam, rtol=0, atol=1e-8 * np.abs(lam).max())
+    np.testing.assert_allclose(npy(a.grad), dLda, rtol=0, atol=1e-8 * np.abs(dLda).max())
+
+
+def _grads(phi, mask, h):
+    idx = torch.nonzero(mask)
+    k, j, i = idx[:, 0], idx[:, 1], idx[:, 2]
+    return ((phi[k, j, i + 1] - phi[k, j, i - 1]) / (2 * h),
+            (phi[k, j + 1, i] - phi[k, j - 1, i]) / (2 * h),
+            (phi[k + 1, j, i] - phi[k - 1, j, i]) / (2 * h))
+
+
+def test_gradient_finite_differences_config4():
+    """Config 4 (256^3, max(a) = 1e3): adjoint dL/da and dL/df against the
+    central difference (L(a + d e_c) - L(a - d e_c)) / 2d with relative step
+    d = 1e-6 on 20 seeded cells near the probe box.
+
+    L changes by only ~1e-10 of itself at this step, below the noise of
+    independent re-solves, so each perturbed solution is formed as
+    phi_0 + e with A_+- e = b_+- - A_+- phi_0 solved in FP64 to 1e-12 of that
+    residual, and L_+ - L_- is summed from the gradients of e_+ and e_-
+    (2 grad phi_0 . (grad e_+ - grad e_-) + |grad e_+|^2 - |grad e_-|^2)."""
+    p = make_config(4)
+    n = p.shape[0]
+    h = 1.0 / n
+    from workloads import probe_box_mask
+    mask = torch.tensor(probe_box_mask(n), device=DEV)
+    a = T(p.a).requires_grad_(True)
+    f = T(p.f).requires_grad_(True)
+    phi = gm.poisson_solve(f, a, p.phi_bot, p.phi_top, tol=1e-8, precision="mixed")
+    L = _probe_loss(phi, mask, h)
+    L.backward()
+    ga, gf = npy(a.grad), npy(f.grad)
+    a0, f0 = T(p.a), T(p.f)
+    solver = gm.GMGPoisson(a0, precision="fp64")
+    phi0 = solver.solve(f0, p.phi_bot, p.phi_top, tol=1e-13).phi
+    G0 = _grads(phi0, mask, h)
+
+    def correction(a_t, f_t):
+        solver.update_coefficient(a_t)
+        r = f_t - solver.apply(phi0, p.phi_bot, p.phi_top)
+        res = solver.solve(r, 0.0, 0.0, tol=1e-12)
+        assert res.converged
+        return _grads(res.phi, mask, h)
+
+    def delta_L(ap, fp, am, fm):
+        Ep, Em = correction(ap, fp), correction(am, fm)
+        tot = 0.0
+        for g0, ep, em in zip(G0, Ep, Em):
+            tot += (2 * g0 * (ep - em) + ep * ep - em * em).sum().item()
+        return tot * h ** 3
+
+    rng = np.random.default_rng(40)
+    lo, hi = int(0.35 * n), int(0.65 * n)
+    cells = [tuple(int(v) for v in rng.integers(lo, hi, 3)) for _ in range(20)]
+    gmax = np.abs(ga).max()
+    print(f"L = {L.item():.6e}, max|dL/da| = {gmax:.3e}", flush=True)
+    worst = 0.0
+    for (k, j, i) in cells:
+        d = 1e-6 * max(abs(p.a[k, j, i]), 1e-6 * np.abs(p.a).max())
+        ap, am = a0.clone(), a0.clone()
+        ap[k, j, i] += d
+        am[k, j, i] -= d
+        fd = delta_L(ap, f0, am, f0) / (2 * d)
+        g = ga[k, j, i]
+        print(f"  a-cell {(k, j, i)}: a={p.a[k, j, i]:.3e} adjoint {g:.6e} fd {fd:.6e}", flush=True)
+        if abs(g) > 1e-3 * gmax:
+            worst = max(worst, abs(fd - g) / abs(g))
+            assert abs(fd - g) <= 1e-4 * abs(g), ((k, j, i), fd, g)
+        else:
+            assert abs(fd - g) <= 1e-7 * gmax, ((k, j, i), fd, g)
+    fmax = np.abs(gf).max()
+    for (k, j, i) in cells[:5]:
+        d = 1e-6 * max(abs(p.f[k, j, i]), 1e-6 * np.abs(p.f).max())
+        fp, fm = f0.clone(), f0.clone()
+        fp[k, j, i] += d
+        fm[k, j, i] -= d
+        fd = delta_L(a0, fp, a0, fm) / (2 * d)
+        g = gf[k, j, i]
+        print(f"  f-cell {(k, j, i)}: adjoint {g:.6e} fd {fd:.6e}", flush=True)
+        if abs(g) > 1e-3 * fmax:
+            worst = max(worst, abs(fd - g) / abs(g))
+        assert abs(fd - g) <= 1e-4 * abs(g) + 1e-7 * fmax, ((k, j, i), fd, g)
+    print(f"worst relative FD mismatch {worst:.2e}", flush=True)
