@@ -417,9 +417,14 @@ FaceCoef<T> face_coef(gmg_ctx* c, int l) {
   return FaceCoef<T>{wsp<T>(c, o.wx), wsp<T>(c, o.wy), wsp<T>(c, o.wz), wsp<T>(c, o.tp)};
 }
 
-template <typename T>
-const char* tname(const char* f32, const char* f64) {
-  return sizeof(T) == 4 ? f32 : f64;
+// Profile name of a kernel: base + finest/coarse level + precision (the
+// returned string lives as long as the process).
+const char* kname(const char* base, int level, size_t tsize) {
+  static std::map<std::string, std::string> names;
+  std::string key = std::string(base) + (level == 0 ? "_fine" : "_coarse") + (tsize == 4 ? "_f32" : "_f64");
+  auto it = names.find(key);
+  if (it == names.end()) it = names.emplace(key, key).first;
+  return it->second.c_str();
 }
 
 // Smoothing and residual on one level, for any coefficient storage.
@@ -429,24 +434,24 @@ void smooth_pre(gmg_ctx* c, int l, T* x, const TB* b, const double* bscale, T* b
   const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
   const Geom g = s.geom();
   const int nu = c->opt.nu_pre;
-  GMG_LAUNCH(c, tname<T>("gs_first_f32", "gs_first_f64"), (k_gs_first<T, TB, Coef>), lc, x, b, bscale, b_out,
+  GMG_LAUNCH(c, kname("gs_first", l, sizeof(T)), (k_gs_first<T, TB, Coef>), lc, x, b, bscale, b_out,
              co, g, lc.kc, nu > 0 ? 1 : 0);
   if (nu == 0) return;
   // b_out holds the scaled right side from now on
   if (b_out) {
-    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
                (const double*)nullptr, co, g, lc.kc, 1);
     for (int it = 1; it < nu; ++it) {
-      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
+      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
                  (const double*)nullptr, co, g, lc.kc, 0);
-      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
+      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
                  (const double*)nullptr, co, g, lc.kc, 1);
     }
   } else {
-    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
     for (int it = 1; it < nu; ++it) {
-      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
-      GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
+      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
+      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
     }
   }
 }
@@ -457,8 +462,8 @@ void smooth_post(gmg_ctx* c, int l, T* x, const TB* b, const double* bscale, Coe
   const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
   const Geom g = s.geom();
   for (int it = 0; it < c->opt.nu_post; ++it) {
-    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
-    GMG_LAUNCH(c, tname<T>("gs_f32", "gs_f64"), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
   }
 }
 
@@ -467,7 +472,7 @@ void resid_restrict(gmg_ctx* c, int l, const T* x, const TB* b, const double* bs
   const LevelShape& s = c->L.shapes[l];
   const LevelShape& cs = c->L.shapes[l + 1];
   const Launch lc = col_launch(cs.nx, cs.ny, cs.nz, 1 << 16);
-  GMG_LAUNCH(c, tname<T>("resid_restrict_f32", "resid_restrict_f64"), (k_resid_restrict<T, TB, Coef>), lc, x, b,
+  GMG_LAUNCH(c, kname("resid_restrict", l, sizeof(T)), (k_resid_restrict<T, TB, Coef>), lc, x, b,
              bscale, co, s.geom(), bc, lc.kc);
 }
 
@@ -475,14 +480,14 @@ template <typename T>
 void prolong_add(gmg_ctx* c, int l, T* x, const T* xc) {
   const LevelShape& s = c->L.shapes[l];
   const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
-  GMG_LAUNCH(c, tname<T>("prolong_add_f32", "prolong_add_f64"), k_prolong_add<T>, lc, x, xc, s.geom(), lc.kc);
+  GMG_LAUNCH(c, kname("prolong_add", l, sizeof(T)), k_prolong_add<T>, lc, x, xc, s.geom(), lc.kc);
 }
 
 template <typename T>
 void coarse_solve(gmg_ctx* c, const T* b, T* x) {
   const int n = c->nc;
   const Launch lc{dim3((n + NTHREADS - 1) / NTHREADS), dim3(BX, BY, 1), 0};
-  GMG_LAUNCH(c, tname<T>("coarse_solve_f32", "coarse_solve_f64"), k_coarse_solve<T>, lc,
+  GMG_LAUNCH(c, kname("coarse_solve", 1, sizeof(T)), k_coarse_solve<T>, lc,
              wsp<const T>(c, c->L.cinv), b, x, n);
 }
 
@@ -516,10 +521,10 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     // scaled copy of the right side, then the direct solve
     const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
     if (c->mixed) {
-      GMG_LAUNCH(c, "gs_first_f32", (k_gs_first<float, double, CellCoef<float>>), lc, (float*)z, u, bscale,
+      GMG_LAUNCH(c, kname("gs_first", 0, 4), (k_gs_first<float, double, CellCoef<float>>), lc, (float*)z, u, bscale,
                  (float*)b0, CellCoef<float>{wsp<float>(c, c->L.a32)}, s.geom(), lc.kc, 0);
     } else {
-      GMG_LAUNCH(c, "gs_first_f64", (k_gs_first<double, double, CellCoef<double>>), lc, (double*)z, u, bscale,
+      GMG_LAUNCH(c, kname("gs_first", 0, 8), (k_gs_first<double, double, CellCoef<double>>), lc, (double*)z, u, bscale,
                  (double*)b0, CellCoef<double>{c->a}, s.geom(), lc.kc, 0);
     }
     coarse_solve<T>(c, b0, z);

@@ -187,9 +187,13 @@ class GMGPoisson:
         return z
 
     def face_flux_grad(self, phi: torch.Tensor, lam: torch.Tensor, phi_bot: float, phi_top: float):
+        """dL/da from the solution phi and the adjoint lam."""
+        return self.face_flux_grad_into(phi, lam, phi_bot, phi_top, torch.empty_like(phi))
+
+    def face_flux_grad_into(self, phi, lam, phi_bot: float, phi_top: float, out: torch.Tensor):
         _check_field(phi, self.shape, "phi", self.device)
         _check_field(lam, self.shape, "lam", self.device)
-        out = torch.empty_like(phi)
+        _check_field(out, self.shape, "out", self.device)
         with torch.cuda.device(self.device):
             self._sync_stream()
             st = self._lib.gmg_face_flux_grad(self._ctx, _ptr(phi), _ptr(lam), float(phi_bot),
