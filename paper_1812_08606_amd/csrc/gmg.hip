@@ -11,6 +11,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "gmg.h"
@@ -55,7 +56,7 @@ struct LevelOffsets {
 struct Layout {
   std::vector<LevelShape> shapes;
   std::vector<LevelOffsets> lv;
-  size_t V, Z, a32, b0, partials, scal, cinv, total;
+  size_t V, Z, a32, b0, xs, partials, scal, cinv, total;
   size_t tsize;  // bytes of the V-cycle precision
   int m;
 };
@@ -67,6 +68,7 @@ bool options_valid(const gmg_options* o) {
   if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8) return false;
   if (o->precision != GMG_FP64 && o->precision != GMG_MIXED) return false;
   if (o->coarse_max_cells < 1 || o->coarse_max_cells > 4096) return false;
+  if (o->fine_sweep < 0 || o->fine_sweep > 2) return false;
   for (int r : o->reserved)
     if (r) return false;
   return true;
@@ -96,6 +98,8 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   // finest-level right side in T: the float32 copy of v_j (mixed) or, when
   // the finest level is also the coarsest, the scaled right side
   L->b0 = (mixed || nl == 1) ? take(N * L->tsize) : 0;
+  // second finest-level iterate for the ping-pong fused sweeps
+  L->xs = nl > 1 ? take(N * L->tsize) : 0;
   L->lv.assign(nl, LevelOffsets{});
   for (int l = 1; l < nl; ++l) {
     const LevelShape& s = L->shapes[l];
@@ -467,6 +471,20 @@ void smooth_post(gmg_ctx* c, int l, T* x, const TB* b, const double* bscale, Coe
   }
 }
 
+// Finest level: the z-marching residual/restriction kernel.
+template <typename T, typename TB>
+void resid_restrict_fine(gmg_ctx* c, const T* x, const TB* b, const double* bscale, const T* a, T* bc) {
+  const LevelShape& s = c->L.shapes[0];
+  const int NX = s.nx / 2, NZ = s.nz / 2;
+  const int gx = (NX + BX - 1) / BX, gy = (s.ny + BY - 1) / BY;
+  const long long cols = (long long)gx * gy;
+  int kc = (int)std::max<long long>(4, (NZ * cols + 8191) / 8192);
+  kc = std::min(kc, NZ);
+  const Launch l{dim3(gx, std::min(gy, 65535), (NZ + kc - 1) / kc), dim3(BX, BY, 1), kc};
+  GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), (k_resid_restrict_cell<T, TB>), l, x, b, bscale, a, s.geom(),
+             bc, kc);
+}
+
 template <typename T, typename TB, typename Coef>
 void resid_restrict(gmg_ctx* c, int l, const T* x, const TB* b, const double* bscale, Coef co, T* bc) {
   const LevelShape& s = c->L.shapes[l];
@@ -510,6 +528,120 @@ void vcycle_coarse(gmg_ctx* c, int l) {
   smooth_post<T, T>(c, l, x, b, nullptr, co);
 }
 
+// Finest-level smoother kernels: option fine_sweep, 0 selects the faster
+// (one kernel per half-sweep, as measured on MI355X).
+int fine_sweep_kind(const gmg_ctx* c) { return c->opt.fine_sweep == 0 ? 2 : c->opt.fine_sweep; }
+
+// Tile height of the fused sweep (LDS: 12 planes of 68 x (TY + 4) values).
+template <typename T>
+struct SweepTY {
+  static constexpr int value = sizeof(T) == 4 ? 8 : 4;
+};
+
+template <typename T, typename TB, int XM>
+void sym_sweep(gmg_ctx* c, const T* x_in, const T* xc, const TB* b, const double* bscale, T* b_out, const T* a,
+               T* x_out, int c1) {
+  constexpr int TY = SweepTY<T>::value;
+  const LevelShape& s = c->L.shapes[0];
+  const int gx = (s.nx + 63) / 64, gy = (s.ny + TY - 1) / TY;
+  const long long tiles = (long long)gx * gy;
+  int kc = (int)std::max<long long>(8, (s.nz * tiles + 4095) / 4096);
+  kc = std::min(kc, s.nz);
+  const int gz = (s.nz + kc - 1) / kc;
+  const Launch l{dim3(gx, std::min(gy, 65535), gz), dim3(BX, BY, 1), kc};
+  SweepArgs<T, TB> A{x_in, xc, b, bscale, b_out, a, x_out, s.geom(), c1, kc};
+  const char* nm = XM == SWEEP_X_ZERO ? "sym_sweep_zero" : (XM == SWEEP_X_LOAD ? "sym_sweep" : "sym_sweep_prolong");
+  if (bscale)
+    GMG_LAUNCH(c, kname(nm, 0, sizeof(T)), (k_sym_sweep<T, TB, XM, TY, true>), l, A);
+  else
+    GMG_LAUNCH(c, kname(nm, 0, sizeof(T)), (k_sym_sweep<T, TB, XM, TY, false>), l, A);
+}
+
+// Finest level with the fused sweeps (nu_pre, nu_post >= 1, at least two
+// levels): pre-sweeps ping-pong between the scratch iterate and z so that
+// the last post-sweep lands in z.
+template <typename T>
+void vcycle_fine_fused(gmg_ctx* c, const double* u, const double* bscale, T* z) {
+  const int npre = c->opt.nu_pre, npost = c->opt.nu_post, L = npre + npost;
+  T* xs = wsp<T>(c, c->L.xs);
+  auto buf = [&](int p) { return ((L - p) % 2 == 0) ? z : xs; };  // buffer written by pass p (1-based)
+  const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
+  T* b0 = c->mixed ? wsp<T>(c, c->L.b0) : nullptr;
+  T* bc = wsp<T>(c, c->L.lv[1].b);
+  // pre-smoothing: red then black, from x = 0
+  sym_sweep<T, double, SWEEP_X_ZERO>(c, nullptr, nullptr, u, bscale, b0, a, buf(1), 0);
+  for (int p = 2; p <= npre; ++p) {
+    if (c->mixed)
+      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, (const T*)b0, nullptr, nullptr, a, buf(p), 0);
+    else
+      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, u, bscale, nullptr, a, buf(p), 0);
+  }
+  if (c->mixed)
+    resid_restrict_fine<T, T>(c, buf(npre), (const T*)b0, nullptr, a, bc);
+  else
+    resid_restrict_fine<T, double>(c, buf(npre), u, bscale, a, bc);
+  vcycle_coarse<T>(c, 1);
+  // coarse correction, then post-smoothing: black then red
+  prolong_add<T>(c, 0, buf(npre), wsp<T>(c, c->L.lv[1].x));
+  for (int p = npre + 1; p <= L; ++p) {
+    if (c->mixed)
+      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, (const T*)b0, nullptr, nullptr, a, buf(p), 1);
+    else
+      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, u, bscale, nullptr, a, buf(p), 1);
+  }
+}
+
+template <typename T, typename TB>
+void gs_pair(gmg_ctx* c, T* x, const TB* b, const double* bscale, const T* a, int colour) {
+  const LevelShape& s = c->L.shapes[0];
+  const int gx = (s.nx / 2 + BX - 1) / BX, gy = (s.ny + BY - 1) / BY;
+  const long long cols = (long long)gx * gy;
+  int kc = (int)std::max<long long>(8, (s.nz * cols + 8191) / 8192);
+  kc = std::min(kc, s.nz);
+  const Launch l{dim3(gx, std::min(gy, 65535), (s.nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
+  if (bscale)
+    GMG_LAUNCH(c, kname("gs", 0, sizeof(T)), (k_gs_pair<T, TB, true>), l, x, b, bscale, a, s.geom(), kc, colour);
+  else
+    GMG_LAUNCH(c, kname("gs", 0, sizeof(T)), (k_gs_pair<T, TB, false>), l, x, b, bscale, a, s.geom(), kc, colour);
+}
+
+// Finest level with one kernel per half-sweep (at least two levels, so the
+// dimensions are even): pre-smoothing red, black (nu_pre times) from x = 0,
+// the first red half-sweep writing the float32 copy of v_j; residual and
+// restriction; coarse correction; post-smoothing black, red (nu_post times).
+template <typename T>
+void vcycle_fine_half(gmg_ctx* c, const double* u, const double* bscale, T* z) {
+  const LevelShape& s = c->L.shapes[0];
+  const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
+  T* b0 = c->mixed ? wsp<T>(c, c->L.b0) : nullptr;
+  T* bc = wsp<T>(c, c->L.lv[1].b);
+  const CellCoef<T> co{a};
+  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
+  const int npre = c->opt.nu_pre, npost = c->opt.nu_post;
+  GMG_LAUNCH(c, kname("gs_first", 0, sizeof(T)), (k_gs_first<T, double, CellCoef<T>>), lc, z, u, bscale, b0, co,
+             s.geom(), lc.kc, npre > 0 ? 1 : 0);
+  auto half = [&](int colour) {
+    if (c->mixed)
+      gs_pair<T, T>(c, z, (const T*)b0, nullptr, a, colour);
+    else
+      gs_pair<T, double>(c, z, u, bscale, a, colour);
+  };
+  for (int it = 0; it < npre; ++it) {
+    if (it > 0) half(0);
+    half(1);
+  }
+  if (c->mixed)
+    resid_restrict_fine<T, T>(c, z, (const T*)b0, nullptr, a, bc);
+  else
+    resid_restrict_fine<T, double>(c, z, u, bscale, a, bc);
+  vcycle_coarse<T>(c, 1);
+  prolong_add<T>(c, 0, z, wsp<T>(c, c->L.lv[1].x));
+  for (int it = 0; it < npost; ++it) {
+    half(1);
+    half(0);
+  }
+}
+
 // z = M (s * u): one V-cycle on the finest level with right side u scaled by
 // *bscale (null = 1); z in the V-cycle precision.
 template <typename T>
@@ -530,22 +662,10 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     coarse_solve<T>(c, b0, z);
     return;
   }
-  const CellCoef<T> co{c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a};
-  T* bc = wsp<T>(c, c->L.lv[1].b);
-  if (c->mixed) {
-    T* b0 = wsp<T>(c, c->L.b0);
-    smooth_pre<T, double>(c, 0, z, u, bscale, b0, co);
-    resid_restrict<T, T>(c, 0, z, (const T*)b0, nullptr, co, bc);
-    vcycle_coarse<T>(c, 1);
-    prolong_add<T>(c, 0, z, wsp<T>(c, c->L.lv[1].x));
-    smooth_post<T, T>(c, 0, z, (const T*)b0, nullptr, co);
-  } else {
-    smooth_pre<T, double>(c, 0, z, u, bscale, (T*)nullptr, co);
-    resid_restrict<T, double>(c, 0, z, u, bscale, co, bc);
-    vcycle_coarse<T>(c, 1);
-    prolong_add<T>(c, 0, z, wsp<T>(c, c->L.lv[1].x));
-    smooth_post<T, double>(c, 0, z, u, bscale, co);
-  }
+  if (fine_sweep_kind(c) == 1 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1)
+    vcycle_fine_fused<T>(c, u, bscale, z);
+  else
+    vcycle_fine_half<T>(c, u, bscale, z);
 }
 
 void vcycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z) {
@@ -581,6 +701,59 @@ void init_residual(gmg_ctx* c, const double* f, const double* x, double pb, doub
              2, misc + 2, nullptr, scal_vscale(c));
 }
 
+// Launches of the vector-count templates (NV = 1..MAXV) through tables.
+Launch red_flat(gmg_ctx* c) {
+  const size_t b = std::min<size_t>((c->N + NTHREADS - 1) / NTHREADS, MAX_RED_BLOCKS);
+  return Launch{dim3((unsigned)std::max<size_t>(b, 1)), dim3(BX, BY, 1), 0};
+}
+
+template <typename TZ, int NV>
+void launch_opdot(gmg_ctx* c, const Launch& rl, const TZ* z, double* w, const double* V) {
+  GMG_LAUNCH(c, sizeof(TZ) == 4 ? "op_multidot_zf32" : "op_multidot_zf64", (k_op_multidot<TZ, NV>), rl, z, c->a,
+             c->L.shapes[0].geom(), w, V, c->N, wsp<double>(c, c->L.partials), rl.kc);
+}
+template <int NV>
+void launch_dot(gmg_ctx* c, const Launch& rl, const double* w, const double* V) {
+  GMG_LAUNCH(c, "multidot", k_multidot<NV>, rl, w, c->N, V, c->N, wsp<double>(c, c->L.partials));
+}
+template <int NV>
+void launch_axpy(gmg_ctx* c, const Launch& rl, double* w, const double* V, const double* hc, const double* vs,
+                 int last) {
+  GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<NV>, rl, w, c->N, V, c->N, hc, vs, last, wsp<double>(c, c->L.partials));
+}
+template <typename TZ, int NV>
+void launch_update(gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y) {
+  GMG_LAUNCH(c, sizeof(TZ) == 4 ? "update_zf32" : "update_zf64", (k_update<TZ, NV>), rl, phi, c->N, Z, c->N, y);
+}
+
+template <typename TZ, size_t... I>
+void opdot_nv(int nv, gmg_ctx* c, const Launch& rl, const TZ* z, double* w, const double* V,
+              std::index_sequence<I...>) {
+  using F = void (*)(gmg_ctx*, const Launch&, const TZ*, double*, const double*);
+  static constexpr F table[] = {&launch_opdot<TZ, (int)I + 1>...};
+  table[nv - 1](c, rl, z, w, V);
+}
+template <size_t... I>
+void dot_nv(int nv, gmg_ctx* c, const Launch& rl, const double* w, const double* V, std::index_sequence<I...>) {
+  using F = void (*)(gmg_ctx*, const Launch&, const double*, const double*);
+  static constexpr F table[] = {&launch_dot<(int)I + 1>...};
+  table[nv - 1](c, rl, w, V);
+}
+template <size_t... I>
+void axpy_nv(int nv, gmg_ctx* c, const Launch& rl, double* w, const double* V, const double* hc, const double* vs,
+             int last, std::index_sequence<I...>) {
+  using F = void (*)(gmg_ctx*, const Launch&, double*, const double*, const double*, const double*, int);
+  static constexpr F table[] = {&launch_axpy<(int)I + 1>...};
+  table[nv - 1](c, rl, w, V, hc, vs, last);
+}
+template <typename TZ, size_t... I>
+void update_nv(int nv, gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y,
+               std::index_sequence<I...>) {
+  using F = void (*)(gmg_ctx*, const Launch&, double*, const TZ*, const Coeffs16&);
+  static constexpr F table[] = {&launch_update<TZ, (int)I + 1>...};
+  table[nv - 1](c, rl, phi, Z, y);
+}
+
 // One Arnoldi step j: z_j = M v_j, w = A z_j, classical Gram-Schmidt against
 // v_0..v_j (dots fused into the operator pass), ||w||; results in hcol(j).
 void arnoldi_step(gmg_ctx* c, int j) {
@@ -591,46 +764,44 @@ void arnoldi_step(gmg_ctx* c, int j) {
   double* hc = scal_hcol(c, j);
   vcycle_any(c, V + (size_t)j * N, vs + j, Zb);
   const Launch rl = red_launch(c);
-  const Geom g = c->L.shapes[0].geom();
+  const Launch fl = red_flat(c);
   double* w = V + (size_t)(j + 1) * N;
   const int nv = j + 1;
+  const auto seq = std::make_index_sequence<MAXV>{};
   for (int q0 = 0; q0 < nv; q0 += MAXV) {
     const int nq = std::min(MAXV, nv - q0);
     if (q0 == 0) {
       if (c->mixed)
-        GMG_LAUNCH(c, "op_multidot_zf32", k_op_multidot<float>, rl, (const float*)Zb, c->a, g, w, V, N, nq,
-                   wsp<double>(c, c->L.partials), rl.kc);
+        opdot_nv<float>(nq, c, rl, (const float*)Zb, w, V, seq);
       else
-        GMG_LAUNCH(c, "op_multidot_zf64", k_op_multidot<double>, rl, (const double*)Zb, c->a, g, w, V, N, nq,
-                   wsp<double>(c, c->L.partials), rl.kc);
+        opdot_nv<double>(nq, c, rl, (const double*)Zb, w, V, seq);
+      finalize(c, rl.nblocks(), nq, 1, hc + q0, vs + q0, nullptr);
     } else {
-      GMG_LAUNCH(c, "multidot", k_multidot, rl, (const double*)w, g, V + (size_t)q0 * N, N, nq,
-                 wsp<double>(c, c->L.partials), rl.kc);
+      dot_nv(nq, c, fl, w, V + (size_t)q0 * N, seq);
+      finalize(c, fl.nblocks(), nq, 1, hc + q0, vs + q0, nullptr);
     }
-    finalize(c, rl.nblocks(), nq, 1, hc + q0, vs + q0, nullptr);
   }
   for (int q0 = 0; q0 < nv; q0 += MAXV) {
     const int nq = std::min(MAXV, nv - q0);
     const int last = q0 + nq >= nv;
-    GMG_LAUNCH(c, "axpy_norm", k_axpy_norm, rl, w, g, (const double*)(V + (size_t)q0 * N), N, nq,
-               (const double*)(hc + q0), (const double*)(vs + q0), last, wsp<double>(c, c->L.partials), rl.kc);
+    axpy_nv(nq, c, fl, w, V + (size_t)q0 * N, hc + q0, vs + q0, last, seq);
   }
-  finalize(c, rl.nblocks(), 1, 2, hc + (j + 1), nullptr, vs + (j + 1));
+  finalize(c, fl.nblocks(), 1, 2, hc + (j + 1), nullptr, vs + (j + 1));
 }
 
 // phi += sum_{i<k} y_i z_i
 void update_solution(gmg_ctx* c, double* phi, int k) {
-  const Launch lc = col_launch(c->nx, c->ny, c->nz, 1 << 16);
-  const Geom g = c->L.shapes[0].geom();
+  const Launch fl = flat_launch(c->N);
+  const auto seq = std::make_index_sequence<MAXV>{};
   for (int q0 = 0; q0 < k; q0 += MAXV) {
     const int nq = std::min(MAXV, k - q0);
     Coeffs16 y{};
     for (int q = 0; q < nq; ++q) y.v[q] = c->y[q0 + q];
     char* Zb = c->ws + c->L.Z + (size_t)q0 * c->N * c->L.tsize;
     if (c->mixed)
-      GMG_LAUNCH(c, "update_zf32", k_update<float>, lc, phi, g, (const float*)Zb, c->N, nq, y, lc.kc);
+      update_nv<float>(nq, c, fl, phi, (const float*)Zb, y, seq);
     else
-      GMG_LAUNCH(c, "update_zf64", k_update<double>, lc, phi, g, (const double*)Zb, c->N, nq, y, lc.kc);
+      update_nv<double>(nq, c, fl, phi, (const double*)Zb, y, seq);
   }
 }
 

@@ -17,19 +17,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gmg_common.hpp"
+#include "gmg_sweep.hpp"
+
 namespace gmg {
-
-constexpr int BX = 64;
-constexpr int BY = 4;
-constexpr int NTHREADS = BX * BY;
-constexpr int NWAVES = NTHREADS / 64;
-constexpr int MAXV = 16;             // vectors per multi-dot / multi-axpy launch
-constexpr int MAX_RED_BLOCKS = 4096; // blocks of a reduction launch
-
-struct Geom {
-  int nx, ny, nz;
-  double ihx2, ihy2, ihz2;  // 1 / h^2 per direction
-};
 
 struct Coeffs16 {
   double v[MAXV];
@@ -237,6 +228,218 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict(const T* __restrict
   }
 }
 
+// Red-black half-sweep of one colour on the finest level (cell
+// coefficient; even nx).  Lane tx owns the x-pair (2m, 2m+1), m = 64 bx + tx,
+// of row j = 4 by + ty and marches its z-chunk keeping x and a of the pair on
+// planes k-1, k, k+1 in registers.  On every plane exactly one cell of the
+// pair has the colour being updated, the same one across a row, so a wave
+// takes one branch; the x-neighbour outside the pair comes from the adjacent
+// lane (a load at the wave's edges).  Only cells of the other colour are
+// read, and none of them is written, so the update is order-free.
+template <typename T, typename TB, bool SCALED>
+__global__ __launch_bounds__(NTHREADS) void k_gs_pair(T* __restrict__ x, const TB* __restrict__ b,
+                                                      const double* __restrict__ bscale, const T* __restrict__ a,
+                                                      Geom g, int kc, int colour) {
+  const int m = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int i0 = 2 * m;
+  const bool act = i0 < g.nx && j < g.ny;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
+  const double s = SCALED ? *bscale : 1.0;
+  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
+  const bool hs = j > 0, hn = j < g.ny - 1;
+  const bool hwo = i0 > 0, heo = i0 + 2 < g.nx;  // faces outside the pair
+  const int lane = threadIdx.x;
+  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
+  T xc0 = T(0), xc1 = T(0), ac0 = T(0), ac1 = T(0), xb0 = T(0), xb1 = T(0), ab0 = T(0), ab1 = T(0);
+  if (act) {
+    xc0 = x[c];
+    xc1 = x[c + 1];
+    ac0 = a[c];
+    ac1 = a[c + 1];
+    if (k0 > 0) {
+      xb0 = x[c - sz];
+      xb1 = x[c - sz + 1];
+      ab0 = a[c - sz];
+      ab1 = a[c - sz + 1];
+    }
+  }
+  for (int k = k0; k < k1; ++k) {
+    const bool top = k == g.nz - 1;
+    T xt0 = T(0), xt1 = T(0), at0 = T(0), at1 = T(0);
+    if (act && !top) {
+      xt0 = x[c + sz];
+      xt1 = x[c + sz + 1];
+      at0 = a[c + sz];
+      at1 = a[c + sz + 1];
+    }
+    // outer x-neighbours of the pair on plane k: lane tx-1's right cell and
+    // lane tx+1's left cell (loads at the wave's edges)
+    T xwo = __shfl_up(xc1, 1, 64), awo = __shfl_up(ac1, 1, 64);
+    T xeo = __shfl_down(xc0, 1, 64), aeo = __shfl_down(ac0, 1, 64);
+    if (act && lane == 0 && hwo) {
+      xwo = x[c - 1];
+      awo = a[c - 1];
+    }
+    if (act && lane == BX - 1 && heo) {
+      xeo = x[c + 2];
+      aeo = a[c + 2];
+    }
+    if (act) {
+      const int e = (colour + i0 + j + k) & 1;  // element of the pair being updated
+      const size_t ce = c + e;
+      const T acv = e ? ac1 : ac0;
+      // x-faces: the pair's inner face and the outer face on the cell's side
+      const T xin = e ? xc0 : xc1, ain = e ? ac0 : ac1;
+      const T xout = e ? xeo : xwo, aout = e ? aeo : awo;
+      const bool hout = e ? heo : hwo;
+      const T wi = (acv + ain) * hx;
+      const T wo = hout ? (acv + aout) * hx : T(0);
+      T D = wi + wo, off = wi * xin + (hout ? wo * xout : T(0));
+      if (hs) {
+        const T w = (acv + a[ce - sy]) * hy;
+        D += w;
+        off += w * x[ce - sy];
+      }
+      if (hn) {
+        const T w = (acv + a[ce + sy]) * hy;
+        D += w;
+        off += w * x[ce + sy];
+      }
+      const T xbv = e ? xb1 : xb0, abv = e ? ab1 : ab0;
+      const T xtv = e ? xt1 : xt0, atv = e ? at1 : at0;
+      if (k > 0) {
+        const T w = (acv + abv) * hz;
+        D += w;
+        off += w * xbv;
+      } else {
+        D += pz * acv;
+      }
+      if (!top) {
+        const T w = (acv + atv) * hz;
+        D += w;
+        off += w * xtv;
+      } else {
+        D += pz * acv;
+      }
+      const T bv = SCALED ? (T)((double)b[ce] * s) : (T)b[ce];
+      x[ce] = (bv + off) * sweep_recip(D);
+    }
+    xb0 = xc0;
+    xb1 = xc1;
+    xc0 = xt0;
+    xc1 = xt1;
+    ab0 = ac0;
+    ab1 = ac1;
+    ac0 = at0;
+    ac1 = at1;
+    c += act ? sz : 0;
+  }
+}
+
+// Finest-level residual and restriction, b_coarse = mean over the 8
+// children of (b - A x), cell coefficient.  Block 64 x 4: lane tx owns the
+// fine x-pair (2I, 2I+1), I = 64 bx + tx, of fine row j = 4 by + ty; each
+// thread marches the fine planes of its z-chunk (2 fine planes per coarse
+// plane) keeping x and a of its pair on planes k-1, k, k+1 in registers; the
+// two fine rows of a coarse row are summed through LDS.  Needs even nx, ny,
+// nz; kc counts coarse planes.
+template <typename T, typename TB>
+__global__ __launch_bounds__(NTHREADS) void k_resid_restrict_cell(const T* __restrict__ x, const TB* __restrict__ b,
+                                                                  const double* __restrict__ bscale,
+                                                                  const T* __restrict__ a, Geom g,
+                                                                  T* __restrict__ bc, int kc) {
+  __shared__ T part[BY][BX];
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const bool act = I < NX && j < g.ny;
+  const int i0 = 2 * I;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
+  const T s = (T)(bscale ? *bscale : 1.0);
+  const int K0 = blockIdx.z * kc, K1 = min(NZ, K0 + kc);
+  const int k0 = 2 * K0, k1 = 2 * K1;
+  // column registers: [0] cell i0, [1] cell i0+1, planes below / centre / above
+  T xb[2] = {T(0), T(0)}, xc[2] = {T(0), T(0)}, xt[2], ab[2] = {T(0), T(0)}, ac[2] = {T(0), T(0)}, at[2];
+  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
+  if (act) {
+    xc[0] = x[c];
+    xc[1] = x[c + 1];
+    ac[0] = a[c];
+    ac[1] = a[c + 1];
+    if (k0 > 0) {
+      xb[0] = x[c - sz];
+      xb[1] = x[c - sz + 1];
+      ab[0] = a[c - sz];
+      ab[1] = a[c - sz + 1];
+    }
+  }
+  T acc = T(0);
+  for (int k = k0; k < k1; ++k) {
+    T rsum = T(0);
+    if (act) {
+      const bool top = k == g.nz - 1;
+      xt[0] = top ? T(0) : x[c + sz];
+      xt[1] = top ? T(0) : x[c + sz + 1];
+      at[0] = top ? T(0) : a[c + sz];
+      at[1] = top ? T(0) : a[c + sz + 1];
+      // in-plane neighbours: west of i0, east of i0+1, rows j-1 and j+1
+      const bool hw = i0 > 0, he = i0 + 2 < g.nx, hs = j > 0, hn = j < g.ny - 1;
+      const T xw = hw ? x[c - 1] : T(0), aw = hw ? a[c - 1] : T(0);
+      const T xe = he ? x[c + 2] : T(0), ae = he ? a[c + 2] : T(0);
+      T xs[2] = {T(0), T(0)}, as_[2] = {T(0), T(0)}, xn[2] = {T(0), T(0)}, an[2] = {T(0), T(0)};
+      if (hs) {
+        xs[0] = x[c - sy];
+        xs[1] = x[c - sy + 1];
+        as_[0] = a[c - sy];
+        as_[1] = a[c - sy + 1];
+      }
+      if (hn) {
+        xn[0] = x[c + sy];
+        xn[1] = x[c + sy + 1];
+        an[0] = a[c + sy];
+        an[1] = a[c + sy + 1];
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const T acv = ac[e], xcv = xc[e];
+        // x-faces: the pair's inner face, and the outer face on its own side
+        const T xo = e == 0 ? xw : xe, ao = e == 0 ? aw : ae;
+        const bool ho = e == 0 ? hw : he;
+        const T xi = xc[1 - e], ai = ac[1 - e];
+        T Ax = (acv + ai) * hx * (xcv - xi);
+        Ax += ho ? (acv + ao) * hx * (xcv - xo) : T(0);
+        Ax += hs ? (acv + as_[e]) * hy * (xcv - xs[e]) : T(0);
+        Ax += hn ? (acv + an[e]) * hy * (xcv - xn[e]) : T(0);
+        Ax += k > 0 ? (acv + ab[e]) * hz * (xcv - xb[e]) : pz * acv * xcv;
+        Ax += !top ? (acv + at[e]) * hz * (xcv - xt[e]) : pz * acv * xcv;
+        rsum += (T)b[c + e] * s - Ax;
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        xb[e] = xc[e];
+        xc[e] = xt[e];
+        ab[e] = ac[e];
+        ac[e] = at[e];
+      }
+      c += sz;
+    }
+    acc += rsum;
+    if (k & 1) {  // both fine planes of coarse plane k/2 done: add the row pair
+      part[threadIdx.y][threadIdx.x] = acc;
+      __syncthreads();
+      if (!(threadIdx.y & 1) && act) {
+        const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
+        bc[((size_t)(k >> 1) * NY + (j >> 1)) * NX + I] = tot * T(0.125);
+      }
+      __syncthreads();
+      acc = T(0);
+    }
+  }
+}
+
 // x_fine += P x_coarse, cell-centred trilinear: per dimension 3/4 of the
 // parent and 1/4 of the nearer coarse neighbour; outside the grid the
 // neighbour is the parent (x, y: Neumann) or minus the parent (z: plates).
@@ -272,6 +475,42 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_add(T* __restrict__ x, con
       const size_t c = cidx(g, i, j, k);
       x[c] += q3 * pl + q1 * sk * ql;
     }
+  }
+}
+
+// One symmetric red-black sweep on the finest level in one pass (the phase
+// functions and the blocking are described in gmg_sweep.hpp).  Block 64 x 4
+// threads; grid (ceil(nx/64), ceil(ny/TY), ceil(nz/kc)).  The plane needed at
+// step t+1 is fetched into registers during step t.  SCALED: b is read as
+// b * (*bscale).
+template <typename T, typename TB, int XM, int TY, bool SCALED>
+__global__ __launch_bounds__(NTHREADS) void k_sym_sweep(SweepArgs<T, TB> A) {
+  constexpr int NPT = (SweepTile<TY>::P + NTHREADS - 1) / NTHREADS;
+  __shared__ SweepSmem<T, TY> s;
+  SweepPlan<NPT, XM> P;
+  SweepPhasePlan<TY> Q;
+  SweepFetch<T, XM, NPT> R;
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  const int k0 = blockIdx.z * A.kc, k1 = min(A.g.nz, k0 + A.kc);
+  const double bsc = SCALED ? *A.bscale : 1.0;
+  const bool store_b = A.b_out != nullptr;
+  sweep_plan<TY, NPT, XM>(P, A.g, blockIdx.x, blockIdx.y, tid, NTHREADS);
+  sweep_phase_plan<TY>(Q, A.g, A.c1, blockIdx.x, blockIdx.y, tid);
+  SweepStep nx = sweep_step(A.g, k0, k1, k0 - 3);
+  sweep_fetch<T, TB, XM, NPT, SCALED>(R, P, A, nx.pxa, nx.load_xa, nx.pb, nx.load_b, nx.store_b && store_b, bsc);
+  for (int t = k0 - 3; t <= k1; ++t) {
+    const SweepStep st = nx;
+    __syncthreads();
+    sweep_stash<T, XM, TY, NPT>(s, R, P, tid, NTHREADS, st.pxa, st.load_xa, st.pb, st.load_b);
+    __syncthreads();
+    if (t < k1) {
+      nx = sweep_step(A.g, k0, k1, t + 1);
+      sweep_fetch<T, TB, XM, NPT, SCALED>(R, P, A, nx.pxa, nx.load_xa, nx.pb, nx.load_b, nx.store_b && store_b,
+                                          bsc);
+    }
+    if (st.do_first) sweep_first<T, XM, TY>(s, Q, A.g, t);
+    __syncthreads();
+    if (st.do_second) sweep_second<T, TY>(s, Q, A.g, A.x_out, t - 1);
   }
 }
 
@@ -326,103 +565,103 @@ __global__ __launch_bounds__(NTHREADS) void k_init_residual(const double* __rest
   block_store_partials<2>(acc, 2, partials, gridDim.x * gridDim.y * gridDim.z);
 }
 
-// w = A z (z promoted to float64) and the dots (w, u_v), v < nv.
-template <typename TZ>
+// Flat grid-stride loop over n cells, block size NTHREADS.
+#define GMG_FLAT_LOOP(c, n)                                                                        \
+  for (size_t c = (size_t)blockIdx.x * NTHREADS + threadIdx.y * BX + threadIdx.x; c < (n);       \
+       c += (size_t)gridDim.x * NTHREADS)
+
+// w = A z (z promoted to float64) and the dots (w, u_v), v < NV.  Each
+// thread marches one (i, j) column through its z-chunk and keeps the values
+// of z and a on the planes below / above in registers.
+template <typename TZ, int NV>
 __global__ __launch_bounds__(NTHREADS) void k_op_multidot(const TZ* __restrict__ z, const double* __restrict__ a,
                                                           Geom g, double* __restrict__ w,
-                                                          const double* __restrict__ U, size_t stride, int nv,
+                                                          const double* __restrict__ U, size_t stride,
                                                           double* __restrict__ partials, int kc) {
-  double acc[MAXV];
+  double acc[NV];
 #pragma unroll
-  for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
   const int i = blockIdx.x * BX + threadIdx.x;
-  const CellCoef<double> co{a};
   if (i < g.nx) {
+    const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+    const double hx = 0.5 * g.ihx2, hy = 0.5 * g.ihy2, hz = 0.5 * g.ihz2, pz = 2.0 * g.ihz2;
     const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
     for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-      for (int k = k0; k < k1; ++k) {
-        const size_t c = cidx(g, i, j, k);
-        const Stencil<double> st = co.load(g, i, j, k, c);
-        const Nbrs<double> v = load_nbrs<double>(z, g, i, j, k, c, 0.0, 0.0);
-        const double az = apply_cell(st, v);
-        w[c] = az;
+      size_t c = cidx(g, i, j, k0);
+      double zc = (double)z[c], ac = a[c];
+      double zb = k0 > 0 ? (double)z[c - sz] : 0.0;
+      double ab = k0 > 0 ? a[c - sz] : 0.0;
+      for (int k = k0; k < k1; ++k, c += sz) {
+        const bool top = k == g.nz - 1;
+        const double zt = top ? 0.0 : (double)z[c + sz];
+        const double at = top ? 0.0 : a[c + sz];
+        double s = 0.0;
+        if (i > 0) s += (ac + a[c - 1]) * hx * (zc - (double)z[c - 1]);
+        if (i < g.nx - 1) s += (ac + a[c + 1]) * hx * (zc - (double)z[c + 1]);
+        if (j > 0) s += (ac + a[c - sy]) * hy * (zc - (double)z[c - sy]);
+        if (j < g.ny - 1) s += (ac + a[c + sy]) * hy * (zc - (double)z[c + sy]);
+        s += k > 0 ? (ac + ab) * hz * (zc - zb) : pz * ac * zc;
+        s += !top ? (ac + at) * hz * (zc - zt) : pz * ac * zc;
+        w[c] = s;
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q)
-          if (q < nv) acc[q] += az * U[(size_t)q * stride + c];
+        for (int q = 0; q < NV; ++q) acc[q] += s * U[(size_t)q * stride + c];
+        zb = zc;
+        zc = zt;
+        ab = ac;
+        ac = at;
       }
     }
   }
-  block_store_partials<MAXV>(acc, nv, partials, gridDim.x * gridDim.y * gridDim.z);
+  block_store_partials<NV>(acc, NV, partials, gridDim.x * gridDim.y * gridDim.z);
 }
 
-// Dots (w, u_v), v < nv.
-__global__ __launch_bounds__(NTHREADS) void k_multidot(const double* __restrict__ w, Geom g,
-                                                       const double* __restrict__ U, size_t stride, int nv,
-                                                       double* __restrict__ partials, int kc) {
-  double acc[MAXV];
+// Dots (w, u_v), v < NV (flat launch).
+template <int NV>
+__global__ __launch_bounds__(NTHREADS) void k_multidot(const double* __restrict__ w, size_t n,
+                                                       const double* __restrict__ U, size_t stride,
+                                                       double* __restrict__ partials) {
+  double acc[NV];
 #pragma unroll
-  for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
-  const int i = blockIdx.x * BX + threadIdx.x;
-  if (i < g.nx) {
-    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-      for (int k = k0; k < k1; ++k) {
-        const size_t c = cidx(g, i, j, k);
-        const double wv = w[c];
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  GMG_FLAT_LOOP(c, n) {
+    const double wv = w[c];
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q)
-          if (q < nv) acc[q] += wv * U[(size_t)q * stride + c];
-      }
-    }
+    for (int q = 0; q < NV; ++q) acc[q] += wv * U[(size_t)q * stride + c];
   }
-  block_store_partials<MAXV>(acc, nv, partials, gridDim.x * gridDim.y * gridDim.z);
+  block_store_partials<NV>(acc, NV, partials, gridDim.x);
 }
 
 // w -= sum_v (h_v * s_v) u_v (h_v = (w, v_v) with v_v = s_v u_v), and the
-// partial sums of ||w||^2 when want_norm.
-__global__ __launch_bounds__(NTHREADS) void k_axpy_norm(double* __restrict__ w, Geom g,
-                                                        const double* __restrict__ U, size_t stride, int nv,
+// partial sums of ||w||^2 when want_norm (flat launch).
+template <int NV>
+__global__ __launch_bounds__(NTHREADS) void k_axpy_norm(double* __restrict__ w, size_t n,
+                                                        const double* __restrict__ U, size_t stride,
                                                         const double* __restrict__ hcol,
                                                         const double* __restrict__ vscale, int want_norm,
-                                                        double* __restrict__ partials, int kc) {
-  double cf[MAXV];
+                                                        double* __restrict__ partials) {
+  double cf[NV];
 #pragma unroll
-  for (int q = 0; q < MAXV; ++q) cf[q] = q < nv ? hcol[q] * vscale[q] : 0.0;
+  for (int q = 0; q < NV; ++q) cf[q] = hcol[q] * vscale[q];
   double acc[1] = {0.0};
-  const int i = blockIdx.x * BX + threadIdx.x;
-  if (i < g.nx) {
-    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-      for (int k = k0; k < k1; ++k) {
-        const size_t c = cidx(g, i, j, k);
-        double wv = w[c];
+  GMG_FLAT_LOOP(c, n) {
+    double wv = w[c];
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q)
-          if (q < nv) wv -= cf[q] * U[(size_t)q * stride + c];
-        w[c] = wv;
-        acc[0] += wv * wv;
-      }
-    }
+    for (int q = 0; q < NV; ++q) wv -= cf[q] * U[(size_t)q * stride + c];
+    w[c] = wv;
+    acc[0] += wv * wv;
   }
-  if (want_norm) block_store_partials<1>(acc, 1, partials, gridDim.x * gridDim.y * gridDim.z);
+  if (want_norm) block_store_partials<1>(acc, 1, partials, gridDim.x);
 }
 
-// phi += sum_v y_v z_v (z promoted to float64).
-template <typename TZ>
-__global__ __launch_bounds__(NTHREADS) void k_update(double* __restrict__ phi, Geom g, const TZ* __restrict__ Z,
-                                                     size_t stride, int nv, Coeffs16 y, int kc) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  if (i >= g.nx) return;
-  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-    for (int k = k0; k < k1; ++k) {
-      const size_t c = cidx(g, i, j, k);
-      double p = phi[c];
+// phi += sum_v y_v z_v (z promoted to float64; flat launch).
+template <typename TZ, int NV>
+__global__ __launch_bounds__(NTHREADS) void k_update(double* __restrict__ phi, size_t n, const TZ* __restrict__ Z,
+                                                     size_t stride, Coeffs16 y) {
+  GMG_FLAT_LOOP(c, n) {
+    double p = phi[c];
 #pragma unroll
-      for (int q = 0; q < MAXV; ++q)
-        if (q < nv) p += y.v[q] * (double)Z[(size_t)q * stride + c];
-      phi[c] = p;
-    }
+    for (int q = 0; q < NV; ++q) p += y.v[q] * (double)Z[(size_t)q * stride + c];
+    phi[c] = p;
   }
 }
 
