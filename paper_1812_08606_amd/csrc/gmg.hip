@@ -27,6 +27,7 @@ constexpr double BREAKDOWN_TOL = 1e-14;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+
 struct LevelShape {
   int nx, ny, nz;
   double hx, hy, hz;
@@ -58,6 +59,7 @@ struct Layout {
   std::vector<LevelOffsets> lv;
   size_t V, Z, a32, b0, xs, partials, scal, cinv, total;
   size_t tsize;  // bytes of the V-cycle precision
+  size_t ldv;    // elements between consecutive Krylov vectors (v_i and z_i)
   int m;
 };
 
@@ -78,6 +80,7 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   if (!options_valid(o)) return GMG_ERR_ARG;
   if (nx < 1 || ny < 1 || nz < 1 || nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return GMG_ERR_SHAPE;
   if ((nx + BX - 1) / BX > MAX_RED_BLOCKS) return GMG_ERR_SHAPE;
+  if ((ny + BY - 1) / BY > 65535) return GMG_ERR_SHAPE;  // grid y of the z-marching kernels
   L->shapes = level_shapes(nx, ny, nz, hx, hy, hz);
   const LevelShape& last = L->shapes.back();
   if (last.n() > (size_t)o->coarse_max_cells) return GMG_ERR_SHAPE;
@@ -92,8 +95,9 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
     off = align_up(off + bytes);
     return at;
   };
-  L->V = take((size_t)(L->m + 1) * N * 8);
-  L->Z = take((size_t)L->m * N * L->tsize);
+  L->ldv = (N + 63) / 64 * 64;  // every Krylov vector starts 512-byte aligned
+  L->V = take((size_t)(L->m + 1) * L->ldv * 8);
+  L->Z = take((size_t)L->m * L->ldv * L->tsize);
   L->a32 = mixed ? take(N * 4) : 0;
   // finest-level right side in T: the float32 copy of v_j (mixed) or, when
   // the finest level is also the coarsest, the scaled right side
@@ -129,6 +133,21 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   L->cinv = take(nc * nc * L->tsize);
   L->total = off;
   return GMG_OK;
+}
+
+// The levels small enough for the one-workgroup bottom kernel: the first
+// level l >= 1 from which every level has at most BOTTOM_MAX_CELLS cells, the
+// coarsest at most BOTTOM_MAX_COARSEST, and at most BOTTOM_MAX_LEVELS levels
+// remain; -1 when that leaves only the coarsest (a plain direct solve).
+constexpr size_t BOTTOM_MAX_CELLS = 4096;
+constexpr size_t BOTTOM_MAX_COARSEST = 512;
+
+int bottom_level(const Layout& L) {
+  const int nl = (int)L.shapes.size();
+  if (nl < 3 || L.shapes.back().n() > BOTTOM_MAX_COARSEST) return -1;
+  int l = nl - 1;
+  while (l > 1 && L.shapes[l - 1].n() <= BOTTOM_MAX_CELLS && nl - (l - 1) <= BOTTOM_MAX_LEVELS) --l;
+  return l < nl - 1 ? l : -1;
 }
 
 struct Launch {
@@ -192,6 +211,7 @@ struct gmg_ctx {
   size_t N;
   bool mixed;
   int nc;  // cells on the coarsest level
+  int bottom_from;  // first level run by the one-workgroup bottom kernel (-1: none)
   double* pinned;
   hipError_t err;
   Profiler prof;
@@ -431,67 +451,64 @@ const char* kname(const char* base, int level, size_t tsize) {
   return it->second.c_str();
 }
 
-// Smoothing and residual on one level, for any coefficient storage.
-template <typename T, typename TB, typename Coef>
-void smooth_pre(gmg_ctx* c, int l, T* x, const TB* b, const double* bscale, T* b_out, Coef co) {
-  const LevelShape& s = c->L.shapes[l];
-  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
-  const Geom g = s.geom();
-  const int nu = c->opt.nu_pre;
-  GMG_LAUNCH(c, kname("gs_first", l, sizeof(T)), (k_gs_first<T, TB, Coef>), lc, x, b, bscale, b_out,
-             co, g, lc.kc, nu > 0 ? 1 : 0);
-  if (nu == 0) return;
-  // b_out holds the scaled right side from now on
-  if (b_out) {
-    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
-               (const double*)nullptr, co, g, lc.kc, 1);
-    for (int it = 1; it < nu; ++it) {
-      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
-                 (const double*)nullptr, co, g, lc.kc, 0);
-      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, T, Coef>), lc, x, (const T*)b_out,
-                 (const double*)nullptr, co, g, lc.kc, 1);
-    }
-  } else {
-    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
-    for (int it = 1; it < nu; ++it) {
-      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
-      GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
-    }
-  }
-}
-
-template <typename T, typename TB, typename Coef>
-void smooth_post(gmg_ctx* c, int l, T* x, const TB* b, const double* bscale, Coef co) {
-  const LevelShape& s = c->L.shapes[l];
-  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
-  const Geom g = s.geom();
-  for (int it = 0; it < c->opt.nu_post; ++it) {
-    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 1);
-    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs<T, TB, Coef>), lc, x, b, bscale, co, g, lc.kc, 0);
-  }
+// Launch of the lane-pair z-marching kernels over an nx x ny x nz grid (nx
+// even): one lane per x-pair, rows of BY threads, z-chunks of kc planes with
+// kc >= min_kc, about `target` blocks.
+Launch pair_launch(int nx, int ny, int nz, long long target, int min_kc) {
+  const int gx = (nx / 2 + BX - 1) / BX, gy = (ny + BY - 1) / BY;
+  const long long cols = (long long)gx * gy;
+  int kc = (int)std::max<long long>(min_kc, (nz * cols + target - 1) / target);
+  kc = std::min(kc, nz);
+  return Launch{dim3(gx, gy, (nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
 }
 
 // Finest level: the z-marching residual/restriction kernel.
 template <typename T, typename TB>
 void resid_restrict_fine(gmg_ctx* c, const T* x, const TB* b, const double* bscale, const T* a, T* bc) {
   const LevelShape& s = c->L.shapes[0];
-  const int NX = s.nx / 2, NZ = s.nz / 2;
-  const int gx = (NX + BX - 1) / BX, gy = (s.ny + BY - 1) / BY;
-  const long long cols = (long long)gx * gy;
-  int kc = (int)std::max<long long>(4, (NZ * cols + 8191) / 8192);
-  kc = std::min(kc, NZ);
-  const Launch l{dim3(gx, std::min(gy, 65535), (NZ + kc - 1) / kc), dim3(BX, BY, 1), kc};
+  const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
   GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), (k_resid_restrict_cell<T, TB>), l, x, b, bscale, a, s.geom(),
-             bc, kc);
+             bc, l.kc);
 }
 
-template <typename T, typename TB, typename Coef>
-void resid_restrict(gmg_ctx* c, int l, const T* x, const TB* b, const double* bscale, Coef co, T* bc) {
+// Coarse level l (not the coarsest, so every dimension is even): red-black
+// smoothing, residual and restriction with the lane-pair kernels on the
+// stored face coefficients.
+template <typename T>
+void smooth_pre_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co) {
   const LevelShape& s = c->L.shapes[l];
-  const LevelShape& cs = c->L.shapes[l + 1];
-  const Launch lc = col_launch(cs.nx, cs.ny, cs.nz, 1 << 16);
-  GMG_LAUNCH(c, kname("resid_restrict", l, sizeof(T)), (k_resid_restrict<T, TB, Coef>), lc, x, b,
-             bscale, co, s.geom(), bc, lc.kc);
+  const Geom g = s.geom();
+  const int nu = c->opt.nu_pre;
+  if (nu == 0) {
+    const Launch fl = flat_launch(s.n());
+    GMG_LAUNCH(c, kname("fill", l, sizeof(T)), k_fill<T>, fl, x, T(0), s.n());
+    return;
+  }
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
+  GMG_LAUNCH(c, kname("gs_first", l, sizeof(T)), (k_gs_pair_face<T, true>), pl, x, b, co, g, pl.kc, 0);
+  GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, g, pl.kc, 1);
+  for (int it = 1; it < nu; ++it) {
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, g, pl.kc, 0);
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, g, pl.kc, 1);
+  }
+}
+
+template <typename T>
+void smooth_post_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co) {
+  const LevelShape& s = c->L.shapes[l];
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
+  for (int it = 0; it < c->opt.nu_post; ++it) {
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, s.geom(), pl.kc, 1);
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, s.geom(), pl.kc, 0);
+  }
+}
+
+template <typename T>
+void resid_restrict_face(gmg_ctx* c, int l, const T* x, const T* b, const FaceCoef<T>& co, T* bc) {
+  const LevelShape& s = c->L.shapes[l];
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2);
+  GMG_LAUNCH(c, kname("resid_restrict", l, sizeof(T)), k_resid_restrict_face<T>, pl, x, b, co, s.geom(), bc,
+             pl.kc);
 }
 
 template <typename T>
@@ -509,6 +526,26 @@ void coarse_solve(gmg_ctx* c, const T* b, T* x) {
              wsp<const T>(c, c->L.cinv), b, x, n);
 }
 
+// The levels from l0 down to the coarsest in one workgroup (k_vcycle_bottom).
+template <typename T>
+void vcycle_bottom(gmg_ctx* c, int l0) {
+  const int nl = (int)c->L.shapes.size();
+  BottomArgs<T> A{};
+  A.nlev = nl - l0;
+  for (int q = 0; q < A.nlev; ++q) {
+    const int l = l0 + q;
+    A.co[q] = face_coef<T>(c, l);
+    A.x[q] = wsp<T>(c, c->L.lv[l].x);
+    A.b[q] = wsp<T>(c, c->L.lv[l].b);
+    A.g[q] = c->L.shapes[l].geom();
+  }
+  A.Ainv = wsp<const T>(c, c->L.cinv);
+  A.nu_pre = c->opt.nu_pre;
+  A.nu_post = c->opt.nu_post;
+  const Launch one{dim3(1), dim3(BOTTOM_THREADS, 1, 1), 0};
+  GMG_LAUNCH(c, kname("vcycle_bottom", 1, sizeof(T)), k_vcycle_bottom<T>, one, A);
+}
+
 // Levels >= 1 (face coefficients), right side in lv[l].b, result in lv[l].x.
 template <typename T>
 void vcycle_coarse(gmg_ctx* c, int l) {
@@ -520,12 +557,16 @@ void vcycle_coarse(gmg_ctx* c, int l) {
     coarse_solve<T>(c, b, x);
     return;
   }
+  if (l == c->bottom_from) {
+    vcycle_bottom<T>(c, l);
+    return;
+  }
   const FaceCoef<T> co = face_coef<T>(c, l);
-  smooth_pre<T, T>(c, l, x, b, nullptr, (T*)nullptr, co);
-  resid_restrict<T, T>(c, l, x, b, nullptr, co, wsp<T>(c, c->L.lv[l + 1].b));
+  smooth_pre_face<T>(c, l, x, b, co);
+  resid_restrict_face<T>(c, l, x, b, co, wsp<T>(c, c->L.lv[l + 1].b));
   vcycle_coarse<T>(c, l + 1);
   prolong_add<T>(c, l, x, wsp<T>(c, c->L.lv[l + 1].x));
-  smooth_post<T, T>(c, l, x, b, nullptr, co);
+  smooth_post_face<T>(c, l, x, b, co);
 }
 
 // Finest-level smoother kernels: option fine_sweep, 0 selects the faster
@@ -539,7 +580,7 @@ struct SweepTY {
 };
 
 template <typename T, typename TB, int XM>
-void sym_sweep(gmg_ctx* c, const T* x_in, const T* xc, const TB* b, const double* bscale, T* b_out, const T* a,
+void sym_sweep(gmg_ctx* c, const T* x_in, const TB* b, const double* bscale, T* b_out, const T* a,
                T* x_out, int c1) {
   constexpr int TY = SweepTY<T>::value;
   const LevelShape& s = c->L.shapes[0];
@@ -549,8 +590,8 @@ void sym_sweep(gmg_ctx* c, const T* x_in, const T* xc, const TB* b, const double
   kc = std::min(kc, s.nz);
   const int gz = (s.nz + kc - 1) / kc;
   const Launch l{dim3(gx, std::min(gy, 65535), gz), dim3(BX, BY, 1), kc};
-  SweepArgs<T, TB> A{x_in, xc, b, bscale, b_out, a, x_out, s.geom(), c1, kc};
-  const char* nm = XM == SWEEP_X_ZERO ? "sym_sweep_zero" : (XM == SWEEP_X_LOAD ? "sym_sweep" : "sym_sweep_prolong");
+  SweepArgs<T, TB> A{x_in, b, bscale, b_out, a, x_out, s.geom(), c1, kc};
+  const char* nm = XM == SWEEP_X_ZERO ? "sym_sweep_zero" : "sym_sweep";
   if (bscale)
     GMG_LAUNCH(c, kname(nm, 0, sizeof(T)), (k_sym_sweep<T, TB, XM, TY, true>), l, A);
   else
@@ -569,12 +610,12 @@ void vcycle_fine_fused(gmg_ctx* c, const double* u, const double* bscale, T* z) 
   T* b0 = c->mixed ? wsp<T>(c, c->L.b0) : nullptr;
   T* bc = wsp<T>(c, c->L.lv[1].b);
   // pre-smoothing: red then black, from x = 0
-  sym_sweep<T, double, SWEEP_X_ZERO>(c, nullptr, nullptr, u, bscale, b0, a, buf(1), 0);
+  sym_sweep<T, double, SWEEP_X_ZERO>(c, nullptr, u, bscale, b0, a, buf(1), 0);
   for (int p = 2; p <= npre; ++p) {
     if (c->mixed)
-      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, (const T*)b0, nullptr, nullptr, a, buf(p), 0);
+      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), (const T*)b0, nullptr, nullptr, a, buf(p), 0);
     else
-      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, u, bscale, nullptr, a, buf(p), 0);
+      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), u, bscale, nullptr, a, buf(p), 0);
   }
   if (c->mixed)
     resid_restrict_fine<T, T>(c, buf(npre), (const T*)b0, nullptr, a, bc);
@@ -585,24 +626,21 @@ void vcycle_fine_fused(gmg_ctx* c, const double* u, const double* bscale, T* z) 
   prolong_add<T>(c, 0, buf(npre), wsp<T>(c, c->L.lv[1].x));
   for (int p = npre + 1; p <= L; ++p) {
     if (c->mixed)
-      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, (const T*)b0, nullptr, nullptr, a, buf(p), 1);
+      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), (const T*)b0, nullptr, nullptr, a, buf(p), 1);
     else
-      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), nullptr, u, bscale, nullptr, a, buf(p), 1);
+      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), u, bscale, nullptr, a, buf(p), 1);
   }
 }
 
-template <typename T, typename TB>
-void gs_pair(gmg_ctx* c, T* x, const TB* b, const double* bscale, const T* a, int colour) {
+template <typename T, typename TB, bool FIRST>
+void gs_pair(gmg_ctx* c, T* x, const TB* b, const double* bscale, T* b_out, const T* a, int colour) {
   const LevelShape& s = c->L.shapes[0];
-  const int gx = (s.nx / 2 + BX - 1) / BX, gy = (s.ny + BY - 1) / BY;
-  const long long cols = (long long)gx * gy;
-  int kc = (int)std::max<long long>(8, (s.nz * cols + 8191) / 8192);
-  kc = std::min(kc, s.nz);
-  const Launch l{dim3(gx, std::min(gy, 65535), (s.nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
+  const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+  const char* nm = kname(FIRST ? "gs_first" : "gs", 0, sizeof(T));
   if (bscale)
-    GMG_LAUNCH(c, kname("gs", 0, sizeof(T)), (k_gs_pair<T, TB, true>), l, x, b, bscale, a, s.geom(), kc, colour);
+    GMG_LAUNCH(c, nm, (k_gs_pair<T, TB, true, FIRST>), l, x, b, bscale, b_out, a, s.geom(), l.kc, colour);
   else
-    GMG_LAUNCH(c, kname("gs", 0, sizeof(T)), (k_gs_pair<T, TB, false>), l, x, b, bscale, a, s.geom(), kc, colour);
+    GMG_LAUNCH(c, nm, (k_gs_pair<T, TB, false, FIRST>), l, x, b, bscale, b_out, a, s.geom(), l.kc, colour);
 }
 
 // Finest level with one kernel per half-sweep (at least two levels, so the
@@ -615,16 +653,19 @@ void vcycle_fine_half(gmg_ctx* c, const double* u, const double* bscale, T* z) {
   const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
   T* b0 = c->mixed ? wsp<T>(c, c->L.b0) : nullptr;
   T* bc = wsp<T>(c, c->L.lv[1].b);
-  const CellCoef<T> co{a};
-  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
   const int npre = c->opt.nu_pre, npost = c->opt.nu_post;
-  GMG_LAUNCH(c, kname("gs_first", 0, sizeof(T)), (k_gs_first<T, double, CellCoef<T>>), lc, z, u, bscale, b0, co,
-             s.geom(), lc.kc, npre > 0 ? 1 : 0);
+  if (npre > 0) {
+    gs_pair<T, double, true>(c, z, u, bscale, b0, a, 0);
+  } else {
+    const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
+    GMG_LAUNCH(c, kname("gs_first", 0, sizeof(T)), (k_gs_first<T, double, CellCoef<T>>), lc, z, u, bscale, b0,
+               CellCoef<T>{a}, s.geom(), lc.kc, 0);
+  }
   auto half = [&](int colour) {
     if (c->mixed)
-      gs_pair<T, T>(c, z, (const T*)b0, nullptr, a, colour);
+      gs_pair<T, T, false>(c, z, (const T*)b0, nullptr, nullptr, a, colour);
     else
-      gs_pair<T, double>(c, z, u, bscale, a, colour);
+      gs_pair<T, double, false>(c, z, u, bscale, nullptr, a, colour);
   };
   for (int it = 0; it < npre; ++it) {
     if (it > 0) half(0);
@@ -710,20 +751,20 @@ Launch red_flat(gmg_ctx* c) {
 template <typename TZ, int NV>
 void launch_opdot(gmg_ctx* c, const Launch& rl, const TZ* z, double* w, const double* V) {
   GMG_LAUNCH(c, sizeof(TZ) == 4 ? "op_multidot_zf32" : "op_multidot_zf64", (k_op_multidot<TZ, NV>), rl, z, c->a,
-             c->L.shapes[0].geom(), w, V, c->N, wsp<double>(c, c->L.partials), rl.kc);
+             c->L.shapes[0].geom(), w, V, c->L.ldv, wsp<double>(c, c->L.partials), rl.kc);
 }
 template <int NV>
 void launch_dot(gmg_ctx* c, const Launch& rl, const double* w, const double* V) {
-  GMG_LAUNCH(c, "multidot", k_multidot<NV>, rl, w, c->N, V, c->N, wsp<double>(c, c->L.partials));
+  GMG_LAUNCH(c, "multidot", k_multidot<NV>, rl, w, c->N, V, c->L.ldv, wsp<double>(c, c->L.partials));
 }
 template <int NV>
 void launch_axpy(gmg_ctx* c, const Launch& rl, double* w, const double* V, const double* hc, const double* vs,
                  int last) {
-  GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<NV>, rl, w, c->N, V, c->N, hc, vs, last, wsp<double>(c, c->L.partials));
+  GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<NV>, rl, w, c->N, V, c->L.ldv, hc, vs, last, wsp<double>(c, c->L.partials));
 }
 template <typename TZ, int NV>
 void launch_update(gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y) {
-  GMG_LAUNCH(c, sizeof(TZ) == 4 ? "update_zf32" : "update_zf64", (k_update<TZ, NV>), rl, phi, c->N, Z, c->N, y);
+  GMG_LAUNCH(c, sizeof(TZ) == 4 ? "update_zf32" : "update_zf64", (k_update<TZ, NV>), rl, phi, c->N, Z, c->L.ldv, y);
 }
 
 template <typename TZ, size_t... I>
@@ -757,7 +798,7 @@ void update_nv(int nv, gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, c
 // One Arnoldi step j: z_j = M v_j, w = A z_j, classical Gram-Schmidt against
 // v_0..v_j (dots fused into the operator pass), ||w||; results in hcol(j).
 void arnoldi_step(gmg_ctx* c, int j) {
-  const size_t N = c->N;
+  const size_t N = c->L.ldv;
   double* V = wsp<double>(c, c->L.V);
   char* Zb = c->ws + c->L.Z + (size_t)j * N * c->L.tsize;
   double* vs = scal_vscale(c);
@@ -797,7 +838,7 @@ void update_solution(gmg_ctx* c, double* phi, int k) {
     const int nq = std::min(MAXV, k - q0);
     Coeffs16 y{};
     for (int q = 0; q < nq; ++q) y.v[q] = c->y[q0 + q];
-    char* Zb = c->ws + c->L.Z + (size_t)q0 * c->N * c->L.tsize;
+    char* Zb = c->ws + c->L.Z + (size_t)q0 * c->L.ldv * c->L.tsize;
     if (c->mixed)
       update_nv<float>(nq, c, fl, phi, (const float*)Zb, y, seq);
     else
@@ -866,6 +907,7 @@ int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const dou
   c->N = L.shapes[0].n();
   c->mixed = opt->precision == GMG_MIXED;
   c->nc = (int)L.shapes.back().n();
+  c->bottom_from = bottom_level(L);
   c->err = hipSuccess;
   c->pinned = nullptr;
   const int m = opt->restart;

@@ -30,6 +30,24 @@ __device__ __forceinline__ size_t cidx(const Geom& g, int i, int j, int k) {
   return ((size_t)k * g.ny + j) * g.nx + i;
 }
 
+// Workgroups go to the chip's 8 XCDs (each with its own L2) round-robin in
+// the order of their linear index.  xcd_tile renumbers them so that every XCD
+// receives one contiguous range of tiles in launch order: tiles adjacent in y
+// or z, which read each other's edge rows and planes, then share one L2 and
+// run at about the same time.  The map is a bijection for any grid size.
+struct Tile {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Tile xcd_tile() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nb = gx * gy * gridDim.z;
+  const int w = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = w & 7, q = nb >> 3, r = nb & 7;
+  const int t = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + (w >> 3);
+  return Tile{t % gx, (t / gx) % gy, t / (gx * gy)};
+}
+
 // Face weights of one cell, already divided by h_d^2.
 template <typename T>
 struct Stencil {
@@ -158,11 +176,12 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_first(T* __restrict__ x, const 
                                                        const double* __restrict__ bscale,
                                                        T* __restrict__ b_out, Coef co, Geom g, int kc,
                                                        int red) {
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * BX + threadIdx.x;
   if (i >= g.nx) return;
   const double s = bscale ? *bscale : 1.0;
-  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
     for (int k = k0; k < k1; ++k) {
       const size_t c = cidx(g, i, j, k);
       const T bv = (T)((double)b_in[c] * s);
@@ -177,57 +196,6 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_first(T* __restrict__ x, const 
   }
 }
 
-// Gauss-Seidel half-sweep over the cells of one colour ((i+j+k)%2 ==
-// colour), in place: x_c = (b_c + sum_f w_f x_nb / h^2) / D_c.  Cells of one
-// colour are never neighbours, so the update is order-free.
-template <typename T, typename TB, typename Coef>
-__global__ __launch_bounds__(NTHREADS) void k_gs(T* __restrict__ x, const TB* __restrict__ b,
-                                                 const double* __restrict__ bscale, Coef co, Geom g, int kc,
-                                                 int colour) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  if (i >= g.nx) return;
-  const T s = (T)(bscale ? *bscale : 1.0);
-  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-    for (int k = k0 + ((i + j + k0 + colour) & 1); k < k1; k += 2) {
-      const size_t c = cidx(g, i, j, k);
-      const Stencil<T> st = co.load(g, i, j, k, c);
-      const Nbrs<T> v = load_nbrs<T>(x, g, i, j, k, c, T(0), T(0));
-      T off = st.ww * v.w + st.we * v.e + st.ws * v.s + st.wn * v.n;
-      if (k > 0) off += st.wb * v.b;
-      if (k < g.nz - 1) off += st.wt * v.t;
-      x[c] = ((T)b[c] * s + off) / diag_cell(st, g, k);
-    }
-  }
-}
-
-// Residual and restriction: b_coarse(I) = mean over the 8 children of
-// (b - A x).  g is the fine grid (all dimensions even); kc chunks coarse z.
-template <typename T, typename TB, typename Coef>
-__global__ __launch_bounds__(NTHREADS) void k_resid_restrict(const T* __restrict__ x, const TB* __restrict__ b,
-                                                             const double* __restrict__ bscale, Coef co, Geom g,
-                                                             T* __restrict__ bc, int kc) {
-  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
-  const int I = blockIdx.x * BX + threadIdx.x;
-  if (I >= NX) return;
-  const T s = (T)(bscale ? *bscale : 1.0);
-  const int K0 = blockIdx.z * kc, K1 = min(NZ, K0 + kc);
-  for (int J = blockIdx.y * BY + threadIdx.y; J < NY; J += gridDim.y * BY) {
-    for (int K = K0; K < K1; ++K) {
-      T sum = T(0);
-#pragma unroll
-      for (int d = 0; d < 8; ++d) {
-        const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
-        const size_t c = cidx(g, i, j, k);
-        const Stencil<T> st = co.load(g, i, j, k, c);
-        const Nbrs<T> v = load_nbrs<T>(x, g, i, j, k, c, T(0), T(0));
-        sum += (T)b[c] * s - apply_cell(st, v);
-      }
-      bc[((size_t)K * NY + J) * NX + I] = sum * T(0.125);
-    }
-  }
-}
-
 // Red-black half-sweep of one colour on the finest level (cell
 // coefficient; even nx).  Lane tx owns the x-pair (2m, 2m+1), m = 64 bx + tx,
 // of row j = 4 by + ty and marches its z-chunk keeping x and a of the pair on
@@ -235,59 +203,132 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict(const T* __restrict
 // pair has the colour being updated, the same one across a row, so a wave
 // takes one branch; the x-neighbour outside the pair comes from the adjacent
 // lane (a load at the wave's edges).  Only cells of the other colour are
-// read, and none of them is written, so the update is order-free.
-template <typename T, typename TB, bool SCALED>
+// read, and none of them is written, so the update is order-free, and every
+// load of plane k+1 (and the pair of plane k+2) is issued before plane k is
+// computed: one memory latency per plane is hidden behind the previous one.
+// FIRST: the first pre-smoothing half-sweep from x = 0 (x is not read; cells
+// of the colour get b / D, the others 0), also storing b in T into b_out if
+// given.
+template <typename T, typename TB>
+struct PairSide {
+  T sa, sx, na, nx;  // a and x of the updated cell's y-neighbours
+  T wa, wx, ea, ex;  // a and x outside the pair (wave-edge lanes only)
+  TB b0, b1;         // right side of the updated cell (FIRST: of both cells)
+};
+
+template <typename T, typename TB, bool FIRST>
+__device__ __forceinline__ void pair_side_fetch(PairSide<T, TB>& S, const T* __restrict__ x,
+                                                const T* __restrict__ a, const TB* __restrict__ b, size_t c,
+                                                size_t sy, int e, bool hs, bool hn, bool lw, bool le) {
+  const size_t ce = c + e;
+  S.sa = S.sx = S.na = S.nx = S.wa = S.wx = S.ea = S.ex = T(0);
+  if (hs) {
+    S.sa = a[ce - sy];
+    if (!FIRST) S.sx = x[ce - sy];
+  }
+  if (hn) {
+    S.na = a[ce + sy];
+    if (!FIRST) S.nx = x[ce + sy];
+  }
+  if (lw) {
+    S.wa = a[c - 1];
+    if (!FIRST) S.wx = x[c - 1];
+  }
+  if (le) {
+    S.ea = a[c + 2];
+    if (!FIRST) S.ex = x[c + 2];
+  }
+  if (FIRST) {
+    S.b0 = b[c];
+    S.b1 = b[c + 1];
+  } else {
+    S.b0 = b[ce];
+    S.b1 = TB(0);
+  }
+}
+
+template <typename T, typename TB, bool SCALED, bool FIRST>
 __global__ __launch_bounds__(NTHREADS) void k_gs_pair(T* __restrict__ x, const TB* __restrict__ b,
-                                                      const double* __restrict__ bscale, const T* __restrict__ a,
-                                                      Geom g, int kc, int colour) {
-  const int m = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
+                                                      const double* __restrict__ bscale, T* __restrict__ b_out,
+                                                      const T* __restrict__ a, Geom g, int kc, int colour) {
+  const Tile tl = xcd_tile();
+  const int m = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
   const int i0 = 2 * m;
   const bool act = i0 < g.nx && j < g.ny;
   const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
   const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
   const double s = SCALED ? *bscale : 1.0;
-  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-  const bool hs = j > 0, hn = j < g.ny - 1;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  const bool hs = act && j > 0, hn = act && j < g.ny - 1;
   const bool hwo = i0 > 0, heo = i0 + 2 < g.nx;  // faces outside the pair
   const int lane = threadIdx.x;
+  const bool lw = act && lane == 0 && hwo, le = act && lane == BX - 1 && heo;
+  const int par = colour + i0 + j;  // the updated element on plane k is (par + k) & 1
   size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
-  T xc0 = T(0), xc1 = T(0), ac0 = T(0), ac1 = T(0), xb0 = T(0), xb1 = T(0), ab0 = T(0), ab1 = T(0);
+  T xc0 = T(0), xc1 = T(0), ac0 = T(0), ac1 = T(0);  // the pair on plane k
+  T xb0 = T(0), xb1 = T(0), ab0 = T(0), ab1 = T(0);  // plane k-1
+  T xt0 = T(0), xt1 = T(0), at0 = T(0), at1 = T(0);  // plane k+1
+  PairSide<T, TB> S{};
   if (act) {
-    xc0 = x[c];
-    xc1 = x[c + 1];
     ac0 = a[c];
     ac1 = a[c + 1];
+    if (!FIRST) {
+      xc0 = x[c];
+      xc1 = x[c + 1];
+    }
     if (k0 > 0) {
-      xb0 = x[c - sz];
-      xb1 = x[c - sz + 1];
       ab0 = a[c - sz];
       ab1 = a[c - sz + 1];
+      if (!FIRST) {
+        xb0 = x[c - sz];
+        xb1 = x[c - sz + 1];
+      }
     }
-  }
-  for (int k = k0; k < k1; ++k) {
-    const bool top = k == g.nz - 1;
-    T xt0 = T(0), xt1 = T(0), at0 = T(0), at1 = T(0);
-    if (act && !top) {
-      xt0 = x[c + sz];
-      xt1 = x[c + sz + 1];
+    if (k0 + 1 < g.nz) {
       at0 = a[c + sz];
       at1 = a[c + sz + 1];
+      if (!FIRST) {
+        xt0 = x[c + sz];
+        xt1 = x[c + sz + 1];
+      }
     }
+    pair_side_fetch<T, TB, FIRST>(S, x, a, b, c, sy, (par + k0) & 1, hs, hn, lw, le);
+  }
+  for (int k = k0; k < k1; ++k) {
+    // prefetch: the pair of plane k+2 and the side values of plane k+1
+    T xu0 = T(0), xu1 = T(0), au0 = T(0), au1 = T(0);
+    PairSide<T, TB> Sn{};
+    if (act && k + 1 < k1) {
+      if (k + 2 < g.nz) {
+        au0 = a[c + 2 * sz];
+        au1 = a[c + 2 * sz + 1];
+        if (!FIRST) {
+          xu0 = x[c + 2 * sz];
+          xu1 = x[c + 2 * sz + 1];
+        }
+      }
+      pair_side_fetch<T, TB, FIRST>(Sn, x, a, b, c + sz, sy, (par + k + 1) & 1, hs, hn, lw, le);
+    }
+    const bool top = k == g.nz - 1;
     // outer x-neighbours of the pair on plane k: lane tx-1's right cell and
     // lane tx+1's left cell (loads at the wave's edges)
-    T xwo = __shfl_up(xc1, 1, 64), awo = __shfl_up(ac1, 1, 64);
-    T xeo = __shfl_down(xc0, 1, 64), aeo = __shfl_down(ac0, 1, 64);
-    if (act && lane == 0 && hwo) {
-      xwo = x[c - 1];
-      awo = a[c - 1];
+    T awo = __shfl_up(ac1, 1, 64), aeo = __shfl_down(ac0, 1, 64);
+    T xwo = T(0), xeo = T(0);
+    if (!FIRST) {
+      xwo = __shfl_up(xc1, 1, 64);
+      xeo = __shfl_down(xc0, 1, 64);
     }
-    if (act && lane == BX - 1 && heo) {
-      xeo = x[c + 2];
-      aeo = a[c + 2];
+    if (lw) {
+      awo = S.wa;
+      xwo = S.wx;
+    }
+    if (le) {
+      aeo = S.ea;
+      xeo = S.ex;
     }
     if (act) {
-      const int e = (colour + i0 + j + k) & 1;  // element of the pair being updated
+      const int e = (par + k) & 1;  // element of the pair being updated
       const size_t ce = c + e;
       const T acv = e ? ac1 : ac0;
       // x-faces: the pair's inner face and the outer face on the cell's side
@@ -298,14 +339,14 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_pair(T* __restrict__ x, const T
       const T wo = hout ? (acv + aout) * hx : T(0);
       T D = wi + wo, off = wi * xin + (hout ? wo * xout : T(0));
       if (hs) {
-        const T w = (acv + a[ce - sy]) * hy;
+        const T w = (acv + S.sa) * hy;
         D += w;
-        off += w * x[ce - sy];
+        off += w * S.sx;
       }
       if (hn) {
-        const T w = (acv + a[ce + sy]) * hy;
+        const T w = (acv + S.na) * hy;
         D += w;
-        off += w * x[ce + sy];
+        off += w * S.nx;
       }
       const T xbv = e ? xb1 : xb0, abv = e ? ab1 : ab0;
       const T xtv = e ? xt1 : xt0, atv = e ? at1 : at0;
@@ -323,18 +364,326 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_pair(T* __restrict__ x, const T
       } else {
         D += pz * acv;
       }
-      const T bv = SCALED ? (T)((double)b[ce] * s) : (T)b[ce];
-      x[ce] = (bv + off) * sweep_recip(D);
+      if (FIRST) {
+        // both cells' right side (stored in T when b_out is given); the
+        // other colour starts at 0
+        const T b0v = SCALED ? (T)((double)S.b0 * s) : (T)S.b0;
+        const T b1v = SCALED ? (T)((double)S.b1 * s) : (T)S.b1;
+        if (b_out) {
+          b_out[c] = b0v;
+          b_out[c + 1] = b1v;
+        }
+        x[ce] = (e ? b1v : b0v) * sweep_recip(D);
+        x[c + 1 - e] = T(0);
+      } else {
+        const T bv = SCALED ? (T)((double)S.b0 * s) : (T)S.b0;
+        x[ce] = (bv + off) * sweep_recip(D);
+      }
     }
     xb0 = xc0;
     xb1 = xc1;
     xc0 = xt0;
     xc1 = xt1;
+    xt0 = xu0;
+    xt1 = xu1;
     ab0 = ac0;
     ab1 = ac1;
     ac0 = at0;
     ac1 = at1;
+    at0 = au0;
+    at1 = au1;
+    S = Sn;
     c += act ? sz : 0;
+  }
+}
+
+// Red-black half-sweep of one colour on a coarse level (stored face
+// coefficients; even nx): the lane-pair scheme of k_gs_pair.  The face
+// between the pair's right cell and the next pair is the adjacent lane's west
+// face.  FIRST: the first pre-smoothing half-sweep from x = 0 (cells of the
+// colour get b / D, the others 0; x is not read).
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(NTHREADS) void k_gs_pair_face(T* __restrict__ x, const T* __restrict__ b,
+                                                           FaceCoef<T> co, Geom g, int kc, int colour) {
+  const Tile tl = xcd_tile();
+  const int m = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
+  const int i0 = 2 * m;
+  const bool act = i0 < g.nx && j < g.ny;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const T ix = (T)g.ihx2, iy = (T)g.ihy2, iz = (T)g.ihz2;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  const bool hs = j > 0, hn = j < g.ny - 1;
+  const bool hwo = i0 > 0, heo = i0 + 2 < g.nx;
+  const int lane = threadIdx.x;
+  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
+  T xc0 = T(0), xc1 = T(0), xb0 = T(0), xb1 = T(0), wb0 = T(0), wb1 = T(0);
+  if (act) {
+    wb0 = co.wz[c];
+    wb1 = co.wz[c + 1];
+    if (!FIRST) {
+      xc0 = x[c];
+      xc1 = x[c + 1];
+      if (k0 > 0) {
+        xb0 = x[c - sz];
+        xb1 = x[c - sz + 1];
+      }
+    }
+  }
+  for (int k = k0; k < k1; ++k) {
+    const bool top = k == g.nz - 1;
+    T xt0 = T(0), xt1 = T(0), wt0 = T(0), wt1 = T(0), wx0 = T(0), wx1 = T(0);
+    if (act) {
+      if (!top) {
+        if (!FIRST) {
+          xt0 = x[c + sz];
+          xt1 = x[c + sz + 1];
+        }
+        wt0 = co.wz[c + sz];
+        wt1 = co.wz[c + sz + 1];
+      } else {
+        wt0 = co.tp[(size_t)j * g.nx + i0];
+        wt1 = co.tp[(size_t)j * g.nx + i0 + 1];
+      }
+      wx0 = co.wx[c];
+      wx1 = co.wx[c + 1];
+    }
+    T wxe = __shfl_down(wx0, 1, 64);
+    if (act && lane == BX - 1 && heo) wxe = co.wx[c + 2];
+    T xwo = T(0), xeo = T(0);
+    if (!FIRST) {
+      xwo = __shfl_up(xc1, 1, 64);
+      xeo = __shfl_down(xc0, 1, 64);
+      if (act && lane == 0 && hwo) xwo = x[c - 1];
+      if (act && lane == BX - 1 && heo) xeo = x[c + 2];
+    }
+    if (act) {
+      const int e = (colour + i0 + j + k) & 1;
+      const size_t ce = c + e;
+      const T ww = e ? wx1 : (hwo ? wx0 : T(0)), we = e ? (heo ? wxe : T(0)) : wx1;
+      const T ws = hs ? co.wy[ce] : T(0), wn = hn ? co.wy[ce + sy] : T(0);
+      const T wb = e ? wb1 : wb0, wt = e ? wt1 : wt0;
+      const T D = (ww + we) * ix + (ws + wn) * iy + (k > 0 ? wb : T(2) * wb) * iz + (top ? T(2) * wt : wt) * iz;
+      if (FIRST) {
+        x[ce] = b[ce] * sweep_recip(D);
+        x[c + 1 - e] = T(0);
+      } else {
+        const T xw = e ? xc0 : xwo, xe = e ? xeo : xc1;
+        const T xs = hs ? x[ce - sy] : T(0), xn = hn ? x[ce + sy] : T(0);
+        const T xbv = e ? xb1 : xb0, xtv = e ? xt1 : xt0;
+        T off = (ww * xw + we * xe) * ix + (ws * xs + wn * xn) * iy;
+        off += k > 0 ? wb * iz * xbv : T(0);
+        off += !top ? wt * iz * xtv : T(0);
+        x[ce] = (b[ce] + off) * sweep_recip(D);
+      }
+    }
+    xb0 = xc0;
+    xb1 = xc1;
+    xc0 = xt0;
+    xc1 = xt1;
+    wb0 = wt0;
+    wb1 = wt1;
+    c += act ? sz : 0;
+  }
+}
+
+// Residual and restriction on a coarse level (stored face coefficients):
+// b_coarse = mean over the 8 children of (b - A x).  Lane tx owns the fine
+// x-pair (2I, 2I+1) of fine row j = 4 by + ty and marches the fine planes of
+// its z-chunk (2 per coarse plane); the two fine rows of a coarse row are
+// summed through LDS.  Needs even nx, ny, nz; kc counts coarse planes.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_resid_restrict_face(const T* __restrict__ x, const T* __restrict__ b,
+                                                                  FaceCoef<T> co, Geom g, T* __restrict__ bc,
+                                                                  int kc) {
+  const Tile tl = xcd_tile();
+  __shared__ T part[BY][BX];
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int I = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
+  const bool act = I < NX && j < g.ny;
+  const int i0 = 2 * I;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const T ix = (T)g.ihx2, iy = (T)g.ihy2, iz = (T)g.ihz2;
+  const int K0 = tl.z * kc, K1 = min(NZ, K0 + kc);
+  const int k0 = 2 * K0, k1 = 2 * K1;
+  const bool hw = i0 > 0, he = i0 + 2 < g.nx, hs = j > 0, hn = j < g.ny - 1;
+  T xb[2] = {T(0), T(0)}, xc[2] = {T(0), T(0)}, wb[2] = {T(0), T(0)};
+  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
+  if (act) {
+    for (int e = 0; e < 2; ++e) {
+      xc[e] = x[c + e];
+      wb[e] = co.wz[c + e];
+      if (k0 > 0) xb[e] = x[c + e - sz];
+    }
+  }
+  T acc = T(0);
+  for (int k = k0; k < k1; ++k) {
+    const bool top = k == g.nz - 1;
+    T rsum = T(0);
+    T xt[2] = {T(0), T(0)}, wt[2] = {T(0), T(0)};
+    if (act) {
+      for (int e = 0; e < 2; ++e) {
+        xt[e] = top ? T(0) : x[c + e + sz];
+        wt[e] = top ? co.tp[(size_t)j * g.nx + i0 + e] : co.wz[c + e + sz];
+      }
+      const T wx0 = co.wx[c], wx1 = co.wx[c + 1], wx2 = he ? co.wx[c + 2] : T(0);
+      const T xw = hw ? x[c - 1] : T(0), xe = he ? x[c + 2] : T(0);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const size_t ce = c + e;
+        const T xcv = xc[e];
+        T Ax = e == 0 ? (hw ? wx0 * ix * (xcv - xw) : T(0)) + wx1 * ix * (xcv - xc[1])
+                      : wx1 * ix * (xcv - xc[0]) + (he ? wx2 * ix * (xcv - xe) : T(0));
+        Ax += hs ? co.wy[ce] * iy * (xcv - x[ce - sy]) : T(0);
+        Ax += hn ? co.wy[ce + sy] * iy * (xcv - x[ce + sy]) : T(0);
+        Ax += k > 0 ? wb[e] * iz * (xcv - xb[e]) : T(2) * wb[e] * iz * xcv;
+        Ax += !top ? wt[e] * iz * (xcv - xt[e]) : T(2) * wt[e] * iz * xcv;
+        rsum += b[ce] - Ax;
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        xb[e] = xc[e];
+        xc[e] = xt[e];
+        wb[e] = wt[e];
+      }
+      c += sz;
+    }
+    acc += rsum;
+    if (k & 1) {
+      part[threadIdx.y][threadIdx.x] = acc;
+      __syncthreads();
+      if (!(threadIdx.y & 1) && act) {
+        const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
+        bc[((size_t)(k >> 1) * NY + (j >> 1)) * NX + I] = tot * T(0.125);
+      }
+      __syncthreads();
+      acc = T(0);
+    }
+  }
+}
+
+// The bottom of the V-cycle in one workgroup: every level from lb down to
+// the coarsest (all small) -- smoothing, residual and restriction, the
+// direct coarsest solve, prolongation and post-smoothing -- with block
+// barriers between the phases instead of kernel launches.  The right side of
+// level lb is read from its buffer and its iterate written to its buffer.
+constexpr int BOTTOM_MAX_LEVELS = 10;
+constexpr int BOTTOM_THREADS = 1024;
+
+template <typename T>
+struct BottomArgs {
+  FaceCoef<T> co[BOTTOM_MAX_LEVELS];
+  T* x[BOTTOM_MAX_LEVELS];
+  T* b[BOTTOM_MAX_LEVELS];
+  Geom g[BOTTOM_MAX_LEVELS];
+  const T* Ainv;
+  int nlev;  // levels handled, the last one the coarsest
+  int nu_pre, nu_post;
+};
+
+template <typename T>
+__device__ __forceinline__ void bottom_half_sweep(T* __restrict__ x, const T* __restrict__ b, const FaceCoef<T>& co,
+                                                  const Geom& g, int colour, bool from_zero) {
+  const int n = g.nx * g.ny * g.nz;
+  for (int c = threadIdx.x; c < n; c += BOTTOM_THREADS) {
+    const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    if (((i + j + k) & 1) != colour) {
+      if (from_zero) x[c] = T(0);
+      continue;
+    }
+    const Stencil<T> st = co.load(g, i, j, k, c);
+    T off = T(0);
+    if (!from_zero) {
+      const Nbrs<T> v = load_nbrs<T>(x, g, i, j, k, c, T(0), T(0));
+      off = st.ww * v.w + st.we * v.e + st.ws * v.s + st.wn * v.n;
+      if (k > 0) off += st.wb * v.b;
+      if (k < g.nz - 1) off += st.wt * v.t;
+    }
+    x[c] = (b[c] + off) / diag_cell(st, g, k);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BOTTOM_THREADS) void k_vcycle_bottom(BottomArgs<T> A) {
+  const int L = A.nlev - 1;  // index of the coarsest level
+  for (int l = 0; l < L; ++l) {
+    const Geom& g = A.g[l];
+    bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 0, true);  // red from x = 0 (black set to 0)
+    if (A.nu_pre == 0) {
+      __syncthreads();
+      const int n = g.nx * g.ny * g.nz;
+      for (int c = threadIdx.x; c < n; c += BOTTOM_THREADS) A.x[l][c] = T(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < A.nu_pre; ++it) {
+      if (it > 0) {
+        bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 0, false);
+        __syncthreads();
+      }
+      bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 1, false);
+      __syncthreads();
+    }
+    // residual and restriction into b of level l+1
+    const Geom& gc = A.g[l + 1];
+    const int nc = gc.nx * gc.ny * gc.nz;
+    for (int C = threadIdx.x; C < nc; C += BOTTOM_THREADS) {
+      const int I = C % gc.nx, J = (C / gc.nx) % gc.ny, K = C / (gc.nx * gc.ny);
+      T sum = T(0);
+      for (int d = 0; d < 8; ++d) {
+        const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
+        const size_t c = cidx(g, i, j, k);
+        const Stencil<T> st = A.co[l].load(g, i, j, k, c);
+        const Nbrs<T> v = load_nbrs<T>(A.x[l], g, i, j, k, c, T(0), T(0));
+        sum += A.b[l][c] - apply_cell(st, v);
+      }
+      A.b[l + 1][C] = sum * T(0.125);
+    }
+    __syncthreads();
+  }
+  // coarsest: x = A_L^{-1} b
+  {
+    const Geom& g = A.g[L];
+    const int n = g.nx * g.ny * g.nz;
+    for (int r = threadIdx.x; r < n; r += BOTTOM_THREADS) {
+      T acc = T(0);
+      for (int c = 0; c < n; ++c) acc += A.Ainv[(size_t)c * n + r] * A.b[L][c];
+      A.x[L][r] = acc;
+    }
+    __syncthreads();
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const Geom& g = A.g[l];
+    const int n = g.nx * g.ny * g.nz;
+    const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+    const T* xc = A.x[l + 1];
+    for (int c = threadIdx.x; c < n; c += BOTTOM_THREADS) {
+      const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+      const int I = i >> 1, J = j >> 1, K = k >> 1;
+      int I2 = I + ((i & 1) ? 1 : -1);
+      if (I2 < 0 || I2 >= NX) I2 = I;
+      int J2 = J + ((j & 1) ? 1 : -1);
+      if (J2 < 0 || J2 >= NY) J2 = J;
+      int K2 = K + ((k & 1) ? 1 : -1);
+      T sk = T(1);
+      if (K2 < 0 || K2 >= NZ) {
+        K2 = K;
+        sk = T(-1);
+      }
+      const T q3 = T(0.75), q1 = T(0.25);
+      const T* p = xc + (size_t)K * NY * NX;
+      const T* q = xc + (size_t)K2 * NY * NX;
+      const T pl = q3 * (q3 * p[J * NX + I] + q1 * p[J * NX + I2]) + q1 * (q3 * p[J2 * NX + I] + q1 * p[J2 * NX + I2]);
+      const T ql = q3 * (q3 * q[J * NX + I] + q1 * q[J * NX + I2]) + q1 * (q3 * q[J2 * NX + I] + q1 * q[J2 * NX + I2]);
+      A.x[l][c] += q3 * pl + q1 * sk * ql;
+    }
+    __syncthreads();
+    for (int it = 0; it < A.nu_post; ++it) {
+      bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 1, false);
+      __syncthreads();
+      bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 0, false);
+      __syncthreads();
+    }
   }
 }
 
@@ -350,16 +699,17 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_cell(const T* __res
                                                                   const double* __restrict__ bscale,
                                                                   const T* __restrict__ a, Geom g,
                                                                   T* __restrict__ bc, int kc) {
+  const Tile tl = xcd_tile();
   __shared__ T part[BY][BX];
   const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
-  const int I = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
+  const int I = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
   const bool act = I < NX && j < g.ny;
   const int i0 = 2 * I;
   const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
   const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
   const T s = (T)(bscale ? *bscale : 1.0);
-  const int K0 = blockIdx.z * kc, K1 = min(NZ, K0 + kc);
+  const int K0 = tl.z * kc, K1 = min(NZ, K0 + kc);
   const int k0 = 2 * K0, k1 = 2 * K1;
   // column registers: [0] cell i0, [1] cell i0+1, planes below / centre / above
   T xb[2] = {T(0), T(0)}, xc[2] = {T(0), T(0)}, xt[2], ab[2] = {T(0), T(0)}, ac[2] = {T(0), T(0)}, at[2];
@@ -446,15 +796,16 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_cell(const T* __res
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_prolong_add(T* __restrict__ x, const T* __restrict__ xc, Geom g,
                                                           int kc) {
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * BX + threadIdx.x;
   if (i >= g.nx) return;
   const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
   const int I = i >> 1;
   int I2 = I + ((i & 1) ? 1 : -1);
   if (I2 < 0 || I2 >= NX) I2 = I;
   const T q3 = T(0.75), q1 = T(0.25);
-  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
     const int J = j >> 1;
     int J2 = J + ((j & 1) ? 1 : -1);
     if (J2 < 0 || J2 >= NY) J2 = J;
@@ -485,17 +836,18 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_add(T* __restrict__ x, con
 // b * (*bscale).
 template <typename T, typename TB, int XM, int TY, bool SCALED>
 __global__ __launch_bounds__(NTHREADS) void k_sym_sweep(SweepArgs<T, TB> A) {
+  const Tile tl = xcd_tile();
   constexpr int NPT = (SweepTile<TY>::P + NTHREADS - 1) / NTHREADS;
   __shared__ SweepSmem<T, TY> s;
   SweepPlan<NPT, XM> P;
   SweepPhasePlan<TY> Q;
   SweepFetch<T, XM, NPT> R;
   const int tid = threadIdx.y * BX + threadIdx.x;
-  const int k0 = blockIdx.z * A.kc, k1 = min(A.g.nz, k0 + A.kc);
+  const int k0 = tl.z * A.kc, k1 = min(A.g.nz, k0 + A.kc);
   const double bsc = SCALED ? *A.bscale : 1.0;
   const bool store_b = A.b_out != nullptr;
-  sweep_plan<TY, NPT, XM>(P, A.g, blockIdx.x, blockIdx.y, tid, NTHREADS);
-  sweep_phase_plan<TY>(Q, A.g, A.c1, blockIdx.x, blockIdx.y, tid);
+  sweep_plan<TY, NPT, XM>(P, A.g, tl.x, tl.y, tid, NTHREADS);
+  sweep_phase_plan<TY>(Q, A.g, A.c1, tl.x, tl.y, tid);
   SweepStep nx = sweep_step(A.g, k0, k1, k0 - 3);
   sweep_fetch<T, TB, XM, NPT, SCALED>(R, P, A, nx.pxa, nx.load_xa, nx.pb, nx.load_b, nx.store_b && store_b, bsc);
   for (int t = k0 - 3; t <= k1; ++t) {
@@ -538,12 +890,13 @@ __global__ __launch_bounds__(NTHREADS) void k_init_residual(const double* __rest
                                                             const double* __restrict__ x0, Geom g, double pb,
                                                             double pt, double* __restrict__ r_out,
                                                             double* __restrict__ partials, int kc) {
+  const Tile tl = xcd_tile();
   double acc[2] = {0.0, 0.0};
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const int i = tl.x * BX + threadIdx.x;
   const CellCoef<double> co{a};
   if (i < g.nx) {
-    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+    for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
       for (int k = k0; k < k1; ++k) {
         const size_t c = cidx(g, i, j, k);
         const double ac = a[c];
@@ -578,15 +931,16 @@ __global__ __launch_bounds__(NTHREADS) void k_op_multidot(const TZ* __restrict__
                                                           Geom g, double* __restrict__ w,
                                                           const double* __restrict__ U, size_t stride,
                                                           double* __restrict__ partials, int kc) {
+  const Tile tl = xcd_tile();
   double acc[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const int i = tl.x * BX + threadIdx.x;
   if (i < g.nx) {
     const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
     const double hx = 0.5 * g.ihx2, hy = 0.5 * g.ihy2, hz = 0.5 * g.ihz2, pz = 2.0 * g.ihz2;
-    const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-    for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+    for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
       size_t c = cidx(g, i, j, k0);
       double zc = (double)z[c], ac = a[c];
       double zb = k0 > 0 ? (double)z[c - sz] : 0.0;
@@ -702,11 +1056,12 @@ __global__ __launch_bounds__(NTHREADS) void k_finalize(const double* __restrict_
 __global__ __launch_bounds__(NTHREADS) void k_apply_bc(const double* __restrict__ x, const double* __restrict__ a,
                                                        Geom g, double pb, double pt, double* __restrict__ y,
                                                        int kc) {
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * BX + threadIdx.x;
   if (i >= g.nx) return;
   const CellCoef<double> co{a};
-  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
     for (int k = k0; k < k1; ++k) {
       const size_t c = cidx(g, i, j, k);
       const Stencil<double> st = co.load(g, i, j, k, c);
@@ -720,11 +1075,12 @@ __global__ __launch_bounds__(NTHREADS) void k_apply_bc(const double* __restrict_
 __global__ __launch_bounds__(NTHREADS) void k_face_grad(const double* __restrict__ phi,
                                                         const double* __restrict__ lam, Geom g, double pb,
                                                         double pt, double* __restrict__ out, int kc) {
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * BX + threadIdx.x;
   if (i >= g.nx) return;
   const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
-  const int k0 = blockIdx.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int j = blockIdx.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
     for (int k = k0; k < k1; ++k) {
       const size_t c = cidx(g, i, j, k);
       const double pc = phi[c], lc = lam[c];

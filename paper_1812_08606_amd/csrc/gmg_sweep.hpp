@@ -32,7 +32,7 @@
 
 namespace gmg {
 
-enum SweepX { SWEEP_X_ZERO = 0, SWEEP_X_LOAD = 1, SWEEP_X_PROLONG = 2 };
+enum SweepX { SWEEP_X_ZERO = 0, SWEEP_X_LOAD = 1 };
 
 template <int TY_>
 struct SweepTile {
@@ -55,8 +55,7 @@ struct SweepSmem {
 
 template <typename T, typename TB>
 struct SweepArgs {
-  const T* x_in;         // old iterate (SWEEP_X_LOAD, SWEEP_X_PROLONG)
-  const T* xc;           // coarse correction added by trilinear prolongation (SWEEP_X_PROLONG)
+  const T* x_in;         // old iterate (SWEEP_X_LOAD)
   const TB* b;           // right side, read as b * (*bscale)
   const double* bscale;  // null = 1
   T* b_out;              // when given, b (in T) is stored for the tile's cells
@@ -90,7 +89,6 @@ struct SweepPlan {
   int off[NPT];   // in-plane offset y * nx + x, -1 outside the grid or the region
   int lds[NPT];   // LDS index
   unsigned tile;  // bit e: a tile cell (its b is stored to b_out)
-  int coff[XM == SWEEP_X_PROLONG ? NPT : 1][4];  // coarse in-plane offsets (J,I) (J,I2) (J2,I) (J2,I2)
 };
 
 template <int TY, int NPT, int XM>
@@ -108,19 +106,6 @@ __device__ __forceinline__ void sweep_plan(SweepPlan<NPT, XM>& P, const Geom& g,
     P.off[e] = in ? y * g.nx + x : -1;
     P.lds[e] = pos < Tl::P ? sweep_lidx<TY>(r, q) : 0;
     if (in && r >= 2 && r < TY + 2 && q >= 2 && q < Tl::TX + 2) P.tile |= 1u << e;
-    if (XM == SWEEP_X_PROLONG) {
-      const int k = XM == SWEEP_X_PROLONG ? e : 0;
-      const int NX = g.nx >> 1, NY = g.ny >> 1;
-      const int I = x >> 1, J = y >> 1;
-      int I2 = I + ((x & 1) ? 1 : -1);
-      if (I2 < 0 || I2 >= NX) I2 = I;
-      int J2 = J + ((y & 1) ? 1 : -1);
-      if (J2 < 0 || J2 >= NY) J2 = J;
-      P.coff[k][0] = in ? J * NX + I : 0;
-      P.coff[k][1] = in ? J * NX + I2 : 0;
-      P.coff[k][2] = in ? J2 * NX + I : 0;
-      P.coff[k][3] = in ? J2 * NX + I2 : 0;
-    }
   }
 }
 
@@ -128,11 +113,9 @@ __device__ __forceinline__ void sweep_plan(SweepPlan<NPT, XM>& P, const Geom& g,
 // fetched one step ahead into registers, stored into LDS at the next step).
 template <typename T, int XM, int NPT>
 struct SweepFetch {
-  T xv[NPT];                                 // x_old (or x_in before the correction)
-  T av[NPT];                                 // coefficient
-  T bv[NPT];                                 // right side
-  T pc[XM == SWEEP_X_PROLONG ? NPT : 1][8];  // coarse values of the trilinear stencil
-  T sk;                                      // -1 where the stencil reaches through a plate
+  T xv[XM == SWEEP_X_LOAD ? NPT : 1];  // x_old
+  T av[NPT];                           // coefficient
+  T bv[NPT];                           // right side
 };
 
 // Fetch phase: x_old and a of plane pxa (if load_xa) and b of plane pb (if
@@ -148,35 +131,13 @@ __device__ __forceinline__ void sweep_fetch(SweepFetch<T, XM, NPT>& R, const Swe
   const T* xp = XM != SWEEP_X_ZERO ? A.x_in + (size_t)(load_xa ? pxa : 0) * nxy : nullptr;
   const TB* bp = A.b + (size_t)(load_b ? pb : 0) * nxy;
   T* bo = store_b ? A.b_out + (size_t)pb * nxy : nullptr;
-  const T* c0 = nullptr;
-  const T* c1 = nullptr;
-  R.sk = T(1);
-  if (XM == SWEEP_X_PROLONG && load_xa) {
-    const int NXY = (g.nx >> 1) * (g.ny >> 1), NZ = g.nz >> 1;
-    const int K = pxa >> 1;
-    int K2 = K + ((pxa & 1) ? 1 : -1);
-    if (K2 < 0 || K2 >= NZ) {
-      K2 = K;
-      R.sk = T(-1);
-    }
-    c0 = A.xc + (size_t)K * NXY;
-    c1 = A.xc + (size_t)K2 * NXY;
-  }
 #pragma unroll
   for (int e = 0; e < NPT; ++e) {
     const int o = P.off[e];
     const bool in = o >= 0;
     if (load_xa) {
       R.av[e] = in ? ap[o] : T(0);
-      if (XM != SWEEP_X_ZERO) R.xv[e] = in ? xp[o] : T(0);
-      if (XM == SWEEP_X_PROLONG) {
-        const int k = XM == SWEEP_X_PROLONG ? e : 0;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          R.pc[k][d] = in ? c0[P.coff[k][d]] : T(0);
-          R.pc[k][4 + d] = in ? c1[P.coff[k][d]] : T(0);
-        }
-      }
+      if (XM == SWEEP_X_LOAD) R.xv[XM == SWEEP_X_LOAD ? e : 0] = in ? xp[o] : T(0);
     }
     if (load_b) {
       T bv = T(0);
@@ -187,9 +148,7 @@ __device__ __forceinline__ void sweep_fetch(SweepFetch<T, XM, NPT>& R, const Swe
   }
 }
 
-// Stash phase: the fetched values into the LDS ring slots of their planes;
-// the trilinear correction (3/4 parent, 1/4 neighbour per dimension, as in
-// k_prolong_add) is added here.
+// Stash phase: the fetched values into the LDS ring slots of their planes.
 template <typename T, int XM, int TY, int NPT>
 __device__ __forceinline__ void sweep_stash(SweepSmem<T, TY>& s, const SweepFetch<T, XM, NPT>& R,
                                             const SweepPlan<NPT, XM>& P, int tid, int nthreads, int pxa,
@@ -203,14 +162,7 @@ __device__ __forceinline__ void sweep_stash(SweepSmem<T, TY>& s, const SweepFetc
     if (tid + e * nthreads >= Tl::P) continue;
     const int l = P.lds[e];
     if (load_xa) {
-      if (XM == SWEEP_X_LOAD) xo[l] = R.xv[e];
-      if (XM == SWEEP_X_PROLONG) {
-        const int k = XM == SWEEP_X_PROLONG ? e : 0;
-        const T q3 = T(0.75), q1 = T(0.25);
-        const T pl = q3 * (q3 * R.pc[k][0] + q1 * R.pc[k][1]) + q1 * (q3 * R.pc[k][2] + q1 * R.pc[k][3]);
-        const T ql = q3 * (q3 * R.pc[k][4] + q1 * R.pc[k][5]) + q1 * (q3 * R.pc[k][6] + q1 * R.pc[k][7]);
-        xo[l] = R.xv[e] + (q3 * pl + q1 * R.sk * ql);
-      }
+      if (XM == SWEEP_X_LOAD) xo[l] = R.xv[XM == SWEEP_X_LOAD ? e : 0];
       av[l] = R.av[e];
     }
     if (load_b) bv[l] = R.bv[e];
