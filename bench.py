@@ -45,8 +45,6 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128, help="edge of the CPU-oracle sample grid")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
-    ap.add_argument("--fine-sweep", type=int, default=0,
-                    help="finest-level smoother kernels: 0 default, 1 fused sweeps, 2 half-sweeps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for hardware-counter scaling)")
     return ap.parse_args()
@@ -126,7 +124,7 @@ def main():
         return ((gx ** 2 + gy ** 2 + gz ** 2) * h ** 3).sum()
 
     def run(precision):
-        solver = gm.GMGPoisson(a, precision=precision, fine_sweep=args.fine_sweep)
+        solver = gm.GMGPoisson(a, precision=precision)
         phi = torch.empty_like(a)
         lam = torch.empty_like(a)
         grad = torch.empty_like(a)

@@ -72,10 +72,7 @@ typedef struct gmg_options {
                            (coefficients, smoother, transfers, coarse solve) in
                            float32, FGMRES in float64 (default GMG_MIXED)       */
   int coarse_max_cells; /* largest coarsest level solved directly (default 4096) */
-  int fine_sweep;       /* kernels of the finest-level smoother: 0 default, 1 one
-                           fused kernel per symmetric (red+black) sweep, 2 one
-                           kernel per half-sweep; the arithmetic is the same */
-  int reserved[3];      /* must be zero */
+  int reserved[4];      /* must be zero */
 } gmg_options;
 
 void gmg_default_options(gmg_options* opt);

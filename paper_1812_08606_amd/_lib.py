@@ -18,8 +18,7 @@ class Options(ctypes.Structure):
         ("nu_post", c_int),
         ("precision", c_int),
         ("coarse_max_cells", c_int),
-        ("fine_sweep", c_int),
-        ("reserved", c_int * 3),
+        ("reserved", c_int * 4),
     ]
 
 

@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "gmg.h"
-#include "gmg_kernels.hpp"
+#include "gmg_fine.hpp"
 
 using namespace gmg;
 
@@ -57,9 +57,10 @@ struct LevelOffsets {
 struct Layout {
   std::vector<LevelShape> shapes;
   std::vector<LevelOffsets> lv;
-  size_t V, Z, a32, b0, xs, partials, scal, cinv, total;
+  size_t V, Z, a32, b0, partials, scal, cinv, total;
   size_t tsize;  // bytes of the V-cycle precision
   size_t ldv;    // elements between consecutive Krylov vectors (v_i and z_i)
+  size_t hn;     // elements of one colour array of a colour-split finest-level field
   int m;
 };
 
@@ -70,7 +71,6 @@ bool options_valid(const gmg_options* o) {
   if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8) return false;
   if (o->precision != GMG_FP64 && o->precision != GMG_MIXED) return false;
   if (o->coarse_max_cells < 1 || o->coarse_max_cells > 4096) return false;
-  if (o->fine_sweep < 0 || o->fine_sweep > 2) return false;
   for (int r : o->reserved)
     if (r) return false;
   return true;
@@ -95,15 +95,16 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
     off = align_up(off + bytes);
     return at;
   };
-  L->ldv = (N + 63) / 64 * 64;  // every Krylov vector starts 512-byte aligned
+  // every Krylov vector, and each colour half of a colour-split one, starts
+  // 512-byte aligned
+  L->hn = ((N + 1) / 2 + 63) / 64 * 64;
+  L->ldv = 2 * L->hn;
   L->V = take((size_t)(L->m + 1) * L->ldv * 8);
   L->Z = take((size_t)L->m * L->ldv * L->tsize);
   L->a32 = mixed ? take(N * 4) : 0;
-  // finest-level right side in T: the float32 copy of v_j (mixed) or, when
-  // the finest level is also the coarsest, the scaled right side
-  L->b0 = (mixed || nl == 1) ? take(N * L->tsize) : 0;
-  // second finest-level iterate for the ping-pong fused sweeps
-  L->xs = nl > 1 ? take(N * L->tsize) : 0;
+  // finest-level right side in T (colour-split; natural when the finest
+  // level is also the coarsest)
+  L->b0 = take(L->ldv * L->tsize);
   L->lv.assign(nl, LevelOffsets{});
   for (int l = 1; l < nl; ++l) {
     const LevelShape& s = L->shapes[l];
@@ -462,15 +463,6 @@ Launch pair_launch(int nx, int ny, int nz, long long target, int min_kc) {
   return Launch{dim3(gx, gy, (nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
 }
 
-// Finest level: the z-marching residual/restriction kernel.
-template <typename T, typename TB>
-void resid_restrict_fine(gmg_ctx* c, const T* x, const TB* b, const double* bscale, const T* a, T* bc) {
-  const LevelShape& s = c->L.shapes[0];
-  const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
-  GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), (k_resid_restrict_cell<T, TB>), l, x, b, bscale, a, s.geom(),
-             bc, l.kc);
-}
-
 // Coarse level l (not the coarsest, so every dimension is even): red-black
 // smoothing, residual and restriction with the lane-pair kernels on the
 // stored face coefficients.
@@ -569,122 +561,60 @@ void vcycle_coarse(gmg_ctx* c, int l) {
   smooth_post_face<T>(c, l, x, b, co);
 }
 
-// Finest-level smoother kernels: option fine_sweep, 0 selects the faster
-// (one kernel per half-sweep, as measured on MI355X).
-int fine_sweep_kind(const gmg_ctx* c) { return c->opt.fine_sweep == 0 ? 2 : c->opt.fine_sweep; }
-
-// Tile height of the fused sweep (LDS: 12 planes of 68 x (TY + 4) values).
-template <typename T>
-struct SweepTY {
-  static constexpr int value = sizeof(T) == 4 ? 8 : 4;
-};
-
-template <typename T, typename TB, int XM>
-void sym_sweep(gmg_ctx* c, const T* x_in, const TB* b, const double* bscale, T* b_out, const T* a,
-               T* x_out, int c1) {
-  constexpr int TY = SweepTY<T>::value;
-  const LevelShape& s = c->L.shapes[0];
-  const int gx = (s.nx + 63) / 64, gy = (s.ny + TY - 1) / TY;
-  const long long tiles = (long long)gx * gy;
-  int kc = (int)std::max<long long>(8, (s.nz * tiles + 4095) / 4096);
-  kc = std::min(kc, s.nz);
-  const int gz = (s.nz + kc - 1) / kc;
-  const Launch l{dim3(gx, std::min(gy, 65535), gz), dim3(BX, BY, 1), kc};
-  SweepArgs<T, TB> A{x_in, b, bscale, b_out, a, x_out, s.geom(), c1, kc};
-  const char* nm = XM == SWEEP_X_ZERO ? "sym_sweep_zero" : "sym_sweep";
-  if (bscale)
-    GMG_LAUNCH(c, kname(nm, 0, sizeof(T)), (k_sym_sweep<T, TB, XM, TY, true>), l, A);
-  else
-    GMG_LAUNCH(c, kname(nm, 0, sizeof(T)), (k_sym_sweep<T, TB, XM, TY, false>), l, A);
-}
-
-// Finest level with the fused sweeps (nu_pre, nu_post >= 1, at least two
-// levels): pre-sweeps ping-pong between the scratch iterate and z so that
-// the last post-sweep lands in z.
-template <typename T>
-void vcycle_fine_fused(gmg_ctx* c, const double* u, const double* bscale, T* z) {
-  const int npre = c->opt.nu_pre, npost = c->opt.nu_post, L = npre + npost;
-  T* xs = wsp<T>(c, c->L.xs);
-  auto buf = [&](int p) { return ((L - p) % 2 == 0) ? z : xs; };  // buffer written by pass p (1-based)
-  const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
-  T* b0 = c->mixed ? wsp<T>(c, c->L.b0) : nullptr;
-  T* bc = wsp<T>(c, c->L.lv[1].b);
-  // pre-smoothing: red then black, from x = 0
-  sym_sweep<T, double, SWEEP_X_ZERO>(c, nullptr, u, bscale, b0, a, buf(1), 0);
-  for (int p = 2; p <= npre; ++p) {
-    if (c->mixed)
-      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), (const T*)b0, nullptr, nullptr, a, buf(p), 0);
-    else
-      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), u, bscale, nullptr, a, buf(p), 0);
-  }
-  if (c->mixed)
-    resid_restrict_fine<T, T>(c, buf(npre), (const T*)b0, nullptr, a, bc);
-  else
-    resid_restrict_fine<T, double>(c, buf(npre), u, bscale, a, bc);
-  vcycle_coarse<T>(c, 1);
-  // coarse correction, then post-smoothing: black then red
-  prolong_add<T>(c, 0, buf(npre), wsp<T>(c, c->L.lv[1].x));
-  for (int p = npre + 1; p <= L; ++p) {
-    if (c->mixed)
-      sym_sweep<T, T, SWEEP_X_LOAD>(c, buf(p - 1), (const T*)b0, nullptr, nullptr, a, buf(p), 1);
-    else
-      sym_sweep<T, double, SWEEP_X_LOAD>(c, buf(p - 1), u, bscale, nullptr, a, buf(p), 1);
-  }
-}
-
-template <typename T, typename TB, bool FIRST>
-void gs_pair(gmg_ctx* c, T* x, const TB* b, const double* bscale, T* b_out, const T* a, int colour) {
+// Finest level on colour-split storage (at least two levels, so every
+// dimension is even).  X and B are colour-split (colour c at offset c * hn).
+template <typename T, bool FIRST>
+void gs_split(gmg_ctx* c, T* X, T* B, const double* u, const double* bscale, const T* a, int colour) {
   const LevelShape& s = c->L.shapes[0];
   const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
   const char* nm = kname(FIRST ? "gs_first" : "gs", 0, sizeof(T));
-  if (bscale)
-    GMG_LAUNCH(c, nm, (k_gs_pair<T, TB, true, FIRST>), l, x, b, bscale, b_out, a, s.geom(), l.kc, colour);
+  if (FIRST && bscale)
+    GMG_LAUNCH(c, nm, (k_gs_split<T, FIRST, true>), l, X, B, u, bscale, a, s.geom(), c->L.hn, l.kc, colour);
   else
-    GMG_LAUNCH(c, nm, (k_gs_pair<T, TB, false, FIRST>), l, x, b, bscale, b_out, a, s.geom(), l.kc, colour);
+    GMG_LAUNCH(c, nm, (k_gs_split<T, FIRST, false>), l, X, B, u, bscale, a, s.geom(), c->L.hn, l.kc, colour);
 }
 
-// Finest level with one kernel per half-sweep (at least two levels, so the
-// dimensions are even): pre-smoothing red, black (nu_pre times) from x = 0,
-// the first red half-sweep writing the float32 copy of v_j; residual and
-// restriction; coarse correction; post-smoothing black, red (nu_post times).
+// z = M (s * u), z colour-split: pre-smoothing red, black (nu_pre times)
+// from x = 0, the first red half-sweep writing the right side B; residual
+// and restriction; coarse correction (added to the red cells only when a
+// black half-sweep follows, which overwrites the black cells without reading
+// them); post-smoothing black, red (nu_post times).
 template <typename T>
-void vcycle_fine_half(gmg_ctx* c, const double* u, const double* bscale, T* z) {
+void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X) {
   const LevelShape& s = c->L.shapes[0];
   const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
-  T* b0 = c->mixed ? wsp<T>(c, c->L.b0) : nullptr;
-  T* bc = wsp<T>(c, c->L.lv[1].b);
+  T* B = wsp<T>(c, c->L.b0);
+  const size_t hn = c->L.hn;
   const int npre = c->opt.nu_pre, npost = c->opt.nu_post;
-  if (npre > 0) {
-    gs_pair<T, double, true>(c, z, u, bscale, b0, a, 0);
-  } else {
-    const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
-    GMG_LAUNCH(c, kname("gs_first", 0, sizeof(T)), (k_gs_first<T, double, CellCoef<T>>), lc, z, u, bscale, b0,
-               CellCoef<T>{a}, s.geom(), lc.kc, 0);
+  gs_split<T, true>(c, X, B, u, bscale, a, 0);
+  if (npre == 0) {  // no pre-smoothing: x = 0 (B is kept)
+    const Launch fl = flat_launch(2 * hn);
+    GMG_LAUNCH(c, kname("fill", 0, sizeof(T)), k_fill<T>, fl, X, T(0), 2 * hn);
   }
-  auto half = [&](int colour) {
-    if (c->mixed)
-      gs_pair<T, T, false>(c, z, (const T*)b0, nullptr, nullptr, a, colour);
-    else
-      gs_pair<T, double, false>(c, z, u, bscale, nullptr, a, colour);
-  };
   for (int it = 0; it < npre; ++it) {
-    if (it > 0) half(0);
-    half(1);
+    if (it > 0) gs_split<T, false>(c, X, B, nullptr, nullptr, a, 0);
+    gs_split<T, false>(c, X, B, nullptr, nullptr, a, 1);
   }
-  if (c->mixed)
-    resid_restrict_fine<T, T>(c, z, (const T*)b0, nullptr, a, bc);
-  else
-    resid_restrict_fine<T, double>(c, z, u, bscale, a, bc);
+  {
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), k_resid_restrict_split<T>, l, (const T*)X, (const T*)B, a,
+               s.geom(), hn, wsp<T>(c, c->L.lv[1].b), l.kc);
+  }
   vcycle_coarse<T>(c, 1);
-  prolong_add<T>(c, 0, z, wsp<T>(c, c->L.lv[1].x));
+  {
+    const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+    GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), k_prolong_split<T>, l, X, (const T*)wsp<T>(c, c->L.lv[1].x),
+               s.geom(), hn, npost > 0 ? 1 : 2, l.kc);
+  }
   for (int it = 0; it < npost; ++it) {
-    half(1);
-    half(0);
+    gs_split<T, false>(c, X, B, nullptr, nullptr, a, 1);
+    gs_split<T, false>(c, X, B, nullptr, nullptr, a, 0);
   }
 }
 
-// z = M (s * u): one V-cycle on the finest level with right side u scaled by
-// *bscale (null = 1); z in the V-cycle precision.
+// z = M (s * u) on the finest level with right side u scaled by *bscale
+// (null = 1); z in the V-cycle precision, colour-split when there are at
+// least two levels, in the natural layout otherwise.
 template <typename T>
 void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
   const int nl = (int)c->L.shapes.size();
@@ -703,10 +633,7 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     coarse_solve<T>(c, b0, z);
     return;
   }
-  if (fine_sweep_kind(c) == 1 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1)
-    vcycle_fine_fused<T>(c, u, bscale, z);
-  else
-    vcycle_fine_half<T>(c, u, bscale, z);
+  vcycle_fine_split<T>(c, u, bscale, z);
 }
 
 void vcycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z) {
@@ -723,7 +650,7 @@ void vcycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z) {
 Launch red_launch(gmg_ctx* c) { return col_launch(c->nx, c->ny, c->nz, MAX_RED_BLOCKS); }
 
 void finalize(gmg_ctx* c, int nblocks, int nv, int mode, double* out, const double* scale, double* out2) {
-  const Launch one{dim3(1), dim3(BX, BY, 1), 0};
+  const Launch one{dim3(1), dim3(FIN_THREADS, 1, 1), 0};
   GMG_LAUNCH(c, "finalize", k_finalize, one, wsp<const double>(c, c->L.partials), nblocks, nv, mode, out, scale,
              out2);
 }
@@ -737,7 +664,7 @@ void init_residual(gmg_ctx* c, const double* f, const double* x, double pb, doub
              store ? wsp<double>(c, c->L.V) : (double*)nullptr, wsp<double>(c, c->L.partials), rl.kc);
   finalize(c, rl.nblocks(), 2, 0, misc, nullptr, nullptr);
   // misc[2] = ||r0||, vscale[0] = 1/||r0||
-  const Launch one{dim3(1), dim3(BX, BY, 1), 0};
+  const Launch one{dim3(1), dim3(FIN_THREADS, 1, 1), 0};
   GMG_LAUNCH(c, "finalize", k_finalize, one, wsp<const double>(c, c->L.partials) + rl.nblocks(), rl.nblocks(), 1,
              2, misc + 2, nullptr, scal_vscale(c));
 }
@@ -748,10 +675,29 @@ Launch red_flat(gmg_ctx* c) {
   return Launch{dim3((unsigned)std::max<size_t>(b, 1)), dim3(BX, BY, 1), 0};
 }
 
+// Launch of the operator + multi-dot pass: lane pairs on colour-split z
+// (at least two levels), one cell per thread otherwise; at most
+// MAX_RED_BLOCKS blocks (one partial per block and vector).
+Launch opdot_launch(gmg_ctx* c) {
+  const LevelShape& s = c->L.shapes[0];
+  if (c->L.shapes.size() == 1) return red_launch(c);
+  const int gx = (s.nx / 2 + BX - 1) / BX;
+  int gy = (s.ny + BY - 1) / BY;
+  if ((long long)gx * gy > MAX_RED_BLOCKS) gy = std::max(1, MAX_RED_BLOCKS / gx);  // rows strided
+  const int gz = std::max(1, std::min(s.nz, MAX_RED_BLOCKS / (gx * gy)));
+  const int kc = (s.nz + gz - 1) / gz;
+  return Launch{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
+}
+
 template <typename TZ, int NV>
 void launch_opdot(gmg_ctx* c, const Launch& rl, const TZ* z, double* w, const double* V) {
-  GMG_LAUNCH(c, sizeof(TZ) == 4 ? "op_multidot_zf32" : "op_multidot_zf64", (k_op_multidot<TZ, NV>), rl, z, c->a,
-             c->L.shapes[0].geom(), w, V, c->L.ldv, wsp<double>(c, c->L.partials), rl.kc);
+  const char* nm = sizeof(TZ) == 4 ? "op_multidot_zf32" : "op_multidot_zf64";
+  if (c->L.shapes.size() > 1)
+    GMG_LAUNCH(c, nm, (k_op_multidot_split<TZ, NV>), rl, z, c->L.hn, c->a, c->L.shapes[0].geom(), w, V, c->L.ldv,
+               wsp<double>(c, c->L.partials), rl.kc);
+  else
+    GMG_LAUNCH(c, nm, (k_op_multidot<TZ, NV>), rl, z, c->a, c->L.shapes[0].geom(), w, V, c->L.ldv,
+               wsp<double>(c, c->L.partials), rl.kc);
 }
 template <int NV>
 void launch_dot(gmg_ctx* c, const Launch& rl, const double* w, const double* V) {
@@ -764,7 +710,14 @@ void launch_axpy(gmg_ctx* c, const Launch& rl, double* w, const double* V, const
 }
 template <typename TZ, int NV>
 void launch_update(gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y) {
-  GMG_LAUNCH(c, sizeof(TZ) == 4 ? "update_zf32" : "update_zf64", (k_update<TZ, NV>), rl, phi, c->N, Z, c->L.ldv, y);
+  const char* nm = sizeof(TZ) == 4 ? "update_zf32" : "update_zf64";
+  if (c->L.shapes.size() > 1) {
+    const LevelShape& s = c->L.shapes[0];
+    const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+    GMG_LAUNCH(c, nm, (k_update_split<TZ, NV>), l, phi, Z, c->L.hn, c->L.ldv, y, s.geom(), l.kc);
+  } else {
+    GMG_LAUNCH(c, nm, (k_update<TZ, NV>), rl, phi, c->N, Z, c->L.ldv, y);
+  }
 }
 
 template <typename TZ, size_t... I>
@@ -804,7 +757,7 @@ void arnoldi_step(gmg_ctx* c, int j) {
   double* vs = scal_vscale(c);
   double* hc = scal_hcol(c, j);
   vcycle_any(c, V + (size_t)j * N, vs + j, Zb);
-  const Launch rl = red_launch(c);
+  const Launch rl = opdot_launch(c);
   const Launch fl = red_flat(c);
   double* w = V + (size_t)(j + 1) * N;
   const int nv = j + 1;
@@ -1043,11 +996,27 @@ int gmg_apply_operator(gmg_ctx* c, const double* x_dev, double* y_dev, double ph
 
 int gmg_vcycle(gmg_ctx* c, const double* v_dev, double* z_dev) {
   if (!valid_ctx(c) || !v_dev || !z_dev) return GMG_ERR_ARG;
+  const bool split = c->L.shapes.size() > 1;
   if (c->mixed) {
     float* z32 = wsp<float>(c, c->L.Z);
     vcycle_fine<float>(c, v_dev, nullptr, z32);
     const Launch fl = flat_launch(c->N);
-    GMG_LAUNCH(c, "convert_f32_f64", (k_convert<double, float>), fl, (const float*)z32, z_dev, c->N);
+    if (split) {  // z = 0 + 1 * z32, exact, into the natural layout
+      GMG_LAUNCH(c, "fill", k_fill<double>, fl, z_dev, 0.0, c->N);
+      Coeffs16 one{};
+      one.v[0] = 1.0;
+      launch_update<float, 1>(c, fl, z_dev, z32, one);
+    } else {
+      GMG_LAUNCH(c, "convert_f32_f64", (k_convert<double, float>), fl, (const float*)z32, z_dev, c->N);
+    }
+  } else if (split) {
+    double* z64 = wsp<double>(c, c->L.Z);
+    vcycle_fine<double>(c, v_dev, nullptr, z64);
+    const Launch fl = flat_launch(c->N);
+    GMG_LAUNCH(c, "fill", k_fill<double>, fl, z_dev, 0.0, c->N);
+    Coeffs16 one{};
+    one.v[0] = 1.0;
+    launch_update<double, 1>(c, fl, z_dev, z64, one);
   } else {
     vcycle_fine<double>(c, v_dev, nullptr, z_dev);
   }

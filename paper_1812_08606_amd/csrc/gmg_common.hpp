@@ -8,7 +8,7 @@ constexpr int BY = 4;
 constexpr int NTHREADS = BX * BY;
 constexpr int NWAVES = NTHREADS / 64;
 constexpr int MAXV = 16;              // vectors per multi-dot / multi-axpy launch
-constexpr int MAX_RED_BLOCKS = 4096;  // blocks of a reduction launch
+constexpr int MAX_RED_BLOCKS = 16384;  // blocks of a reduction launch
 
 struct Geom {
   int nx, ny, nz;

@@ -1,0 +1,452 @@
+// gmg_fine.hpp -- finest-level kernels on colour-split storage.
+//
+// On the finest level (at least two levels, so nx, ny, nz are even) the
+// V-cycle iterate x (which becomes z = M v) and its right side b are stored
+// by colour: X_c = X + c * hn holds, for every x-pair (2m, 2m+1) of row j on
+// plane k, the one cell of the pair whose colour (i + j + k) % 2 is c, at
+// index idx = (k * ny + j) * H + m, H = nx / 2.  In X_c at (m, j, k) sits the
+// cell i = 2m + e, e = (c + j + k) % 2.
+//
+// A red-black half-sweep of colour c then reads only X_{1-c} (every
+// neighbour of a colour-c cell has the other colour) and writes only X_c, in
+// whole cache lines: the neighbours of the colour-c cell of pair m sit in
+// X_{1-c} at m (the pair's other cell, and the cells above, below, north and
+// south), and at m - 1 or m + 1 (the x-neighbour outside the pair).  The
+// coefficient a stays in the natural (k, j, i) layout.
+#pragma once
+
+#include "gmg_kernels.hpp"
+
+namespace gmg {
+
+// Index of pair m of row j on plane k in a colour array.
+__device__ __forceinline__ size_t sidx(const Geom& g, int m, int j, int k) {
+  return ((size_t)k * g.ny + j) * (size_t)(g.nx >> 1) + m;
+}
+
+// Red-black half-sweep of colour `colour` (cell coefficient a, face = mean of
+// the two cells).  Lane tx owns pair m = 64 bx + tx of row j = 4 by + ty and
+// marches its z-chunk, keeping a of the pair and X_{1-c} at m on the planes
+// k-1, k, k+1 in registers.  Every load of a plane is issued in one group
+// with clamped (always valid) addresses and no branches -- the values behind
+// a missing face are multiplied by zero weights -- and the group of plane k+1
+// is issued before plane k is computed.  FIRST: the first pre-smoothing
+// half-sweep from x = 0: b is read from the natural-layout u (times *bscale
+// when SCALED), stored by colour into B for both cells, and X_c = b / D;
+// X_{1-c} is left as it is (the next half-sweep overwrites it without
+// reading it).
+constexpr int SPLIT_BATCH = 2;  // planes whose loads are issued together
+
+template <typename T>
+struct SplitSide {
+  T at0, at1;    // a of the pair on plane k+1
+  T xot;         // X_{1-c} at m on plane k+1
+  T as, an;      // a of the updated cell's south / north neighbours
+  T xs, xn;      // X_{1-c} at m on rows j-1 / j+1
+  T aout, xout;  // a and X_{1-c} of the x-neighbour outside the pair
+  T b0, b1;      // right side (FIRST: of both cells of the pair; else b0 = B_c)
+};
+
+template <typename T, bool FIRST, bool SCALED>
+__device__ __forceinline__ void split_side_load(SplitSide<T>& S, const T* __restrict__ Xo, const T* __restrict__ Bc,
+                                                const double* __restrict__ u, double s, const T* __restrict__ a,
+                                                const Geom& g, int H, int m, int j, int k, int colour, bool act) {
+  const size_t ty = (size_t)H, tz = (size_t)H * g.ny;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const int e = (colour + j + k) & 1;
+  const int kk = act ? k : 0, jj = act ? j : 0, mm = act ? m : 0;
+  const size_t q = sidx(g, mm, jj, kk), cn = 2 * q, ce = cn + e;
+  const bool up = act && kk + 1 < g.nz;
+  const size_t qt = up ? q + tz : q, ct = up ? cn + sz : cn;
+  const size_t dys = (act && jj > 0) ? ty : 0, dyn = (act && jj < g.ny - 1) ? ty : 0;
+  const size_t das = (act && jj > 0) ? sy : 0, dan = (act && jj < g.ny - 1) ? sy : 0;
+  // outside the pair: cell 2m-1 (e = 0) or 2m+2 (e = 1), clamped to the pair
+  const bool hout = act && (e ? mm < H - 1 : mm > 0);
+  const size_t qo = hout ? (e ? q + 1 : q - 1) : q;
+  const size_t co = hout ? (e ? cn + 2 : cn - 1) : ce;
+  S.at0 = a[ct];
+  S.at1 = a[ct + 1];
+  S.as = a[ce - das];
+  S.an = a[ce + dan];
+  S.aout = a[co];
+  if (!FIRST) {
+    S.xot = Xo[qt];
+    S.xs = Xo[q - dys];
+    S.xn = Xo[q + dyn];
+    S.xout = Xo[qo];
+    S.b0 = Bc[q];
+    S.b1 = T(0);
+  } else {
+    S.xot = S.xs = S.xn = S.xout = T(0);
+    S.b0 = (T)(SCALED ? u[cn] * s : u[cn]);
+    S.b1 = (T)(SCALED ? u[cn + 1] * s : u[cn + 1]);
+  }
+}
+
+template <typename T, bool FIRST, bool SCALED>
+__global__ __launch_bounds__(NTHREADS) void k_gs_split(T* __restrict__ X, T* __restrict__ B,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ bscale, const T* __restrict__ a,
+                                                       Geom g, size_t hn, int kc, int colour) {
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int m = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
+  const bool act = m < H && j < g.ny;
+  const size_t sz = (size_t)g.nx * g.ny, tz = (size_t)H * g.ny;
+  const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
+  const double s = SCALED ? *bscale : 1.0;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  const bool hs = j > 0, hn_ = j < g.ny - 1;
+  T* __restrict__ Xc = X + (size_t)colour * hn;
+  const T* __restrict__ Xo = X + (size_t)(1 - colour) * hn;
+  T* __restrict__ Bc = B + (size_t)colour * hn;
+  T* __restrict__ Bo = B + (size_t)(1 - colour) * hn;
+  // planes k and k-1 (clamped loads; plane k0-1 is used only when k0 > 0)
+  T ac0, ac1, ab0, ab1, xo = T(0), xob = T(0);
+  {
+    const size_t q = act ? sidx(g, m, j, k0) : 0, cn = 2 * q;
+    const size_t qb = (act && k0 > 0) ? q - tz : q, cb = (act && k0 > 0) ? cn - sz : cn;
+    ac0 = a[cn];
+    ac1 = a[cn + 1];
+    ab0 = a[cb];
+    ab1 = a[cb + 1];
+    if (!FIRST) {
+      xo = Xo[q];
+      xob = Xo[qb];
+    }
+  }
+  // update of plane k from its loaded values Sc
+  auto plane = [&](int k, const SplitSide<T>& Sc) {
+    const bool top = k == g.nz - 1;
+    const int e = (colour + j + k) & 1;  // element of the pair being updated
+    const bool hout = e ? m < H - 1 : m > 0;
+    const T acv = e ? ac1 : ac0, ain = e ? ac0 : ac1;
+    const T abv = e ? ab1 : ab0, atv = e ? Sc.at1 : Sc.at0;
+    const T wi = (acv + ain) * hx;
+    const T wo = hout ? (acv + Sc.aout) * hx : T(0);
+    const T ws = hs ? (acv + Sc.as) * hy : T(0);
+    const T wn = hn_ ? (acv + Sc.an) * hy : T(0);
+    const T wb = k > 0 ? (acv + abv) * hz : T(0);
+    const T wt = !top ? (acv + atv) * hz : T(0);
+    const T D = wi + wo + ws + wn + (k > 0 ? wb : pz * acv) + (!top ? wt : pz * acv);
+    if (act) {
+      const size_t q = sidx(g, m, j, k);
+      if (FIRST) {
+        const T bc = e ? Sc.b1 : Sc.b0;
+        Bc[q] = bc;
+        Bo[q] = e ? Sc.b0 : Sc.b1;
+        Xc[q] = bc * recip(D);
+      } else {
+        const T off = wi * xo + wo * Sc.xout + ws * Sc.xs + wn * Sc.xn + wb * xob + wt * Sc.xot;
+        Xc[q] = (Sc.b0 + off) * recip(D);
+      }
+    }
+    ab0 = ac0;
+    ab1 = ac1;
+    ac0 = Sc.at0;
+    ac1 = Sc.at1;
+    xob = xo;
+    xo = Sc.xot;
+  };
+  // planes in batches of SPLIT_BATCH: the loads of a whole batch are issued
+  // before its first plane is updated (planes past the chunk load a valid
+  // clamped plane and are not updated)
+  for (int k = k0; k < k1; k += SPLIT_BATCH) {
+    SplitSide<T> S[SPLIT_BATCH];
+#pragma unroll
+    for (int t = 0; t < SPLIT_BATCH; ++t)
+      split_side_load<T, FIRST, SCALED>(S[t], Xo, Bc, u, s, a, g, H, m, j, min(k + t, k1 - 1), colour, act);
+#pragma unroll
+    for (int t = 0; t < SPLIT_BATCH; ++t)
+      if (k + t < k1) plane(k + t, S[t]);
+  }
+}
+
+// Values of the pair (left = cell 2m, right = cell 2m+1) at colour-array
+// index q on a row/plane whose cell 2m has colour p.
+template <typename TO, typename T>
+__device__ __forceinline__ void split_pair(const T* __restrict__ X, size_t hn, size_t q, int p, TO& l, TO& r) {
+  const TO v0 = (TO)X[q], v1 = (TO)X[q + hn];
+  l = p ? v1 : v0;
+  r = p ? v0 : v1;
+}
+
+// Residual and restriction from the colour-split iterate and right side:
+// b_coarse = mean over the 8 children of (b - A x).  Lane tx owns pair m
+// (= the coarse x-index) of fine row j and marches the fine planes of its
+// z-chunk, 2 per coarse plane; the two fine rows of a coarse row are summed
+// through LDS.  kc counts coarse planes.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_resid_restrict_split(const T* __restrict__ X, const T* __restrict__ B,
+                                                                   const T* __restrict__ a, Geom g, size_t hn,
+                                                                   T* __restrict__ bc, int kc) {
+  __shared__ T part[BY][BX];
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int m = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
+  const bool act = m < H && j < g.ny;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const size_t ty = (size_t)H, tz = (size_t)H * g.ny;
+  const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
+  const int K0 = tl.z * kc, K1 = min(NZ, K0 + kc);
+  const int k0 = 2 * K0, k1 = 2 * K1;
+  const bool hw = m > 0, he = m < H - 1, hs = j > 0, hn_ = j < g.ny - 1;
+  const int lane = threadIdx.x;
+  size_t cn = act ? 2 * sidx(g, m, j, k0) : 0;
+  size_t q = act ? sidx(g, m, j, k0) : 0;
+  // pair registers: [0] cell 2m, [1] cell 2m+1, planes below / centre
+  T xb[2] = {T(0), T(0)}, xc[2] = {T(0), T(0)}, ab[2] = {T(0), T(0)}, ac[2] = {T(0), T(0)};
+  if (act) {
+    split_pair(X, hn, q, (j + k0) & 1, xc[0], xc[1]);
+    ac[0] = a[cn];
+    ac[1] = a[cn + 1];
+    if (k0 > 0) {
+      split_pair(X, hn, q - tz, (j + k0 - 1) & 1, xb[0], xb[1]);
+      ab[0] = a[cn - sz];
+      ab[1] = a[cn - sz + 1];
+    }
+  }
+  T acc = T(0);
+  for (int k = k0; k < k1; ++k) {
+    const bool top = k == g.nz - 1;
+    const int p = (j + k) & 1;
+    T xt[2] = {T(0), T(0)}, at[2] = {T(0), T(0)};
+    if (act && !top) {
+      split_pair(X, hn, q + tz, p ^ 1, xt[0], xt[1]);
+      at[0] = a[cn + sz];
+      at[1] = a[cn + sz + 1];
+    }
+    T xw = __shfl_up(xc[1], 1, 64), aw = __shfl_up(ac[1], 1, 64);
+    T xe = __shfl_down(xc[0], 1, 64), ae = __shfl_down(ac[0], 1, 64);
+    if (act && lane == 0 && hw) {
+      xw = X[q - 1 + (size_t)(p ^ 1) * hn];  // right cell of pair m-1: colour p^1
+      aw = a[cn - 1];
+    }
+    if (act && lane == BX - 1 && he) {
+      xe = X[q + 1 + (size_t)p * hn];  // left cell of pair m+1: colour p
+      ae = a[cn + 2];
+    }
+    T rsum = T(0);
+    if (act) {
+      T xs[2] = {T(0), T(0)}, as_[2] = {T(0), T(0)}, xn[2] = {T(0), T(0)}, an[2] = {T(0), T(0)};
+      if (hs) {
+        split_pair(X, hn, q - ty, p ^ 1, xs[0], xs[1]);
+        as_[0] = a[cn - sy];
+        as_[1] = a[cn - sy + 1];
+      }
+      if (hn_) {
+        split_pair(X, hn, q + ty, p ^ 1, xn[0], xn[1]);
+        an[0] = a[cn + sy];
+        an[1] = a[cn + sy + 1];
+      }
+      T bv[2];
+      split_pair(B, hn, q, p, bv[0], bv[1]);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const T acv = ac[e], xcv = xc[e];
+        const T xo = e == 0 ? xw : xe, ao = e == 0 ? aw : ae;
+        const bool ho = e == 0 ? hw : he;
+        T Ax = (acv + ac[1 - e]) * hx * (xcv - xc[1 - e]);
+        Ax += ho ? (acv + ao) * hx * (xcv - xo) : T(0);
+        Ax += hs ? (acv + as_[e]) * hy * (xcv - xs[e]) : T(0);
+        Ax += hn_ ? (acv + an[e]) * hy * (xcv - xn[e]) : T(0);
+        Ax += k > 0 ? (acv + ab[e]) * hz * (xcv - xb[e]) : pz * acv * xcv;
+        Ax += !top ? (acv + at[e]) * hz * (xcv - xt[e]) : pz * acv * xcv;
+        rsum += bv[e] - Ax;
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        xb[e] = xc[e];
+        xc[e] = xt[e];
+        ab[e] = ac[e];
+        ac[e] = at[e];
+      }
+      cn += sz;
+      q += tz;
+    }
+    acc += rsum;
+    if (k & 1) {  // both fine planes of coarse plane k/2 done: add the row pair
+      part[threadIdx.y][threadIdx.x] = acc;
+      __syncthreads();
+      if (!(threadIdx.y & 1) && act) {
+        const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
+        bc[((size_t)(k >> 1) * NY + (j >> 1)) * H + m] = tot * T(0.125);
+      }
+      __syncthreads();
+      acc = T(0);
+    }
+  }
+}
+
+// X_c += P x_coarse for the colours c < ncol (cell-centred trilinear, as
+// k_prolong_add).  Grid over (H, ny, nz) with z-chunks of kc planes.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_prolong_split(T* __restrict__ X, const T* __restrict__ xc, Geom g,
+                                                            size_t hn, int ncol, int kc) {
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int m = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
+  if (m >= H || j >= g.ny) return;
+  const int NX = H, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const T q3 = T(0.75), q1 = T(0.25);
+  const int J = j >> 1;
+  int J2 = J + ((j & 1) ? 1 : -1);
+  if (J2 < 0 || J2 >= NY) J2 = J;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int k = k0; k < k1; ++k) {
+    const int K = k >> 1;
+    int K2 = K + ((k & 1) ? 1 : -1);
+    T sk = T(1);
+    if (K2 < 0 || K2 >= NZ) {
+      K2 = K;
+      sk = T(-1);
+    }
+    const T* p = xc + (size_t)K * NY * NX;
+    const T* pq = xc + (size_t)K2 * NY * NX;
+    for (int c = 0; c < ncol; ++c) {
+      const int e = (c + j + k) & 1;  // the cell is i = 2m + e
+      const int I = m;                 // parent: i >> 1
+      int I2 = I + (e ? 1 : -1);
+      if (I2 < 0 || I2 >= NX) I2 = I;
+      const T pl = q3 * (q3 * p[(size_t)J * NX + I] + q1 * p[(size_t)J * NX + I2]) +
+                   q1 * (q3 * p[(size_t)J2 * NX + I] + q1 * p[(size_t)J2 * NX + I2]);
+      const T ql = q3 * (q3 * pq[(size_t)J * NX + I] + q1 * pq[(size_t)J * NX + I2]) +
+                   q1 * (q3 * pq[(size_t)J2 * NX + I] + q1 * pq[(size_t)J2 * NX + I2]);
+      X[(size_t)c * hn + sidx(g, m, j, k)] += q3 * pl + q1 * sk * ql;
+    }
+  }
+}
+
+// w = A z (z colour-split, promoted to float64) and the dots (w, u_v),
+// v < NV.  Lane tx owns pair m of row j (rows strided by the grid's y extent)
+// and marches its z-chunk keeping z and a of the pair on planes k-1, k, k+1
+// in registers; the x-neighbours outside the pair come from the adjacent
+// lanes.
+template <typename TZ, int NV>
+__global__ __launch_bounds__(NTHREADS) void k_op_multidot_split(const TZ* __restrict__ Z, size_t hn,
+                                                                const double* __restrict__ a, Geom g,
+                                                                double* __restrict__ w, const double* __restrict__ U,
+                                                                size_t stride, double* __restrict__ partials, int kc) {
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int m = tl.x * BX + threadIdx.x;
+  const bool act = m < H;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const size_t ty = (size_t)H, tz = (size_t)H * g.ny;
+  const double hx = 0.5 * g.ihx2, hy = 0.5 * g.ihy2, hz = 0.5 * g.ihz2, pz = 2.0 * g.ihz2;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  const bool hw = m > 0, he = m < H - 1;
+  const int lane = threadIdx.x;
+  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    const bool hs = j > 0, hn_ = j < g.ny - 1;
+    size_t cn = act ? 2 * sidx(g, m, j, k0) : 0;
+    size_t q = act ? sidx(g, m, j, k0) : 0;
+    double zb[2] = {0.0, 0.0}, zc[2] = {0.0, 0.0}, ab[2] = {0.0, 0.0}, ac[2] = {0.0, 0.0};
+    if (act) {
+      split_pair(Z, hn, q, (j + k0) & 1, zc[0], zc[1]);
+      ac[0] = a[cn];
+      ac[1] = a[cn + 1];
+      if (k0 > 0) {
+        split_pair(Z, hn, q - tz, (j + k0 - 1) & 1, zb[0], zb[1]);
+        ab[0] = a[cn - sz];
+        ab[1] = a[cn - sz + 1];
+      }
+    }
+    for (int k = k0; k < k1; ++k) {
+      const bool top = k == g.nz - 1;
+      const int p = (j + k) & 1;
+      double zt[2] = {0.0, 0.0}, at[2] = {0.0, 0.0};
+      if (act && !top) {
+        split_pair(Z, hn, q + tz, p ^ 1, zt[0], zt[1]);
+        at[0] = a[cn + sz];
+        at[1] = a[cn + sz + 1];
+      }
+      double zw = __shfl_up(zc[1], 1, 64), aw = __shfl_up(ac[1], 1, 64);
+      double ze = __shfl_down(zc[0], 1, 64), ae = __shfl_down(ac[0], 1, 64);
+      if (act && lane == 0 && hw) {
+        zw = (double)Z[q - 1 + (size_t)(p ^ 1) * hn];
+        aw = a[cn - 1];
+      }
+      if (act && lane == BX - 1 && he) {
+        ze = (double)Z[q + 1 + (size_t)p * hn];
+        ae = a[cn + 2];
+      }
+      if (act) {
+        double zs[2] = {0.0, 0.0}, as_[2] = {0.0, 0.0}, zn[2] = {0.0, 0.0}, an[2] = {0.0, 0.0};
+        if (hs) {
+          split_pair(Z, hn, q - ty, p ^ 1, zs[0], zs[1]);
+          as_[0] = a[cn - sy];
+          as_[1] = a[cn - sy + 1];
+        }
+        if (hn_) {
+          split_pair(Z, hn, q + ty, p ^ 1, zn[0], zn[1]);
+          an[0] = a[cn + sy];
+          an[1] = a[cn + sy + 1];
+        }
+        double wv[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const double acv = ac[e], zcv = zc[e];
+          const double zo = e == 0 ? zw : ze, ao = e == 0 ? aw : ae;
+          const bool ho = e == 0 ? hw : he;
+          double s = (acv + ac[1 - e]) * hx * (zcv - zc[1 - e]);
+          s += ho ? (acv + ao) * hx * (zcv - zo) : 0.0;
+          s += hs ? (acv + as_[e]) * hy * (zcv - zs[e]) : 0.0;
+          s += hn_ ? (acv + an[e]) * hy * (zcv - zn[e]) : 0.0;
+          s += k > 0 ? (acv + ab[e]) * hz * (zcv - zb[e]) : pz * acv * zcv;
+          s += !top ? (acv + at[e]) * hz * (zcv - zt[e]) : pz * acv * zcv;
+          wv[e] = s;
+        }
+        w[cn] = wv[0];
+        w[cn + 1] = wv[1];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          acc[v] += wv[0] * U[(size_t)v * stride + cn] + wv[1] * U[(size_t)v * stride + cn + 1];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          zb[e] = zc[e];
+          zc[e] = zt[e];
+          ab[e] = ac[e];
+          ac[e] = at[e];
+        }
+        cn += sz;
+        q += tz;
+      }
+    }
+  }
+  block_store_partials<NV>(acc, NV, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// phi += sum_v y_v z_v with z_v colour-split (z promoted to float64).
+template <typename TZ, int NV>
+__global__ __launch_bounds__(NTHREADS) void k_update_split(double* __restrict__ phi, const TZ* __restrict__ Z,
+                                                           size_t hn, size_t stride, Coeffs16 y, Geom g, int kc) {
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int m = tl.x * BX + threadIdx.x;
+  const int j = tl.y * BY + threadIdx.y;
+  if (m >= H || j >= g.ny) return;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int k = k0; k < k1; ++k) {
+    const size_t q = sidx(g, m, j, k), cn = 2 * q;
+    const int p = (j + k) & 1;
+    double l = phi[cn], r = phi[cn + 1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double zl, zr;
+      split_pair(Z + (size_t)v * stride, hn, q, p, zl, zr);
+      l += y.v[v] * zl;
+      r += y.v[v] * zr;
+    }
+    phi[cn] = l;
+    phi[cn + 1] = r;
+  }
+}
+
+}  // namespace gmg

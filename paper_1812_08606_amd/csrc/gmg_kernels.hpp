@@ -18,7 +18,6 @@
 #include <stdint.h>
 
 #include "gmg_common.hpp"
-#include "gmg_sweep.hpp"
 
 namespace gmg {
 
@@ -29,6 +28,11 @@ struct Coeffs16 {
 __device__ __forceinline__ size_t cidx(const Geom& g, int i, int j, int k) {
   return ((size_t)k * g.ny + j) * g.nx + i;
 }
+
+// 1 / d: the hardware reciprocal (1 ulp) in the float32 preconditioner, an
+// exact division in float64.
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
 
 // Workgroups go to the chip's 8 XCDs (each with its own L2) round-robin in
 // the order of their linear index.  xcd_tile renumbers them so that every XCD
@@ -196,207 +200,6 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_first(T* __restrict__ x, const 
   }
 }
 
-// Red-black half-sweep of one colour on the finest level (cell
-// coefficient; even nx).  Lane tx owns the x-pair (2m, 2m+1), m = 64 bx + tx,
-// of row j = 4 by + ty and marches its z-chunk keeping x and a of the pair on
-// planes k-1, k, k+1 in registers.  On every plane exactly one cell of the
-// pair has the colour being updated, the same one across a row, so a wave
-// takes one branch; the x-neighbour outside the pair comes from the adjacent
-// lane (a load at the wave's edges).  Only cells of the other colour are
-// read, and none of them is written, so the update is order-free, and every
-// load of plane k+1 (and the pair of plane k+2) is issued before plane k is
-// computed: one memory latency per plane is hidden behind the previous one.
-// FIRST: the first pre-smoothing half-sweep from x = 0 (x is not read; cells
-// of the colour get b / D, the others 0), also storing b in T into b_out if
-// given.
-template <typename T, typename TB>
-struct PairSide {
-  T sa, sx, na, nx;  // a and x of the updated cell's y-neighbours
-  T wa, wx, ea, ex;  // a and x outside the pair (wave-edge lanes only)
-  TB b0, b1;         // right side of the updated cell (FIRST: of both cells)
-};
-
-template <typename T, typename TB, bool FIRST>
-__device__ __forceinline__ void pair_side_fetch(PairSide<T, TB>& S, const T* __restrict__ x,
-                                                const T* __restrict__ a, const TB* __restrict__ b, size_t c,
-                                                size_t sy, int e, bool hs, bool hn, bool lw, bool le) {
-  const size_t ce = c + e;
-  S.sa = S.sx = S.na = S.nx = S.wa = S.wx = S.ea = S.ex = T(0);
-  if (hs) {
-    S.sa = a[ce - sy];
-    if (!FIRST) S.sx = x[ce - sy];
-  }
-  if (hn) {
-    S.na = a[ce + sy];
-    if (!FIRST) S.nx = x[ce + sy];
-  }
-  if (lw) {
-    S.wa = a[c - 1];
-    if (!FIRST) S.wx = x[c - 1];
-  }
-  if (le) {
-    S.ea = a[c + 2];
-    if (!FIRST) S.ex = x[c + 2];
-  }
-  if (FIRST) {
-    S.b0 = b[c];
-    S.b1 = b[c + 1];
-  } else {
-    S.b0 = b[ce];
-    S.b1 = TB(0);
-  }
-}
-
-template <typename T, typename TB, bool SCALED, bool FIRST>
-__global__ __launch_bounds__(NTHREADS) void k_gs_pair(T* __restrict__ x, const TB* __restrict__ b,
-                                                      const double* __restrict__ bscale, T* __restrict__ b_out,
-                                                      const T* __restrict__ a, Geom g, int kc, int colour) {
-  const Tile tl = xcd_tile();
-  const int m = tl.x * BX + threadIdx.x;
-  const int j = tl.y * BY + threadIdx.y;
-  const int i0 = 2 * m;
-  const bool act = i0 < g.nx && j < g.ny;
-  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
-  const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
-  const double s = SCALED ? *bscale : 1.0;
-  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
-  const bool hs = act && j > 0, hn = act && j < g.ny - 1;
-  const bool hwo = i0 > 0, heo = i0 + 2 < g.nx;  // faces outside the pair
-  const int lane = threadIdx.x;
-  const bool lw = act && lane == 0 && hwo, le = act && lane == BX - 1 && heo;
-  const int par = colour + i0 + j;  // the updated element on plane k is (par + k) & 1
-  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
-  T xc0 = T(0), xc1 = T(0), ac0 = T(0), ac1 = T(0);  // the pair on plane k
-  T xb0 = T(0), xb1 = T(0), ab0 = T(0), ab1 = T(0);  // plane k-1
-  T xt0 = T(0), xt1 = T(0), at0 = T(0), at1 = T(0);  // plane k+1
-  PairSide<T, TB> S{};
-  if (act) {
-    ac0 = a[c];
-    ac1 = a[c + 1];
-    if (!FIRST) {
-      xc0 = x[c];
-      xc1 = x[c + 1];
-    }
-    if (k0 > 0) {
-      ab0 = a[c - sz];
-      ab1 = a[c - sz + 1];
-      if (!FIRST) {
-        xb0 = x[c - sz];
-        xb1 = x[c - sz + 1];
-      }
-    }
-    if (k0 + 1 < g.nz) {
-      at0 = a[c + sz];
-      at1 = a[c + sz + 1];
-      if (!FIRST) {
-        xt0 = x[c + sz];
-        xt1 = x[c + sz + 1];
-      }
-    }
-    pair_side_fetch<T, TB, FIRST>(S, x, a, b, c, sy, (par + k0) & 1, hs, hn, lw, le);
-  }
-  for (int k = k0; k < k1; ++k) {
-    // prefetch: the pair of plane k+2 and the side values of plane k+1
-    T xu0 = T(0), xu1 = T(0), au0 = T(0), au1 = T(0);
-    PairSide<T, TB> Sn{};
-    if (act && k + 1 < k1) {
-      if (k + 2 < g.nz) {
-        au0 = a[c + 2 * sz];
-        au1 = a[c + 2 * sz + 1];
-        if (!FIRST) {
-          xu0 = x[c + 2 * sz];
-          xu1 = x[c + 2 * sz + 1];
-        }
-      }
-      pair_side_fetch<T, TB, FIRST>(Sn, x, a, b, c + sz, sy, (par + k + 1) & 1, hs, hn, lw, le);
-    }
-    const bool top = k == g.nz - 1;
-    // outer x-neighbours of the pair on plane k: lane tx-1's right cell and
-    // lane tx+1's left cell (loads at the wave's edges)
-    T awo = __shfl_up(ac1, 1, 64), aeo = __shfl_down(ac0, 1, 64);
-    T xwo = T(0), xeo = T(0);
-    if (!FIRST) {
-      xwo = __shfl_up(xc1, 1, 64);
-      xeo = __shfl_down(xc0, 1, 64);
-    }
-    if (lw) {
-      awo = S.wa;
-      xwo = S.wx;
-    }
-    if (le) {
-      aeo = S.ea;
-      xeo = S.ex;
-    }
-    if (act) {
-      const int e = (par + k) & 1;  // element of the pair being updated
-      const size_t ce = c + e;
-      const T acv = e ? ac1 : ac0;
-      // x-faces: the pair's inner face and the outer face on the cell's side
-      const T xin = e ? xc0 : xc1, ain = e ? ac0 : ac1;
-      const T xout = e ? xeo : xwo, aout = e ? aeo : awo;
-      const bool hout = e ? heo : hwo;
-      const T wi = (acv + ain) * hx;
-      const T wo = hout ? (acv + aout) * hx : T(0);
-      T D = wi + wo, off = wi * xin + (hout ? wo * xout : T(0));
-      if (hs) {
-        const T w = (acv + S.sa) * hy;
-        D += w;
-        off += w * S.sx;
-      }
-      if (hn) {
-        const T w = (acv + S.na) * hy;
-        D += w;
-        off += w * S.nx;
-      }
-      const T xbv = e ? xb1 : xb0, abv = e ? ab1 : ab0;
-      const T xtv = e ? xt1 : xt0, atv = e ? at1 : at0;
-      if (k > 0) {
-        const T w = (acv + abv) * hz;
-        D += w;
-        off += w * xbv;
-      } else {
-        D += pz * acv;
-      }
-      if (!top) {
-        const T w = (acv + atv) * hz;
-        D += w;
-        off += w * xtv;
-      } else {
-        D += pz * acv;
-      }
-      if (FIRST) {
-        // both cells' right side (stored in T when b_out is given); the
-        // other colour starts at 0
-        const T b0v = SCALED ? (T)((double)S.b0 * s) : (T)S.b0;
-        const T b1v = SCALED ? (T)((double)S.b1 * s) : (T)S.b1;
-        if (b_out) {
-          b_out[c] = b0v;
-          b_out[c + 1] = b1v;
-        }
-        x[ce] = (e ? b1v : b0v) * sweep_recip(D);
-        x[c + 1 - e] = T(0);
-      } else {
-        const T bv = SCALED ? (T)((double)S.b0 * s) : (T)S.b0;
-        x[ce] = (bv + off) * sweep_recip(D);
-      }
-    }
-    xb0 = xc0;
-    xb1 = xc1;
-    xc0 = xt0;
-    xc1 = xt1;
-    xt0 = xu0;
-    xt1 = xu1;
-    ab0 = ac0;
-    ab1 = ac1;
-    ac0 = at0;
-    ac1 = at1;
-    at0 = au0;
-    at1 = au1;
-    S = Sn;
-    c += act ? sz : 0;
-  }
-}
-
 // Red-black half-sweep of one colour on a coarse level (stored face
 // coefficients; even nx): the lane-pair scheme of k_gs_pair.  The face
 // between the pair's right cell and the next pair is the adjacent lane's west
@@ -465,7 +268,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_pair_face(T* __restrict__ x, co
       const T wb = e ? wb1 : wb0, wt = e ? wt1 : wt0;
       const T D = (ww + we) * ix + (ws + wn) * iy + (k > 0 ? wb : T(2) * wb) * iz + (top ? T(2) * wt : wt) * iz;
       if (FIRST) {
-        x[ce] = b[ce] * sweep_recip(D);
+        x[ce] = b[ce] * recip(D);
         x[c + 1 - e] = T(0);
       } else {
         const T xw = e ? xc0 : xwo, xe = e ? xeo : xc1;
@@ -474,7 +277,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_pair_face(T* __restrict__ x, co
         T off = (ww * xw + we * xe) * ix + (ws * xs + wn * xn) * iy;
         off += k > 0 ? wb * iz * xbv : T(0);
         off += !top ? wt * iz * xtv : T(0);
-        x[ce] = (b[ce] + off) * sweep_recip(D);
+        x[ce] = (b[ce] + off) * recip(D);
       }
     }
     xb0 = xc0;
@@ -687,109 +490,6 @@ __global__ __launch_bounds__(BOTTOM_THREADS) void k_vcycle_bottom(BottomArgs<T> 
   }
 }
 
-// Finest-level residual and restriction, b_coarse = mean over the 8
-// children of (b - A x), cell coefficient.  Block 64 x 4: lane tx owns the
-// fine x-pair (2I, 2I+1), I = 64 bx + tx, of fine row j = 4 by + ty; each
-// thread marches the fine planes of its z-chunk (2 fine planes per coarse
-// plane) keeping x and a of its pair on planes k-1, k, k+1 in registers; the
-// two fine rows of a coarse row are summed through LDS.  Needs even nx, ny,
-// nz; kc counts coarse planes.
-template <typename T, typename TB>
-__global__ __launch_bounds__(NTHREADS) void k_resid_restrict_cell(const T* __restrict__ x, const TB* __restrict__ b,
-                                                                  const double* __restrict__ bscale,
-                                                                  const T* __restrict__ a, Geom g,
-                                                                  T* __restrict__ bc, int kc) {
-  const Tile tl = xcd_tile();
-  __shared__ T part[BY][BX];
-  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
-  const int I = tl.x * BX + threadIdx.x;
-  const int j = tl.y * BY + threadIdx.y;
-  const bool act = I < NX && j < g.ny;
-  const int i0 = 2 * I;
-  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
-  const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
-  const T s = (T)(bscale ? *bscale : 1.0);
-  const int K0 = tl.z * kc, K1 = min(NZ, K0 + kc);
-  const int k0 = 2 * K0, k1 = 2 * K1;
-  // column registers: [0] cell i0, [1] cell i0+1, planes below / centre / above
-  T xb[2] = {T(0), T(0)}, xc[2] = {T(0), T(0)}, xt[2], ab[2] = {T(0), T(0)}, ac[2] = {T(0), T(0)}, at[2];
-  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
-  if (act) {
-    xc[0] = x[c];
-    xc[1] = x[c + 1];
-    ac[0] = a[c];
-    ac[1] = a[c + 1];
-    if (k0 > 0) {
-      xb[0] = x[c - sz];
-      xb[1] = x[c - sz + 1];
-      ab[0] = a[c - sz];
-      ab[1] = a[c - sz + 1];
-    }
-  }
-  T acc = T(0);
-  for (int k = k0; k < k1; ++k) {
-    T rsum = T(0);
-    if (act) {
-      const bool top = k == g.nz - 1;
-      xt[0] = top ? T(0) : x[c + sz];
-      xt[1] = top ? T(0) : x[c + sz + 1];
-      at[0] = top ? T(0) : a[c + sz];
-      at[1] = top ? T(0) : a[c + sz + 1];
-      // in-plane neighbours: west of i0, east of i0+1, rows j-1 and j+1
-      const bool hw = i0 > 0, he = i0 + 2 < g.nx, hs = j > 0, hn = j < g.ny - 1;
-      const T xw = hw ? x[c - 1] : T(0), aw = hw ? a[c - 1] : T(0);
-      const T xe = he ? x[c + 2] : T(0), ae = he ? a[c + 2] : T(0);
-      T xs[2] = {T(0), T(0)}, as_[2] = {T(0), T(0)}, xn[2] = {T(0), T(0)}, an[2] = {T(0), T(0)};
-      if (hs) {
-        xs[0] = x[c - sy];
-        xs[1] = x[c - sy + 1];
-        as_[0] = a[c - sy];
-        as_[1] = a[c - sy + 1];
-      }
-      if (hn) {
-        xn[0] = x[c + sy];
-        xn[1] = x[c + sy + 1];
-        an[0] = a[c + sy];
-        an[1] = a[c + sy + 1];
-      }
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const T acv = ac[e], xcv = xc[e];
-        // x-faces: the pair's inner face, and the outer face on its own side
-        const T xo = e == 0 ? xw : xe, ao = e == 0 ? aw : ae;
-        const bool ho = e == 0 ? hw : he;
-        const T xi = xc[1 - e], ai = ac[1 - e];
-        T Ax = (acv + ai) * hx * (xcv - xi);
-        Ax += ho ? (acv + ao) * hx * (xcv - xo) : T(0);
-        Ax += hs ? (acv + as_[e]) * hy * (xcv - xs[e]) : T(0);
-        Ax += hn ? (acv + an[e]) * hy * (xcv - xn[e]) : T(0);
-        Ax += k > 0 ? (acv + ab[e]) * hz * (xcv - xb[e]) : pz * acv * xcv;
-        Ax += !top ? (acv + at[e]) * hz * (xcv - xt[e]) : pz * acv * xcv;
-        rsum += (T)b[c + e] * s - Ax;
-      }
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        xb[e] = xc[e];
-        xc[e] = xt[e];
-        ab[e] = ac[e];
-        ac[e] = at[e];
-      }
-      c += sz;
-    }
-    acc += rsum;
-    if (k & 1) {  // both fine planes of coarse plane k/2 done: add the row pair
-      part[threadIdx.y][threadIdx.x] = acc;
-      __syncthreads();
-      if (!(threadIdx.y & 1) && act) {
-        const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
-        bc[((size_t)(k >> 1) * NY + (j >> 1)) * NX + I] = tot * T(0.125);
-      }
-      __syncthreads();
-      acc = T(0);
-    }
-  }
-}
-
 // x_fine += P x_coarse, cell-centred trilinear: per dimension 3/4 of the
 // parent and 1/4 of the nearer coarse neighbour; outside the grid the
 // neighbour is the parent (x, y: Neumann) or minus the parent (z: plates).
@@ -826,43 +526,6 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_add(T* __restrict__ x, con
       const size_t c = cidx(g, i, j, k);
       x[c] += q3 * pl + q1 * sk * ql;
     }
-  }
-}
-
-// One symmetric red-black sweep on the finest level in one pass (the phase
-// functions and the blocking are described in gmg_sweep.hpp).  Block 64 x 4
-// threads; grid (ceil(nx/64), ceil(ny/TY), ceil(nz/kc)).  The plane needed at
-// step t+1 is fetched into registers during step t.  SCALED: b is read as
-// b * (*bscale).
-template <typename T, typename TB, int XM, int TY, bool SCALED>
-__global__ __launch_bounds__(NTHREADS) void k_sym_sweep(SweepArgs<T, TB> A) {
-  const Tile tl = xcd_tile();
-  constexpr int NPT = (SweepTile<TY>::P + NTHREADS - 1) / NTHREADS;
-  __shared__ SweepSmem<T, TY> s;
-  SweepPlan<NPT, XM> P;
-  SweepPhasePlan<TY> Q;
-  SweepFetch<T, XM, NPT> R;
-  const int tid = threadIdx.y * BX + threadIdx.x;
-  const int k0 = tl.z * A.kc, k1 = min(A.g.nz, k0 + A.kc);
-  const double bsc = SCALED ? *A.bscale : 1.0;
-  const bool store_b = A.b_out != nullptr;
-  sweep_plan<TY, NPT, XM>(P, A.g, tl.x, tl.y, tid, NTHREADS);
-  sweep_phase_plan<TY>(Q, A.g, A.c1, tl.x, tl.y, tid);
-  SweepStep nx = sweep_step(A.g, k0, k1, k0 - 3);
-  sweep_fetch<T, TB, XM, NPT, SCALED>(R, P, A, nx.pxa, nx.load_xa, nx.pb, nx.load_b, nx.store_b && store_b, bsc);
-  for (int t = k0 - 3; t <= k1; ++t) {
-    const SweepStep st = nx;
-    __syncthreads();
-    sweep_stash<T, XM, TY, NPT>(s, R, P, tid, NTHREADS, st.pxa, st.load_xa, st.pb, st.load_b);
-    __syncthreads();
-    if (t < k1) {
-      nx = sweep_step(A.g, k0, k1, t + 1);
-      sweep_fetch<T, TB, XM, NPT, SCALED>(R, P, A, nx.pxa, nx.load_xa, nx.pb, nx.load_b, nx.store_b && store_b,
-                                          bsc);
-    }
-    if (st.do_first) sweep_first<T, XM, TY>(s, Q, A.g, t);
-    __syncthreads();
-    if (st.do_second) sweep_second<T, TY>(s, Q, A.g, A.x_out, t - 1);
   }
 }
 
@@ -1023,32 +686,42 @@ __global__ __launch_bounds__(NTHREADS) void k_update(double* __restrict__ phi, s
 // vectors in a fixed order.  mode 0: out[v] = sum; mode 1: out[v] = sum *
 // scale[v] (dots against lazily normalised vectors); mode 2 (nv = 1):
 // out[0] = sqrt(sum), out2[0] = 1 / sqrt(sum) (0 if the sum is 0).
-__global__ __launch_bounds__(NTHREADS) void k_finalize(const double* __restrict__ partials, int nblocks, int nv,
-                                                       int mode, double* __restrict__ out,
-                                                       const double* __restrict__ scale,
-                                                       double* __restrict__ out2) {
-  __shared__ double sm[NWAVES];
-  const int tid = threadIdx.y * BX + threadIdx.x;
-  for (int v = 0; v < nv; ++v) {
-    double s = 0.0;
-    for (int b = tid; b < nblocks; b += NTHREADS) s += partials[(size_t)v * nblocks + b];
-    s = wave_sum(s);
-    if ((tid & 63) == 0) sm[tid >> 6] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < NWAVES; ++w) t += sm[w];
-      if (mode == 0) {
-        out[v] = t;
-      } else if (mode == 1) {
-        out[v] = t * scale[v];
-      } else {
-        const double r = sqrt(t);
-        out[0] = r;
-        out2[0] = r > 0.0 ? 1.0 / r : 0.0;
-      }
+constexpr int FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ partials, int nblocks, int nv,
+                                                          int mode, double* __restrict__ out,
+                                                          const double* __restrict__ scale,
+                                                          double* __restrict__ out2) {
+  __shared__ double sm[MAXV][FIN_THREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double s[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) s[v] = 0.0;
+  for (int b = tid; b < nblocks; b += FIN_THREADS) {
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v)
+      if (v < nv) s[v] += partials[(size_t)v * nblocks + b];
+  }
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) {
+    if (v < nv) {
+      const double t = wave_sum(s[v]);
+      if (lane == 0) sm[v][wave] = t;
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  if (tid < nv) {
+    double t = 0.0;
+    for (int w = 0; w < FIN_THREADS / 64; ++w) t += sm[tid][w];
+    if (mode == 0) {
+      out[tid] = t;
+    } else if (mode == 1) {
+      out[tid] = t * scale[tid];
+    } else {
+      const double r = sqrt(t);
+      out[0] = r;
+      out2[0] = r > 0.0 ? 1.0 / r : 0.0;
+    }
   }
 }
 

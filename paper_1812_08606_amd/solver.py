@@ -65,7 +65,7 @@ class GMGPoisson:
 
     def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
                  max_iter: int = 200, nu_pre: int = 2, nu_post: int = 2,
-                 coarse_max_cells: int = 4096, fine_sweep: int = 0):
+                 coarse_max_cells: int = 4096):
         self._lib = _lib.load()
         if a.dim() != 3:
             raise ValueError("a must be 3-D (nz, ny, nx)")
@@ -83,7 +83,6 @@ class GMGPoisson:
         opt.nu_pre, opt.nu_post = int(nu_pre), int(nu_post)
         opt.precision = _PRECISION[precision]
         opt.coarse_max_cells = int(coarse_max_cells)
-        opt.fine_sweep = int(fine_sweep)
         self.options = opt
         nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
         if nbytes == 0:

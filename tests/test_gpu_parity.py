@@ -84,15 +84,14 @@ def test_vcycle_mixed_matches_float32_oracle(shape):
     assert rel(z, ref) < 2e-5
 
 
-@pytest.mark.parametrize("fine_sweep", [1, 2])
-@pytest.mark.parametrize("shape", [(64, 32, 48), (130, 8, 4), (66, 10, 12)])
-def test_vcycle_fine_smoother_kernels(fine_sweep, shape):
-    """Both finest-level smoother implementations (one fused kernel per
-    symmetric sweep; one kernel per half-sweep) give the oracle's V-cycle."""
+@pytest.mark.parametrize("shape", [(64, 32, 48), (130, 8, 4), (66, 10, 12), (256, 12, 8)])
+def test_vcycle_colour_split_finest_level(shape):
+    """The finest level's colour-split kernels (several 64-pair wave rows,
+    ragged last wave, thin grids) give the oracle's V-cycle."""
     a, f, h = _rand_problem(shape, 6)
-    s64 = gm.GMGPoisson(T(a), h=h, precision="fp64", fine_sweep=fine_sweep)
+    s64 = gm.GMGPoisson(T(a), h=h, precision="fp64")
     assert rel(npy(s64.vcycle(T(f))), vcycle(build_hierarchy(a, h), f)) < 1e-12
-    s32 = gm.GMGPoisson(T(a), h=h, precision="mixed", fine_sweep=fine_sweep)
+    s32 = gm.GMGPoisson(T(a), h=h, precision="mixed")
     ref32 = vcycle(build_hierarchy(a, h, dtype=np.float32), f.astype(np.float32)).astype(np.float64)
     assert rel(npy(s32.vcycle(T(f))), ref32) < 2e-5
 
