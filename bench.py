@@ -1,21 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the GMG-preconditioned FGMRES solve on one MI355X.
 
-Workload: the 512^3 single-filament problem (max(a) = 1e4, f = 50 (n_p -
-n_e)), unit cube, phi = 0 / 1 on the plates, tolerance 1e-8, FGMRES(10) with
-one V(2,2)-cycle per step.  One benchmark step is one pass of the whole hot
-path: coefficient renewal (hierarchy rebuild), the forward solve from a zero
-guess, the adjoint solve for a fixed dL/dphi and the dL/da face-flux kernel.
-Each step therefore holds two converged 1e-8 solves; ``value`` counts
-cells x solves per second over the timed steps (inputs resident in HBM).
+Default workload (c3): the 512^3 single-filament problem (max(a) = 1e4,
+f = 50 (n_p - n_e)), unit cube, phi = 0 / 1 on the plates, tolerance 1e-8,
+FGMRES(10) with one V(2,2)-cycle per step.  One benchmark step is one pass
+of the whole hot path: coefficient renewal (hierarchy rebuild), the forward
+solve from a zero guess, the adjoint solve for a fixed dL/dphi and the dL/da
+face-flux kernel.  Each step therefore holds two converged 1e-8 solves;
+``value`` counts cells x solves per second over the timed steps (inputs
+resident in HBM).
+
+Workload c5: the 768^3 two-filament time loop.  Step t advects both
+filaments t cells in +z (the step-0 fields rolled along z on the device),
+renews the coefficient and solves warm-started from the previous phi; one
+solve per step.
 
 Prints one JSON line on stdout; progress goes to stderr.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--n 512]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c3|c5] [--n N]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -28,6 +36,8 @@ if ROOT not in sys.path:
 
 METRIC = "converged cells/s per 1e-8 Poisson solve + HBM GB/s, FP64 vs mixed, 512^3"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SOURCES = ["gmg_common.hpp", "gmg_kernels.hpp", "gmg_fine.hpp", "gmg.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gs_fine_f32_filament512.md")
 
 
 def log(*a):
@@ -37,35 +47,58 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (c3: 3, c5: 19)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
+    ap.add_argument("--n", type=int, default=None, help="grid edge (c3: 512, c5: 768)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side-by-side run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=128, help="edge of the CPU-oracle sample grid")
+    ap.add_argument("--cpu-n", type=int, default=160, help="edge of the CPU-oracle sample grid")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (for hardware-counter scaling)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 3 if args.workload == "c3" else 19
+    if args.n is None:
+        args.n = 512 if args.workload == "c3" else 768
+    return args
 
 
 # ---------------------------------------------------------------------------
-# Algorithmic (compulsory) bytes per finest-level cell of each kernel: every
-# kernel reads each input once and writes each output once at element
-# granularity.  s = bytes of the V-cycle precision; j = vectors in a
-# multi-dot / multi-axpy launch; k = preconditioned vectors in an update.
+# Algorithmic bytes per cell of the level a kernel runs on: every kernel reads
+# each input once and writes each output once, at element granularity.
+# s = bytes of the V-cycle precision.  On the finest level the iterate x and
+# its right side B are stored by colour, so a half-sweep touches half of each.
 # ---------------------------------------------------------------------------
-def bytes_per_cell(name, s, nv=0):
-    base = name.rsplit("_", 2)[0] if name.endswith(("_f32", "_f64")) else name
-    if base == "gs":  # half-sweep: x (all) + a (all) + b (own colour) read, x (own colour) written
-        return 3 * s
-    if base == "gs_first":  # b_in (float64) + a read; x (and the float32 copy of b) written
-        return 8 + s + s + (s if s == 4 else 0)
-    if base == "resid_restrict":  # x, a, b read; coarse b (1/8) written
-        return 3 * s + s / 8
-    if base == "prolong_add":  # x, coarse x (1/8) read; x written
-        return 2 * s + s / 8
+def split_name(name):
+    """'gs_fine_f32' -> ('gs', 0); 'gs_L2_f32' -> ('gs', 2); other -> (name, None)."""
+    m = re.match(r"^(.*)_(fine|L(\d+)|coarsest)_(f32|f64)$", name)
+    if not m:
+        return name, None
+    level = 0 if m.group(2) == "fine" else (int(m.group(3)) if m.group(3) else -1)
+    return m.group(1), level
+
+
+def bytes_per_cell(base, level, s, nu_post=2):
+    if level == 0:
+        if base == "gs":  # X of the other colour, a, B of the own colour read; X own colour written
+            return 0.5 * s + s + 0.5 * s + 0.5 * s
+        if base == "gs_first":  # u (float64) and a read; B (both colours) and X (own colour) written
+            return 8 + s + s + 0.5 * s
+        if base == "resid_restrict":  # X, B, a read; coarse right side (1/8) written
+            return 3 * s + s / 8
+        if base == "prolong_add":  # the red half of X read and written (both halves without post-sweeps)
+            return (1 if nu_post > 0 else 2) * s + s / 8
+        return None
+    if level is not None and level > 0:  # face coefficients wx, wy, wz (plates neglected)
+        if base == "gs":  # x, faces read; b, x of the own colour read / written
+            return s + 3 * s + 0.5 * s + 0.5 * s
+        if base == "gs_first":  # faces, b of the own colour read; x written
+            return 3 * s + 0.5 * s + s
+        if base == "resid_restrict":  # x, b, faces read; coarse right side written
+            return s + s + 3 * s + s / 8
+        if base == "prolong_add":  # x read and written, coarse x read
+            return 2 * s + s / 8
     return None
 
 
@@ -85,10 +118,28 @@ def outer_bytes(name, nv, s_z):
 
 def nv_sequence(iterations, restart):
     """Vectors per Arnoldi step j (j+1 within each restart cycle)."""
-    seq = []
-    for it in range(iterations):
-        seq.append(it % restart + 1)
-    return seq
+    return [it % restart + 1 for it in range(iterations)]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1812_08606_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the finest-level half-sweep from the committed
+    counter summary, if it was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    if not (m_b and m_h) or m_h.group(1) != kernel_source_hash():
+        return None
+    return float(m_b.group(1))
 
 
 def main():
@@ -97,7 +148,6 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this solver is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_1812_08606_amd as gm  # raises if the HIP library is missing
@@ -106,14 +156,16 @@ def main():
     dev = torch.device("cuda:0")
     n = args.n
     N = n ** 3
-    t_gen = time.perf_counter()
-    p = make_config(3, n=n)
-    mask = torch.tensor(probe_box_mask(n), device=dev)
-    a = torch.tensor(p.a, device=dev)
-    f = torch.tensor(p.f, device=dev)
-    del p.a, p.f
-    log(f"inputs: filament {n}^3, max(a)=1e4, generated in {time.perf_counter() - t_gen:.1f}s")
     h = 1.0 / n
+    c5 = args.workload == "c5"
+    t_gen = time.perf_counter()
+    p = make_config(5 if c5 else 3, n=n)
+    a0 = torch.tensor(p.a, device=dev)
+    f0 = torch.tensor(p.f, device=dev)
+    del p.a, p.f
+    log(f"inputs: {'two filaments' if c5 else 'filament'} {n}^3, max(a)=1e4, generated in "
+        f"{time.perf_counter() - t_gen:.1f}s")
+    mask = None if c5 else torch.tensor(probe_box_mask(n), device=dev)
 
     def probe_loss(phi):
         idx = torch.nonzero(mask)
@@ -123,26 +175,25 @@ def main():
         gz = (phi[k + 1, j, i] - phi[k - 1, j, i]) / (2 * h)
         return ((gx ** 2 + gy ** 2 + gz ** 2) * h ** 3).sum()
 
-    def run(precision):
-        solver = gm.GMGPoisson(a, precision=precision)
-        phi = torch.empty_like(a)
-        lam = torch.empty_like(a)
-        grad = torch.empty_like(a)
+    def run_c3(precision):
+        solver = gm.GMGPoisson(a0, precision=precision)
+        phi = torch.empty_like(a0)
+        lam = torch.empty_like(a0)
+        grad = torch.empty_like(a0)
         # dL/dphi of the probe-box loss at the solution (fixed input of the backward)
-        r = solver.solve(f, p.phi_bot, p.phi_top, args.tol, out=phi)
+        solver.solve(f0, p.phi_bot, p.phi_top, args.tol, out=phi)
         leaf = phi.detach().clone().requires_grad_(True)
         probe_loss(leaf).backward()
         gphi = leaf.grad.detach().contiguous()
         del leaf
-
-        info = {}
+        info = {"solves": []}
 
         def step():
-            solver.update_coefficient(a)
-            r1 = solver.solve(f, p.phi_bot, p.phi_top, args.tol, out=phi)
+            solver.update_coefficient(a0)
+            r1 = solver.solve(f0, p.phi_bot, p.phi_top, args.tol, out=phi)
             r2 = solver.solve(gphi, 0.0, 0.0, args.tol, out=lam)
             solver.face_flux_grad_into(phi, lam, p.phi_bot, p.phi_top, grad)
-            info["fwd"], info["adj"] = r1, r2
+            info["solves"] = [r1, r2]
 
         for _ in range(args.warmup):
             step()
@@ -151,14 +202,14 @@ def main():
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ms = (t1 - t0) * 1e3 / args.steps
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        solves = info["solves"]
         # forward solve alone, timed with events on the solver's stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         solve_ms = []
         for _ in range(3):
             e0.record()
-            solver.solve(f, p.phi_bot, p.phi_top, args.tol, out=phi)
+            solver.solve(f0, p.phi_bot, p.phi_top, args.tol, out=phi)
             e1.record()
             e1.synchronize()
             solve_ms.append(e0.elapsed_time(e1))
@@ -170,82 +221,121 @@ def main():
                 step()
             prof = solver.profile_read()
             solver.profile(False)
-        out = dict(ms_per_step=ms, solve_ms=statistics.median(solve_ms), fwd=info["fwd"], adj=info["adj"],
-                   prof=prof, levels=solver.levels)
+        out = dict(ms_per_step=ms, solve_ms=statistics.median(solve_ms), solves=solves, prof=prof,
+                   prof_steps=args.steps, levels=solver.levels, solves_per_step=2)
         del solver, phi, lam, grad, gphi
         torch.cuda.empty_cache()
         return out
 
+    def run_c5(precision):
+        solver = gm.GMGPoisson(a0, precision=precision)
+        phi = torch.zeros_like(a0)
+        a_t = torch.empty_like(a0)
+        f_t = torch.empty_like(f0)
+        state = {"t": 0, "first": True, "solves": []}
+
+        def step():
+            t = state["t"]
+            a_t.copy_(torch.roll(a0, t, dims=0))
+            f_t.copy_(torch.roll(f0, t, dims=0))
+            solver.update_coefficient(a_t)
+            r = solver.solve(f_t, p.phi_bot, p.phi_top, args.tol, out=phi,
+                             x0=None if state["first"] else phi)
+            state["first"] = False
+            state["t"] = t + 1
+            state["solves"].append(r)
+
+        for _ in range(args.warmup):
+            step()
+        state["solves"] = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        solves = list(state["solves"])
+        prof = {}
+        if not args.no_profile:
+            solver.profile(True)
+            solver.profile_reset()
+            for _ in range(2):
+                step()
+            prof = solver.profile_read()
+            solver.profile(False)
+        out = dict(ms_per_step=ms, solve_ms=None, solves=solves, prof=prof, prof_steps=2,
+                   prof_solves=list(state["solves"][-2:]), levels=solver.levels, solves_per_step=1)
+        del solver, phi, a_t, f_t
+        torch.cuda.empty_cache()
+        return out
+
+    run = run_c5 if c5 else run_c3
     log("mixed precision run ...")
     mixed = run("mixed")
-    fwd, adj = mixed["fwd"], mixed["adj"]
-    log(f"mixed: {mixed['ms_per_step']:.2f} ms/step, forward {fwd.iterations} steps "
-        f"(relres {fwd.final_relres:.2e}), adjoint {adj.iterations} steps, solve {mixed['solve_ms']:.2f} ms")
+    its_mixed = [r.iterations for r in mixed["solves"]]
+    log(f"mixed: {mixed['ms_per_step']:.2f} ms/step, iterations {its_mixed}, "
+        f"relres {[float(f'{r.final_relres:.2e}') for r in mixed['solves']]}")
     fp64 = None
     if not args.no_fp64:
         log("fp64 run ...")
         fp64 = run("fp64")
-        log(f"fp64: {fp64['ms_per_step']:.2f} ms/step, forward {fp64['fwd'].iterations} steps, "
-            f"solve {fp64['solve_ms']:.2f} ms")
+        log(f"fp64: {fp64['ms_per_step']:.2f} ms/step, iterations {[r.iterations for r in fp64['solves']]}")
 
-    if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 1 GiB read + 1 GiB written by one device copy")
-        del src, dst
-
-    # -- per-kernel roofline from the event pass --------------------------
+    # -- per-kernel table and roofline from the event pass ------------------
     s = 4
-    its_f, its_a = fwd.iterations, adj.iterations
     restart = 10
-    nvs = nv_sequence(its_f, restart) + nv_sequence(its_a, restart)
+    ps = mixed["prof_steps"]
+    # iterations of the solves inside the profiled pass (c3: the same every step)
+    its_prof = [r.iterations for r in mixed["prof_solves"]] if c5 else its_mixed * ps
+    nvs = [nv for its in its_prof for nv in nv_sequence(its, restart)]
     table = []
     total_bytes = 0.0
     for name, (tot_ms, cnt) in sorted(mixed["prof"].items(), key=lambda kv: -kv[1][0]):
-        bpc = None
-        if "_fine_" in name:
-            bpc = bytes_per_cell(name, s)
-            per_launch = None if bpc is None else bpc * N
-            tb = None if per_launch is None else per_launch * cnt
-        else:
-            tb = None
-            if name.startswith("op_multidot") or name == "axpy_norm":
-                tb = sum(outer_bytes(name, nv, s) for nv in nvs) * N * args.steps
-            elif name.startswith("update"):
-                b_upd = 0.0
-                for its in (its_f, its_a):
-                    left = its
-                    while left > 0:
-                        k = min(left, restart)
-                        b_upd += outer_bytes(name, k, s)
-                        left -= k
-                tb = b_upd * N * args.steps
-            elif outer_bytes(name, 0, s) is not None:
-                tb = outer_bytes(name, 0, s) * N * cnt
+        base, level = split_name(name)
+        tb = None
+        bpl = None
+        if level is not None and level >= 0:
+            bpc = bytes_per_cell(base, level, s)
+            if bpc is not None:
+                bpl = bpc * N / 8 ** level
+                tb = bpl * cnt
+        elif name.startswith("op_multidot") or name == "axpy_norm":
+            tb = sum(outer_bytes(name, nv, s) for nv in nvs) * N
+        elif name.startswith("update"):
+            b_upd = 0.0
+            for its in its_prof:
+                left = its
+                while left > 0:
+                    k = min(left, restart)
+                    b_upd += outer_bytes(name, k, s)
+                    left -= k
+            tb = b_upd * N
+        elif outer_bytes(name, 0, s) is not None:
+            tb = outer_bytes(name, 0, s) * N * cnt
         gbs = tb / (tot_ms * 1e-3) / 1e9 if tb else None
         if tb:
             total_bytes += tb
-        table.append((name, tot_ms / args.steps, cnt // max(args.steps, 1), tot_ms / cnt, gbs))
+        table.append((name, tot_ms / ps, cnt / ps, tot_ms / cnt, gbs, bpl))
     if table:
         log(f"{'kernel':34s} {'ms/step':>9s} {'launch':>7s} {'avg ms':>9s} {'GB/s':>8s}")
-        for name, ms_s, cnt, avg, gbs in table:
-            log(f"{name:34s} {ms_s:9.3f} {cnt:7d} {avg:9.4f} {gbs if gbs else float('nan'):8.0f}")
+        for name, ms_s, cnt, avg, gbs, _ in table:
+            log(f"{name:34s} {ms_s:9.3f} {cnt:7.1f} {avg:9.4f} {gbs if gbs else float('nan'):8.0f}")
     roofline = None
-    dom = next((t for t in table if t[4] is not None), None)
+    dom = next((t for t in table if t[5] is not None), None)
     if dom is not None:
-        name, ms_s, cnt, avg_ms, gbs = dom
+        name, ms_s, cnt, avg_ms, gbs, bpl = dom
+        achieved = bpl / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic() if (name == "gs_fine_f32" and n == 512 and not c5) else None
         roofline = {
             "bound": "hbm",
             "kernel": name,
-            "achieved": round(gbs, 1),
+            "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
-            "frac": round(gbs / PEAK_HBM_GBS, 4),
-            "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
             "avg_launch_ms": round(avg_ms, 5),
-            "bytes_per_launch": bytes_per_cell(name, s) * N if "_fine_" in name else None,
+            "bytes_per_launch": bpl,
             "share_of_step": round(ms_s / mixed["ms_per_step"], 3),
         }
 
@@ -254,18 +344,27 @@ def main():
     if not args.no_cpu_baseline:
         from oracle.fgmres import solve_poisson
         m = args.cpu_n
-        q = make_config(3, n=m)
+        q = make_config(5 if c5 else 3, n=m)
         log(f"cpu baseline: oracle fp64 solve at {m}^3 ...")
         t0 = time.perf_counter()
         res = solve_poisson(q.a, q.f, q.h, q.phi_bot, q.phi_top, tol=args.tol, precision="fp64")
         dt = time.perf_counter() - t0
         cpu = {"value": m ** 3 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-               "sample": (f"one FP64 NumPy oracle solve to {args.tol:g} of the same filament generator at "
-                          f"{m}^3 ({res.iterations} steps, {dt:.1f} s; NumPy element-wise work on one "
-                          f"thread, host has {os.cpu_count()} cpus)")}
+               "sample": (f"one FP64 NumPy oracle solve to {args.tol:g} from a zero guess of the same "
+                          f"{'two-filament' if c5 else 'filament'} generator at {m}^3 ({res.iterations} "
+                          f"steps, {dt:.1f} s; NumPy element-wise work on one thread, host has "
+                          f"{os.cpu_count()} cpus)")}
         log(f"cpu baseline: {dt:.1f}s, {res.iterations} steps")
 
-    value = 2 * N / (mixed["ms_per_step"] * 1e-3)
+    sps = mixed["solves_per_step"]
+    value = sps * N / (mixed["ms_per_step"] * 1e-3)
+    if c5:
+        workload = (f"two filaments {n}^3 time loop, max(a)=1e4, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
+                    "(float32 V-cycle, float64 outer); step = advect (roll) + renewal + warm-started solve")
+    else:
+        workload = (f"filament {n}^3, max(a)=1e4, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
+                    "(float32 V-cycle, float64 outer); step = renewal + forward solve + adjoint "
+                    "solve + dL/da")
     line = {
         "metric": METRIC,
         "value": value,
@@ -280,31 +379,29 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"filament {n}^3, max(a)=1e4, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
-                         "(float32 V-cycle, float64 outer); step = renewal + forward solve + adjoint "
-                         "solve + dL/da"),
+            "workload": workload,
             "grid": [n, n, n],
             "levels": len(mixed["levels"]),
-            "solves_per_step": 2,
+            "solves_per_step": sps,
         },
-        "iterations": {"forward": its_f, "adjoint": its_a},
-        "final_relres": fwd.final_relres,
+        "iterations": its_mixed,
+        "final_relres": [r.final_relres for r in mixed["solves"]],
         "solve_ms": mixed["solve_ms"],
-        "solve_cells_per_s": N / (mixed["solve_ms"] * 1e-3),
-        "model_gbs": (total_bytes / args.steps) / (mixed["ms_per_step"] * 1e-3) / 1e9 if total_bytes else None,
+        "solve_cells_per_s": N / (mixed["solve_ms"] * 1e-3) if mixed["solve_ms"] else None,
+        "model_gbs": (total_bytes / ps) / (mixed["ms_per_step"] * 1e-3) / 1e9 if total_bytes else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     if fp64 is not None:
         line["fp64"] = {
             "ms_per_step": fp64["ms_per_step"],
-            "value": 2 * N / (fp64["ms_per_step"] * 1e-3),
+            "value": sps * N / (fp64["ms_per_step"] * 1e-3),
             "solve_ms": fp64["solve_ms"],
-            "solve_cells_per_s": N / (fp64["solve_ms"] * 1e-3),
-            "iterations": {"forward": fp64["fwd"].iterations, "adjoint": fp64["adj"].iterations},
-            "final_relres": fp64["fwd"].final_relres,
+            "solve_cells_per_s": N / (fp64["solve_ms"] * 1e-3) if fp64["solve_ms"] else None,
+            "iterations": [r.iterations for r in fp64["solves"]],
+            "final_relres": [r.final_relres for r in fp64["solves"]],
         }
-        line["mixed_speedup_vs_fp64"] = fp64["solve_ms"] / mixed["solve_ms"]
+        line["mixed_speedup_vs_fp64"] = fp64["ms_per_step"] / mixed["ms_per_step"]
     print(json.dumps(line), flush=True)
 
 

@@ -57,7 +57,7 @@ struct LevelOffsets {
 struct Layout {
   std::vector<LevelShape> shapes;
   std::vector<LevelOffsets> lv;
-  size_t V, Z, a32, b0, partials, scal, cinv, total;
+  size_t V, Z, a32, b0, partials, scal, cinv, bargs, total;
   size_t tsize;  // bytes of the V-cycle precision
   size_t ldv;    // elements between consecutive Krylov vectors (v_i and z_i)
   size_t hn;     // elements of one colour array of a colour-split finest-level field
@@ -132,6 +132,7 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   L->scal = take((size_t)(L->m * (L->m + 2) + (L->m + 2) + 16) * 8);
   const size_t nc = last.n();
   L->cinv = take(nc * nc * L->tsize);
+  L->bargs = take(sizeof(BottomArgs<double>));
   L->total = off;
   return GMG_OK;
 }
@@ -147,7 +148,12 @@ int bottom_level(const Layout& L) {
   const int nl = (int)L.shapes.size();
   if (nl < 3 || L.shapes.back().n() > BOTTOM_MAX_COARSEST) return -1;
   int l = nl - 1;
-  while (l > 1 && L.shapes[l - 1].n() <= BOTTOM_MAX_CELLS && nl - (l - 1) <= BOTTOM_MAX_LEVELS) --l;
+  size_t cells = L.shapes[l].n();
+  while (l > 1 && L.shapes[l - 1].n() <= BOTTOM_MAX_CELLS && nl - (l - 1) <= BOTTOM_MAX_LEVELS &&
+         cells + L.shapes[l - 1].n() <= (size_t)BOTTOM_LDS_CELLS) {
+    --l;
+    cells += L.shapes[l].n();
+  }
   return l < nl - 1 ? l : -1;
 }
 
@@ -442,11 +448,13 @@ FaceCoef<T> face_coef(gmg_ctx* c, int l) {
   return FaceCoef<T>{wsp<T>(c, o.wx), wsp<T>(c, o.wy), wsp<T>(c, o.wz), wsp<T>(c, o.tp)};
 }
 
-// Profile name of a kernel: base + finest/coarse level + precision (the
-// returned string lives as long as the process).
+// Profile name of a kernel: base + level ("fine" for level 0, "L<l>" for a
+// coarser one, "coarsest") + precision (the returned string lives as long as
+// the process).
 const char* kname(const char* base, int level, size_t tsize) {
   static std::map<std::string, std::string> names;
-  std::string key = std::string(base) + (level == 0 ? "_fine" : "_coarse") + (tsize == 4 ? "_f32" : "_f64");
+  const std::string lv = level == 0 ? "_fine" : (level < 0 ? "_coarsest" : "_L" + std::to_string(level));
+  std::string key = std::string(base) + lv + (tsize == 4 ? "_f32" : "_f64");
   auto it = names.find(key);
   if (it == names.end()) it = names.emplace(key, key).first;
   return it->second.c_str();
@@ -514,28 +522,39 @@ template <typename T>
 void coarse_solve(gmg_ctx* c, const T* b, T* x) {
   const int n = c->nc;
   const Launch lc{dim3((n + NTHREADS - 1) / NTHREADS), dim3(BX, BY, 1), 0};
-  GMG_LAUNCH(c, kname("coarse_solve", 1, sizeof(T)), k_coarse_solve<T>, lc,
+  GMG_LAUNCH(c, kname("coarse_solve", -1, sizeof(T)), k_coarse_solve<T>, lc,
              wsp<const T>(c, c->L.cinv), b, x, n);
 }
 
-// The levels from l0 down to the coarsest in one workgroup (k_vcycle_bottom).
+// The levels from l0 down to the coarsest in one workgroup (k_vcycle_bottom);
+// its arguments were written to the workspace at set-up.
 template <typename T>
-void vcycle_bottom(gmg_ctx* c, int l0) {
-  const int nl = (int)c->L.shapes.size();
+void vcycle_bottom(gmg_ctx* c) {
+  const Launch one{dim3(1), dim3(BottomThreads<T>::value, 1, 1), 0};
+  GMG_LAUNCH(c, kname("vcycle_bottom", c->bottom_from, sizeof(T)), k_vcycle_bottom<T>, one,
+             wsp<const BottomArgs<T>>(c, c->L.bargs));
+}
+
+// Arguments of the bottom kernel (fixed for the life of the context).
+template <typename T>
+int write_bottom_args(gmg_ctx* c) {
+  const int nl = (int)c->L.shapes.size(), l0 = c->bottom_from;
+  if (l0 < 0) return GMG_OK;
   BottomArgs<T> A{};
   A.nlev = nl - l0;
   for (int q = 0; q < A.nlev; ++q) {
     const int l = l0 + q;
     A.co[q] = face_coef<T>(c, l);
-    A.x[q] = wsp<T>(c, c->L.lv[l].x);
-    A.b[q] = wsp<T>(c, c->L.lv[l].b);
     A.g[q] = c->L.shapes[l].geom();
   }
+  A.x0 = wsp<T>(c, c->L.lv[l0].x);
+  A.b0 = wsp<T>(c, c->L.lv[l0].b);
   A.Ainv = wsp<const T>(c, c->L.cinv);
   A.nu_pre = c->opt.nu_pre;
   A.nu_post = c->opt.nu_post;
-  const Launch one{dim3(1), dim3(BOTTOM_THREADS, 1, 1), 0};
-  GMG_LAUNCH(c, kname("vcycle_bottom", 1, sizeof(T)), k_vcycle_bottom<T>, one, A);
+  note(c, hipMemcpyAsync(wsp<BottomArgs<T>>(c, c->L.bargs), &A, sizeof(A), hipMemcpyHostToDevice, c->stream));
+  note(c, hipStreamSynchronize(c->stream));
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }
 
 // Levels >= 1 (face coefficients), right side in lv[l].b, result in lv[l].x.
@@ -550,7 +569,7 @@ void vcycle_coarse(gmg_ctx* c, int l) {
     return;
   }
   if (l == c->bottom_from) {
-    vcycle_bottom<T>(c, l);
+    vcycle_bottom<T>(c);
     return;
   }
   const FaceCoef<T> co = face_coef<T>(c, l);
@@ -873,7 +892,8 @@ int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const dou
     delete c;
     return GMG_ERR_HIP;
   }
-  const int r = build_hierarchy(c);
+  int r = c->mixed ? write_bottom_args<float>(c) : write_bottom_args<double>(c);
+  if (r == GMG_OK) r = build_hierarchy(c);
   if (r != GMG_OK) {
     gmg_destroy(c);
     return r;

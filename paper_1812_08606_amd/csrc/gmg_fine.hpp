@@ -175,8 +175,49 @@ __device__ __forceinline__ void split_pair(const T* __restrict__ X, size_t hn, s
 // Residual and restriction from the colour-split iterate and right side:
 // b_coarse = mean over the 8 children of (b - A x).  Lane tx owns pair m
 // (= the coarse x-index) of fine row j and marches the fine planes of its
-// z-chunk, 2 per coarse plane; the two fine rows of a coarse row are summed
-// through LDS.  kc counts coarse planes.
+// z-chunk, 2 per coarse plane, keeping x and a of the pair on planes k-1, k
+// in registers; the loads of both fine planes of a coarse plane are issued in
+// one branch-free group with clamped addresses.  The two fine rows of a
+// coarse row are summed through LDS.  kc counts coarse planes.
+template <typename T>
+struct ResidSide {
+  T xt0, xt1, at0, at1;  // pair on plane k+1
+  T xs0, xs1, as0, as1;  // pair on row j-1
+  T xn0, xn1, an0, an1;  // pair on row j+1
+  T xw, aw, xe, ae;      // cells 2m-1 and 2m+2
+  T b0, b1;              // right side of the pair
+};
+
+template <typename T>
+__device__ __forceinline__ void resid_side_load(ResidSide<T>& S, const T* __restrict__ X, const T* __restrict__ B,
+                                                const T* __restrict__ a, const Geom& g, size_t hn, int H, int m,
+                                                int j, int k, bool act) {
+  const size_t ty = (size_t)H, tz = (size_t)H * g.ny;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const int kk = act ? k : 0, jj = act ? j : 0, mm = act ? m : 0;
+  const int p = (jj + kk) & 1;  // colour of cell 2m on row j, plane k
+  const size_t q = sidx(g, mm, jj, kk), cn = 2 * q;
+  const bool up = kk + 1 < g.nz;
+  const size_t qt = up ? q + tz : q, ct = up ? cn + sz : cn;
+  const size_t qs = jj > 0 ? q - ty : q, cs = jj > 0 ? cn - sy : cn;
+  const size_t qn = jj < g.ny - 1 ? q + ty : q, cnn = jj < g.ny - 1 ? cn + sy : cn;
+  split_pair(X, hn, qt, p ^ 1, S.xt0, S.xt1);
+  S.at0 = a[ct];
+  S.at1 = a[ct + 1];
+  split_pair(X, hn, qs, p ^ 1, S.xs0, S.xs1);
+  S.as0 = a[cs];
+  S.as1 = a[cs + 1];
+  split_pair(X, hn, qn, p ^ 1, S.xn0, S.xn1);
+  S.an0 = a[cnn];
+  S.an1 = a[cnn + 1];
+  // cell 2m-1 has colour p^1, cell 2m+2 colour p (clamped to the pair)
+  S.xw = X[(mm > 0 ? q - 1 : q) + (size_t)(p ^ 1) * hn];
+  S.aw = a[mm > 0 ? cn - 1 : cn];
+  S.xe = X[(mm < H - 1 ? q + 1 : q) + (size_t)p * hn];
+  S.ae = a[mm < H - 1 ? cn + 2 : cn];
+  split_pair(B, hn, q, p, S.b0, S.b1);
+}
+
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_split(const T* __restrict__ X, const T* __restrict__ B,
                                                                    const T* __restrict__ a, Geom g, size_t hn,
@@ -187,96 +228,67 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_split(const T* __re
   const int m = tl.x * BX + threadIdx.x;
   const int j = tl.y * BY + threadIdx.y;
   const bool act = m < H && j < g.ny;
-  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
-  const size_t ty = (size_t)H, tz = (size_t)H * g.ny;
+  const size_t tz = (size_t)H * g.ny, sz = (size_t)g.nx * g.ny;
   const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
   const int K0 = tl.z * kc, K1 = min(NZ, K0 + kc);
-  const int k0 = 2 * K0, k1 = 2 * K1;
   const bool hw = m > 0, he = m < H - 1, hs = j > 0, hn_ = j < g.ny - 1;
-  const int lane = threadIdx.x;
-  size_t cn = act ? 2 * sidx(g, m, j, k0) : 0;
-  size_t q = act ? sidx(g, m, j, k0) : 0;
-  // pair registers: [0] cell 2m, [1] cell 2m+1, planes below / centre
-  T xb[2] = {T(0), T(0)}, xc[2] = {T(0), T(0)}, ab[2] = {T(0), T(0)}, ac[2] = {T(0), T(0)};
-  if (act) {
-    split_pair(X, hn, q, (j + k0) & 1, xc[0], xc[1]);
+  // pair registers: [0] cell 2m, [1] cell 2m+1, planes k-1 and k
+  T xb[2], xc[2], ab[2], ac[2];
+  {
+    const int k0 = 2 * K0;
+    const size_t q = act ? sidx(g, m, j, k0) : 0, cn = 2 * q;
+    const int p = act ? (j + k0) & 1 : 0;
+    const bool dn = act && k0 > 0;
+    split_pair(X, hn, q, p, xc[0], xc[1]);
+    split_pair(X, hn, dn ? q - tz : q, p ^ 1, xb[0], xb[1]);
     ac[0] = a[cn];
     ac[1] = a[cn + 1];
-    if (k0 > 0) {
-      split_pair(X, hn, q - tz, (j + k0 - 1) & 1, xb[0], xb[1]);
-      ab[0] = a[cn - sz];
-      ab[1] = a[cn - sz + 1];
-    }
+    ab[0] = a[dn ? cn - sz : cn];
+    ab[1] = a[dn ? cn - sz + 1 : cn + 1];
   }
-  T acc = T(0);
-  for (int k = k0; k < k1; ++k) {
+  auto plane = [&](int k, const ResidSide<T>& S) -> T {
     const bool top = k == g.nz - 1;
-    const int p = (j + k) & 1;
-    T xt[2] = {T(0), T(0)}, at[2] = {T(0), T(0)};
-    if (act && !top) {
-      split_pair(X, hn, q + tz, p ^ 1, xt[0], xt[1]);
-      at[0] = a[cn + sz];
-      at[1] = a[cn + sz + 1];
-    }
-    T xw = __shfl_up(xc[1], 1, 64), aw = __shfl_up(ac[1], 1, 64);
-    T xe = __shfl_down(xc[0], 1, 64), ae = __shfl_down(ac[0], 1, 64);
-    if (act && lane == 0 && hw) {
-      xw = X[q - 1 + (size_t)(p ^ 1) * hn];  // right cell of pair m-1: colour p^1
-      aw = a[cn - 1];
-    }
-    if (act && lane == BX - 1 && he) {
-      xe = X[q + 1 + (size_t)p * hn];  // left cell of pair m+1: colour p
-      ae = a[cn + 2];
-    }
+    const T xt[2] = {S.xt0, S.xt1}, at[2] = {S.at0, S.at1};
+    const T xs[2] = {S.xs0, S.xs1}, as_[2] = {S.as0, S.as1};
+    const T xn[2] = {S.xn0, S.xn1}, an[2] = {S.an0, S.an1};
+    const T bv[2] = {S.b0, S.b1};
     T rsum = T(0);
-    if (act) {
-      T xs[2] = {T(0), T(0)}, as_[2] = {T(0), T(0)}, xn[2] = {T(0), T(0)}, an[2] = {T(0), T(0)};
-      if (hs) {
-        split_pair(X, hn, q - ty, p ^ 1, xs[0], xs[1]);
-        as_[0] = a[cn - sy];
-        as_[1] = a[cn - sy + 1];
-      }
-      if (hn_) {
-        split_pair(X, hn, q + ty, p ^ 1, xn[0], xn[1]);
-        an[0] = a[cn + sy];
-        an[1] = a[cn + sy + 1];
-      }
-      T bv[2];
-      split_pair(B, hn, q, p, bv[0], bv[1]);
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const T acv = ac[e], xcv = xc[e];
-        const T xo = e == 0 ? xw : xe, ao = e == 0 ? aw : ae;
-        const bool ho = e == 0 ? hw : he;
-        T Ax = (acv + ac[1 - e]) * hx * (xcv - xc[1 - e]);
-        Ax += ho ? (acv + ao) * hx * (xcv - xo) : T(0);
-        Ax += hs ? (acv + as_[e]) * hy * (xcv - xs[e]) : T(0);
-        Ax += hn_ ? (acv + an[e]) * hy * (xcv - xn[e]) : T(0);
-        Ax += k > 0 ? (acv + ab[e]) * hz * (xcv - xb[e]) : pz * acv * xcv;
-        Ax += !top ? (acv + at[e]) * hz * (xcv - xt[e]) : pz * acv * xcv;
-        rsum += bv[e] - Ax;
-      }
+    for (int e = 0; e < 2; ++e) {
+      const T acv = ac[e], xcv = xc[e];
+      const T xo = e == 0 ? S.xw : S.xe, ao = e == 0 ? S.aw : S.ae;
+      const bool ho = e == 0 ? hw : he;
+      T Ax = (acv + ac[1 - e]) * hx * (xcv - xc[1 - e]);
+      Ax += ho ? (acv + ao) * hx * (xcv - xo) : T(0);
+      Ax += hs ? (acv + as_[e]) * hy * (xcv - xs[e]) : T(0);
+      Ax += hn_ ? (acv + an[e]) * hy * (xcv - xn[e]) : T(0);
+      Ax += k > 0 ? (acv + ab[e]) * hz * (xcv - xb[e]) : pz * acv * xcv;
+      Ax += !top ? (acv + at[e]) * hz * (xcv - xt[e]) : pz * acv * xcv;
+      rsum += bv[e] - Ax;
+    }
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        xb[e] = xc[e];
-        xc[e] = xt[e];
-        ab[e] = ac[e];
-        ac[e] = at[e];
-      }
-      cn += sz;
-      q += tz;
+    for (int e = 0; e < 2; ++e) {
+      xb[e] = xc[e];
+      xc[e] = xt[e];
+      ab[e] = ac[e];
+      ac[e] = at[e];
     }
-    acc += rsum;
-    if (k & 1) {  // both fine planes of coarse plane k/2 done: add the row pair
-      part[threadIdx.y][threadIdx.x] = acc;
-      __syncthreads();
-      if (!(threadIdx.y & 1) && act) {
-        const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
-        bc[((size_t)(k >> 1) * NY + (j >> 1)) * H + m] = tot * T(0.125);
-      }
-      __syncthreads();
-      acc = T(0);
+    return rsum;
+  };
+  for (int K = K0; K < K1; ++K) {
+    ResidSide<T> S0, S1;
+    resid_side_load(S0, X, B, a, g, hn, H, m, j, 2 * K, act);
+    resid_side_load(S1, X, B, a, g, hn, H, m, j, 2 * K + 1, act);
+    T acc = plane(2 * K, S0);
+    acc += plane(2 * K + 1, S1);
+    // both fine planes of coarse plane K done: add the row pair
+    part[threadIdx.y][threadIdx.x] = acc;
+    __syncthreads();
+    if (!(threadIdx.y & 1) && act) {
+      const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
+      bc[((size_t)K * NY + (j >> 1)) * H + m] = tot * T(0.125);
     }
+    __syncthreads();
   }
 }
 

@@ -201,10 +201,56 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_first(T* __restrict__ x, const 
 }
 
 // Red-black half-sweep of one colour on a coarse level (stored face
-// coefficients; even nx): the lane-pair scheme of k_gs_pair.  The face
-// between the pair's right cell and the next pair is the adjacent lane's west
-// face.  FIRST: the first pre-smoothing half-sweep from x = 0 (cells of the
-// colour get b / D, the others 0; x is not read).
+// coefficients; even nx).  Lane tx owns the x-pair (2m, 2m+1) of row j; on
+// every plane exactly one cell of the pair has the colour being updated.
+// The thread marches its z-chunk keeping x and the bottom faces of the pair
+// in registers; the loads of two planes are issued in one branch-free group
+// with clamped addresses (values behind a missing face get zero weight).
+// Only cells of the other colour are read and none of them is written, so
+// the update is order-free.  FIRST: the first pre-smoothing half-sweep from
+// x = 0 (cells of the colour get b / D, the others 0; x is not read).
+template <typename T>
+struct FaceSide {
+  T xt0, xt1;        // x of the pair on plane k+1
+  T wt0, wt1;        // top faces of the pair (wz on plane k+1, or the top plate's)
+  T wx0, wx1, wxe;   // x-faces: west of cell 2m, between, east of cell 2m+1
+  T xw, xe;          // x of cells 2m-1 and 2m+2
+  T ws, wn, xs, xn;  // y-faces and y-neighbours of the updated cell
+  T b;               // right side of the updated cell
+};
+
+template <typename T, bool FIRST>
+__device__ __forceinline__ void face_side_load(FaceSide<T>& S, const T* __restrict__ x, const T* __restrict__ b,
+                                               const FaceCoef<T>& co, const Geom& g, int i0, int j, int k,
+                                               int colour, bool act) {
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const int kk = act ? k : 0, jj = act ? j : 0, ii = act ? i0 : 0;
+  const size_t c = ((size_t)kk * g.ny + jj) * g.nx + ii;
+  const int e = (colour + ii + jj + kk) & 1;
+  const size_t ce = c + e;
+  const bool up = kk + 1 < g.nz;
+  const T* wtp = up ? co.wz + c + sz : co.tp + (size_t)jj * g.nx + ii;
+  S.wt0 = wtp[0];
+  S.wt1 = wtp[1];
+  S.wx0 = co.wx[c];
+  S.wx1 = co.wx[c + 1];
+  S.wxe = co.wx[ii + 2 < g.nx ? c + 2 : c + 1];
+  S.ws = co.wy[ce];
+  S.wn = co.wy[jj < g.ny - 1 ? ce + sy : ce];
+  S.b = b[ce];
+  if (!FIRST) {
+    const size_t ct = up ? c + sz : c;
+    S.xt0 = x[ct];
+    S.xt1 = x[ct + 1];
+    S.xw = x[ii > 0 ? c - 1 : c];
+    S.xe = x[ii + 2 < g.nx ? c + 2 : c];
+    S.xs = x[jj > 0 ? ce - sy : ce];
+    S.xn = x[jj < g.ny - 1 ? ce + sy : ce];
+  } else {
+    S.xt0 = S.xt1 = S.xw = S.xe = S.xs = S.xn = T(0);
+  }
+}
+
 template <typename T, bool FIRST>
 __global__ __launch_bounds__(NTHREADS) void k_gs_pair_face(T* __restrict__ x, const T* __restrict__ b,
                                                            FaceCoef<T> co, Geom g, int kc, int colour) {
@@ -213,183 +259,213 @@ __global__ __launch_bounds__(NTHREADS) void k_gs_pair_face(T* __restrict__ x, co
   const int j = tl.y * BY + threadIdx.y;
   const int i0 = 2 * m;
   const bool act = i0 < g.nx && j < g.ny;
-  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const size_t sz = (size_t)g.nx * g.ny;
   const T ix = (T)g.ihx2, iy = (T)g.ihy2, iz = (T)g.ihz2;
   const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
   const bool hs = j > 0, hn = j < g.ny - 1;
   const bool hwo = i0 > 0, heo = i0 + 2 < g.nx;
-  const int lane = threadIdx.x;
-  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
-  T xc0 = T(0), xc1 = T(0), xb0 = T(0), xb1 = T(0), wb0 = T(0), wb1 = T(0);
-  if (act) {
+  // x of the pair on planes k-1, k and the pair's bottom faces on plane k
+  T xb0 = T(0), xb1 = T(0), xc0 = T(0), xc1 = T(0), wb0, wb1;
+  {
+    const size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
+    const size_t cb = (act && k0 > 0) ? c - sz : c;
     wb0 = co.wz[c];
     wb1 = co.wz[c + 1];
     if (!FIRST) {
       xc0 = x[c];
       xc1 = x[c + 1];
-      if (k0 > 0) {
-        xb0 = x[c - sz];
-        xb1 = x[c - sz + 1];
-      }
+      xb0 = x[cb];
+      xb1 = x[cb + 1];
     }
   }
-  for (int k = k0; k < k1; ++k) {
+  auto plane = [&](int k, const FaceSide<T>& S) {
     const bool top = k == g.nz - 1;
-    T xt0 = T(0), xt1 = T(0), wt0 = T(0), wt1 = T(0), wx0 = T(0), wx1 = T(0);
+    const int e = (colour + i0 + j + k) & 1;
+    const T ww = e ? S.wx1 : (hwo ? S.wx0 : T(0)), we = e ? (heo ? S.wxe : T(0)) : S.wx1;
+    const T ws = hs ? S.ws : T(0), wn = hn ? S.wn : T(0);
+    const T wb = e ? wb1 : wb0, wt = e ? S.wt1 : S.wt0;
+    const T D = (ww + we) * ix + (ws + wn) * iy + (k > 0 ? wb : T(2) * wb) * iz + (top ? T(2) * wt : wt) * iz;
     if (act) {
-      if (!top) {
-        if (!FIRST) {
-          xt0 = x[c + sz];
-          xt1 = x[c + sz + 1];
-        }
-        wt0 = co.wz[c + sz];
-        wt1 = co.wz[c + sz + 1];
-      } else {
-        wt0 = co.tp[(size_t)j * g.nx + i0];
-        wt1 = co.tp[(size_t)j * g.nx + i0 + 1];
-      }
-      wx0 = co.wx[c];
-      wx1 = co.wx[c + 1];
-    }
-    T wxe = __shfl_down(wx0, 1, 64);
-    if (act && lane == BX - 1 && heo) wxe = co.wx[c + 2];
-    T xwo = T(0), xeo = T(0);
-    if (!FIRST) {
-      xwo = __shfl_up(xc1, 1, 64);
-      xeo = __shfl_down(xc0, 1, 64);
-      if (act && lane == 0 && hwo) xwo = x[c - 1];
-      if (act && lane == BX - 1 && heo) xeo = x[c + 2];
-    }
-    if (act) {
-      const int e = (colour + i0 + j + k) & 1;
-      const size_t ce = c + e;
-      const T ww = e ? wx1 : (hwo ? wx0 : T(0)), we = e ? (heo ? wxe : T(0)) : wx1;
-      const T ws = hs ? co.wy[ce] : T(0), wn = hn ? co.wy[ce + sy] : T(0);
-      const T wb = e ? wb1 : wb0, wt = e ? wt1 : wt0;
-      const T D = (ww + we) * ix + (ws + wn) * iy + (k > 0 ? wb : T(2) * wb) * iz + (top ? T(2) * wt : wt) * iz;
+      const size_t c = ((size_t)k * g.ny + j) * g.nx + i0;
       if (FIRST) {
-        x[ce] = b[ce] * recip(D);
+        x[c + e] = S.b * recip(D);
         x[c + 1 - e] = T(0);
       } else {
-        const T xw = e ? xc0 : xwo, xe = e ? xeo : xc1;
-        const T xs = hs ? x[ce - sy] : T(0), xn = hn ? x[ce + sy] : T(0);
-        const T xbv = e ? xb1 : xb0, xtv = e ? xt1 : xt0;
-        T off = (ww * xw + we * xe) * ix + (ws * xs + wn * xn) * iy;
+        const T xw = e ? xc0 : S.xw, xe = e ? S.xe : xc1;
+        const T xbv = e ? xb1 : xb0, xtv = e ? S.xt1 : S.xt0;
+        T off = (ww * xw + we * xe) * ix + (ws * S.xs + wn * S.xn) * iy;
         off += k > 0 ? wb * iz * xbv : T(0);
         off += !top ? wt * iz * xtv : T(0);
-        x[ce] = (b[ce] + off) * recip(D);
+        x[c + e] = (S.b + off) * recip(D);
       }
     }
     xb0 = xc0;
     xb1 = xc1;
-    xc0 = xt0;
-    xc1 = xt1;
-    wb0 = wt0;
-    wb1 = wt1;
-    c += act ? sz : 0;
+    xc0 = S.xt0;
+    xc1 = S.xt1;
+    wb0 = S.wt0;
+    wb1 = S.wt1;
+  };
+  for (int k = k0; k < k1; k += 2) {
+    FaceSide<T> S0, S1;
+    face_side_load<T, FIRST>(S0, x, b, co, g, i0, j, k, colour, act);
+    face_side_load<T, FIRST>(S1, x, b, co, g, i0, j, min(k + 1, k1 - 1), colour, act);
+    plane(k, S0);
+    if (k + 1 < k1) plane(k + 1, S1);
   }
 }
 
 // Residual and restriction on a coarse level (stored face coefficients):
 // b_coarse = mean over the 8 children of (b - A x).  Lane tx owns the fine
 // x-pair (2I, 2I+1) of fine row j = 4 by + ty and marches the fine planes of
-// its z-chunk (2 per coarse plane); the two fine rows of a coarse row are
-// summed through LDS.  Needs even nx, ny, nz; kc counts coarse planes.
+// its z-chunk, 2 per coarse plane, their loads issued in one branch-free
+// group with clamped addresses; the two fine rows of a coarse row are summed
+// through LDS.  Needs even nx, ny, nz; kc counts coarse planes.
+template <typename T>
+struct FaceResidSide {
+  T xt0, xt1, wt0, wt1;      // x of the pair on plane k+1; top faces of the pair
+  T wx0, wx1, wxe, xw, xe;   // x-faces west / between / east; x of cells 2I-1, 2I+2
+  T ws0, ws1, xs0, xs1;      // south faces and neighbours of both cells
+  T wn0, wn1, xn0, xn1;      // north faces and neighbours of both cells
+  T b0, b1;
+};
+
+template <typename T>
+__device__ __forceinline__ void face_resid_load(FaceResidSide<T>& S, const T* __restrict__ x,
+                                                const T* __restrict__ b, const FaceCoef<T>& co, const Geom& g,
+                                                int i0, int j, int k, bool act) {
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const int kk = act ? k : 0, jj = act ? j : 0, ii = act ? i0 : 0;
+  const size_t c = ((size_t)kk * g.ny + jj) * g.nx + ii;
+  const bool up = kk + 1 < g.nz;
+  const size_t ct = up ? c + sz : c;
+  const T* wtp = up ? co.wz + c + sz : co.tp + (size_t)jj * g.nx + ii;
+  const size_t cs = jj > 0 ? c - sy : c, cn = jj < g.ny - 1 ? c + sy : c;
+  S.xt0 = x[ct];
+  S.xt1 = x[ct + 1];
+  S.wt0 = wtp[0];
+  S.wt1 = wtp[1];
+  S.wx0 = co.wx[c];
+  S.wx1 = co.wx[c + 1];
+  S.wxe = co.wx[ii + 2 < g.nx ? c + 2 : c + 1];
+  S.xw = x[ii > 0 ? c - 1 : c];
+  S.xe = x[ii + 2 < g.nx ? c + 2 : c];
+  S.ws0 = co.wy[c];
+  S.ws1 = co.wy[c + 1];
+  S.xs0 = x[cs];
+  S.xs1 = x[cs + 1];
+  S.wn0 = co.wy[cn];
+  S.wn1 = co.wy[cn + 1];
+  S.xn0 = x[cn];
+  S.xn1 = x[cn + 1];
+  S.b0 = b[c];
+  S.b1 = b[c + 1];
+}
+
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_face(const T* __restrict__ x, const T* __restrict__ b,
                                                                   FaceCoef<T> co, Geom g, T* __restrict__ bc,
                                                                   int kc) {
-  const Tile tl = xcd_tile();
   __shared__ T part[BY][BX];
+  const Tile tl = xcd_tile();
   const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
   const int I = tl.x * BX + threadIdx.x;
   const int j = tl.y * BY + threadIdx.y;
   const bool act = I < NX && j < g.ny;
   const int i0 = 2 * I;
-  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const size_t sz = (size_t)g.nx * g.ny;
   const T ix = (T)g.ihx2, iy = (T)g.ihy2, iz = (T)g.ihz2;
   const int K0 = tl.z * kc, K1 = min(NZ, K0 + kc);
-  const int k0 = 2 * K0, k1 = 2 * K1;
   const bool hw = i0 > 0, he = i0 + 2 < g.nx, hs = j > 0, hn = j < g.ny - 1;
-  T xb[2] = {T(0), T(0)}, xc[2] = {T(0), T(0)}, wb[2] = {T(0), T(0)};
-  size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
-  if (act) {
-    for (int e = 0; e < 2; ++e) {
-      xc[e] = x[c + e];
-      wb[e] = co.wz[c + e];
-      if (k0 > 0) xb[e] = x[c + e - sz];
-    }
+  T xb[2], xc[2], wb[2];
+  {
+    const int k0 = 2 * K0;
+    const size_t c = act ? ((size_t)k0 * g.ny + j) * g.nx + i0 : 0;
+    const size_t cb = (act && k0 > 0) ? c - sz : c;
+    xc[0] = x[c];
+    xc[1] = x[c + 1];
+    xb[0] = x[cb];
+    xb[1] = x[cb + 1];
+    wb[0] = co.wz[c];
+    wb[1] = co.wz[c + 1];
   }
-  T acc = T(0);
-  for (int k = k0; k < k1; ++k) {
+  auto plane = [&](int k, const FaceResidSide<T>& S) -> T {
     const bool top = k == g.nz - 1;
+    const T xt[2] = {S.xt0, S.xt1}, wt[2] = {S.wt0, S.wt1};
+    const T wsv[2] = {S.ws0, S.ws1}, xs[2] = {S.xs0, S.xs1};
+    const T wnv[2] = {S.wn0, S.wn1}, xn[2] = {S.xn0, S.xn1};
+    const T bv[2] = {S.b0, S.b1};
     T rsum = T(0);
-    T xt[2] = {T(0), T(0)}, wt[2] = {T(0), T(0)};
-    if (act) {
-      for (int e = 0; e < 2; ++e) {
-        xt[e] = top ? T(0) : x[c + e + sz];
-        wt[e] = top ? co.tp[(size_t)j * g.nx + i0 + e] : co.wz[c + e + sz];
-      }
-      const T wx0 = co.wx[c], wx1 = co.wx[c + 1], wx2 = he ? co.wx[c + 2] : T(0);
-      const T xw = hw ? x[c - 1] : T(0), xe = he ? x[c + 2] : T(0);
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const size_t ce = c + e;
-        const T xcv = xc[e];
-        T Ax = e == 0 ? (hw ? wx0 * ix * (xcv - xw) : T(0)) + wx1 * ix * (xcv - xc[1])
-                      : wx1 * ix * (xcv - xc[0]) + (he ? wx2 * ix * (xcv - xe) : T(0));
-        Ax += hs ? co.wy[ce] * iy * (xcv - x[ce - sy]) : T(0);
-        Ax += hn ? co.wy[ce + sy] * iy * (xcv - x[ce + sy]) : T(0);
-        Ax += k > 0 ? wb[e] * iz * (xcv - xb[e]) : T(2) * wb[e] * iz * xcv;
-        Ax += !top ? wt[e] * iz * (xcv - xt[e]) : T(2) * wt[e] * iz * xcv;
-        rsum += b[ce] - Ax;
-      }
+    for (int e = 0; e < 2; ++e) {
+      const T xcv = xc[e];
+      T Ax = e == 0 ? (hw ? S.wx0 * ix * (xcv - S.xw) : T(0)) + S.wx1 * ix * (xcv - xc[1])
+                    : S.wx1 * ix * (xcv - xc[0]) + (he ? S.wxe * ix * (xcv - S.xe) : T(0));
+      Ax += hs ? wsv[e] * iy * (xcv - xs[e]) : T(0);
+      Ax += hn ? wnv[e] * iy * (xcv - xn[e]) : T(0);
+      Ax += k > 0 ? wb[e] * iz * (xcv - xb[e]) : T(2) * wb[e] * iz * xcv;
+      Ax += !top ? wt[e] * iz * (xcv - xt[e]) : T(2) * wt[e] * iz * xcv;
+      rsum += bv[e] - Ax;
+    }
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        xb[e] = xc[e];
-        xc[e] = xt[e];
-        wb[e] = wt[e];
-      }
-      c += sz;
+    for (int e = 0; e < 2; ++e) {
+      xb[e] = xc[e];
+      xc[e] = xt[e];
+      wb[e] = wt[e];
     }
-    acc += rsum;
-    if (k & 1) {
-      part[threadIdx.y][threadIdx.x] = acc;
-      __syncthreads();
-      if (!(threadIdx.y & 1) && act) {
-        const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
-        bc[((size_t)(k >> 1) * NY + (j >> 1)) * NX + I] = tot * T(0.125);
-      }
-      __syncthreads();
-      acc = T(0);
+    return rsum;
+  };
+  for (int K = K0; K < K1; ++K) {
+    FaceResidSide<T> S0, S1;
+    face_resid_load(S0, x, b, co, g, i0, j, 2 * K, act);
+    face_resid_load(S1, x, b, co, g, i0, j, 2 * K + 1, act);
+    T acc = plane(2 * K, S0);
+    acc += plane(2 * K + 1, S1);
+    part[threadIdx.y][threadIdx.x] = acc;
+    __syncthreads();
+    if (!(threadIdx.y & 1) && act) {
+      const T tot = acc + part[threadIdx.y + 1][threadIdx.x];
+      bc[((size_t)K * NY + (j >> 1)) * NX + I] = tot * T(0.125);
     }
+    __syncthreads();
   }
 }
 
 // The bottom of the V-cycle in one workgroup: every level from lb down to
 // the coarsest (all small) -- smoothing, residual and restriction, the
 // direct coarsest solve, prolongation and post-smoothing -- with block
-// barriers between the phases instead of kernel launches.  The right side of
-// level lb is read from its buffer and its iterate written to its buffer.
+// barriers between the phases instead of kernel launches.  The iterates and
+// right sides of these levels live in LDS; the right side of level lb is
+// read from b0 and its iterate written to x0 at the end.  The arguments sit
+// in device memory (written once at set-up) so that the per-level fields
+// are read with scalar loads.
 constexpr int BOTTOM_MAX_LEVELS = 10;
-constexpr int BOTTOM_THREADS = 1024;
+// threads of the bottom workgroup: 1024 in float32; 512 in float64, where
+// 1024 threads would leave too few registers per thread
+template <typename T>
+struct BottomThreads {
+  static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
+};
+constexpr int BOTTOM_LDS_CELLS = 4704;  // >= 4096 * (1 + 1/8 + 1/64 + ...)
 
 template <typename T>
 struct BottomArgs {
   FaceCoef<T> co[BOTTOM_MAX_LEVELS];
-  T* x[BOTTOM_MAX_LEVELS];
-  T* b[BOTTOM_MAX_LEVELS];
   Geom g[BOTTOM_MAX_LEVELS];
+  T* x0;
+  const T* b0;
   const T* Ainv;
   int nlev;  // levels handled, the last one the coarsest
   int nu_pre, nu_post;
 };
 
+__device__ __forceinline__ int geom_cells(const Geom& g) { return g.nx * g.ny * g.nz; }
+
 template <typename T>
 __device__ __forceinline__ void bottom_half_sweep(T* __restrict__ x, const T* __restrict__ b, const FaceCoef<T>& co,
                                                   const Geom& g, int colour, bool from_zero) {
-  const int n = g.nx * g.ny * g.nz;
-  for (int c = threadIdx.x; c < n; c += BOTTOM_THREADS) {
+  const int n = geom_cells(g);
+  for (int c = threadIdx.x; c < n; c += BottomThreads<T>::value) {
     const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
     if (((i + j + k) & 1) != colour) {
       if (from_zero) x[c] = T(0);
@@ -408,59 +484,78 @@ __device__ __forceinline__ void bottom_half_sweep(T* __restrict__ x, const T* __
 }
 
 template <typename T>
-__global__ __launch_bounds__(BOTTOM_THREADS) void k_vcycle_bottom(BottomArgs<T> A) {
-  const int L = A.nlev - 1;  // index of the coarsest level
+__global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const BottomArgs<T>* __restrict__ A) {
+  __shared__ T lx[BOTTOM_LDS_CELLS], lb[BOTTOM_LDS_CELLS];
+  const int L = A->nlev - 1;  // index of the coarsest level
+  const int nu_pre = A->nu_pre, nu_post = A->nu_post;
+  {
+    const int n0 = geom_cells(A->g[0]);
+    for (int c = threadIdx.x; c < n0; c += BottomThreads<T>::value) lb[c] = A->b0[c];
+    __syncthreads();
+  }
+  int off = 0;  // LDS offset of level l
   for (int l = 0; l < L; ++l) {
-    const Geom& g = A.g[l];
-    bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 0, true);  // red from x = 0 (black set to 0)
-    if (A.nu_pre == 0) {
+    const Geom g = A->g[l];
+    const FaceCoef<T> co = A->co[l];
+    T* x = lx + off;
+    T* b = lb + off;
+    bottom_half_sweep<T>(x, b, co, g, 0, true);  // red from x = 0 (black set to 0)
+    if (nu_pre == 0) {
       __syncthreads();
-      const int n = g.nx * g.ny * g.nz;
-      for (int c = threadIdx.x; c < n; c += BOTTOM_THREADS) A.x[l][c] = T(0);
+      for (int c = threadIdx.x; c < geom_cells(g); c += BottomThreads<T>::value) x[c] = T(0);
     }
     __syncthreads();
-    for (int it = 0; it < A.nu_pre; ++it) {
+    for (int it = 0; it < nu_pre; ++it) {
       if (it > 0) {
-        bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 0, false);
+        bottom_half_sweep<T>(x, b, co, g, 0, false);
         __syncthreads();
       }
-      bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 1, false);
+      bottom_half_sweep<T>(x, b, co, g, 1, false);
       __syncthreads();
     }
     // residual and restriction into b of level l+1
-    const Geom& gc = A.g[l + 1];
-    const int nc = gc.nx * gc.ny * gc.nz;
-    for (int C = threadIdx.x; C < nc; C += BOTTOM_THREADS) {
+    const Geom gc = A->g[l + 1];
+    T* bc = lb + off + geom_cells(g);
+    const int nc = geom_cells(gc);
+    for (int C = threadIdx.x; C < nc; C += BottomThreads<T>::value) {
       const int I = C % gc.nx, J = (C / gc.nx) % gc.ny, K = C / (gc.nx * gc.ny);
       T sum = T(0);
       for (int d = 0; d < 8; ++d) {
         const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
         const size_t c = cidx(g, i, j, k);
-        const Stencil<T> st = A.co[l].load(g, i, j, k, c);
-        const Nbrs<T> v = load_nbrs<T>(A.x[l], g, i, j, k, c, T(0), T(0));
-        sum += A.b[l][c] - apply_cell(st, v);
+        const Stencil<T> st = co.load(g, i, j, k, c);
+        const Nbrs<T> v = load_nbrs<T>(x, g, i, j, k, c, T(0), T(0));
+        sum += b[c] - apply_cell(st, v);
       }
-      A.b[l + 1][C] = sum * T(0.125);
+      bc[C] = sum * T(0.125);
     }
     __syncthreads();
+    off += geom_cells(g);
   }
   // coarsest: x = A_L^{-1} b
   {
-    const Geom& g = A.g[L];
-    const int n = g.nx * g.ny * g.nz;
-    for (int r = threadIdx.x; r < n; r += BOTTOM_THREADS) {
+    const int n = geom_cells(A->g[L]);
+    const T* b = lb + off;
+    T* x = lx + off;
+    const T* Ainv = A->Ainv;
+    for (int r = threadIdx.x; r < n; r += BottomThreads<T>::value) {
       T acc = T(0);
-      for (int c = 0; c < n; ++c) acc += A.Ainv[(size_t)c * n + r] * A.b[L][c];
-      A.x[L][r] = acc;
+      for (int c = 0; c < n; ++c) acc += Ainv[(size_t)c * n + r] * b[c];
+      x[r] = acc;
     }
     __syncthreads();
   }
   for (int l = L - 1; l >= 0; --l) {
-    const Geom& g = A.g[l];
-    const int n = g.nx * g.ny * g.nz;
+    const Geom g = A->g[l];
+    const FaceCoef<T> co = A->co[l];
+    const int n = geom_cells(g);
+    const int offc = off;  // level l+1
+    off -= n;              // level l
+    T* x = lx + off;
+    const T* b = lb + off;
     const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
-    const T* xc = A.x[l + 1];
-    for (int c = threadIdx.x; c < n; c += BOTTOM_THREADS) {
+    const T* xc = lx + offc;
+    for (int c = threadIdx.x; c < n; c += BottomThreads<T>::value) {
       const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
       const int I = i >> 1, J = j >> 1, K = k >> 1;
       int I2 = I + ((i & 1) ? 1 : -1);
@@ -474,19 +569,23 @@ __global__ __launch_bounds__(BOTTOM_THREADS) void k_vcycle_bottom(BottomArgs<T> 
         sk = T(-1);
       }
       const T q3 = T(0.75), q1 = T(0.25);
-      const T* p = xc + (size_t)K * NY * NX;
-      const T* q = xc + (size_t)K2 * NY * NX;
+      const T* p = xc + K * NY * NX;
+      const T* q = xc + K2 * NY * NX;
       const T pl = q3 * (q3 * p[J * NX + I] + q1 * p[J * NX + I2]) + q1 * (q3 * p[J2 * NX + I] + q1 * p[J2 * NX + I2]);
       const T ql = q3 * (q3 * q[J * NX + I] + q1 * q[J * NX + I2]) + q1 * (q3 * q[J2 * NX + I] + q1 * q[J2 * NX + I2]);
-      A.x[l][c] += q3 * pl + q1 * sk * ql;
+      x[c] += q3 * pl + q1 * sk * ql;
     }
     __syncthreads();
-    for (int it = 0; it < A.nu_post; ++it) {
-      bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 1, false);
+    for (int it = 0; it < nu_post; ++it) {
+      bottom_half_sweep<T>(x, b, co, g, 1, false);
       __syncthreads();
-      bottom_half_sweep<T>(A.x[l], A.b[l], A.co[l], g, 0, false);
+      bottom_half_sweep<T>(x, b, co, g, 0, false);
       __syncthreads();
     }
+  }
+  {
+    const int n0 = geom_cells(A->g[0]);
+    for (int c = threadIdx.x; c < n0; c += BottomThreads<T>::value) A->x0[c] = lx[c];
   }
 }
 
