@@ -10,6 +10,8 @@ face-flux kernel.  Each step therefore holds two converged 1e-8 solves;
 ``value`` counts cells x solves per second over the timed steps (inputs
 resident in HBM).
 
+Workloads c1, c2, c4 (64^3 constant coefficient, 256^3 filament with
+max(a) = 1e3, 256^3 gradient workload) run the same step on their fields.
 Workload c5: the 768^3 two-filament time loop.  Step t advects both
 filaments t cells in +z (the step-0 fields rolled along z on the device),
 renews the coefficient and solves warm-started from the previous phi; one
@@ -17,7 +19,7 @@ solve per step.
 
 Prints one JSON line on stdout; progress goes to stderr.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c3|c5] [--n N]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c1..c5] [--n N]
 """
 import argparse
 import hashlib
@@ -49,18 +51,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (c3: 3, c5: 19)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
-    ap.add_argument("--n", type=int, default=None, help="grid edge (c3: 512, c5: 768)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5"], default="c3")
+    ap.add_argument("--n", type=int, default=None, help="grid edge (default: the workload's)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side-by-side run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=160, help="edge of the CPU-oracle sample grid")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (scale of the hardware traffic counters)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = 3 if args.workload == "c3" else 19
+        args.steps = 19 if args.workload == "c5" else 3
     if args.n is None:
-        args.n = 512 if args.workload == "c3" else 768
+        args.n = {"c1": 64, "c2": 256, "c3": 512, "c4": 256, "c5": 768}[args.workload]
     return args
 
 
@@ -158,13 +162,13 @@ def main():
     N = n ** 3
     h = 1.0 / n
     c5 = args.workload == "c5"
+    cfg = int(args.workload[1])
     t_gen = time.perf_counter()
-    p = make_config(5 if c5 else 3, n=n)
+    p = make_config(cfg, n=n)
     a0 = torch.tensor(p.a, device=dev)
     f0 = torch.tensor(p.f, device=dev)
     del p.a, p.f
-    log(f"inputs: {'two filaments' if c5 else 'filament'} {n}^3, max(a)=1e4, generated in "
-        f"{time.perf_counter() - t_gen:.1f}s")
+    log(f"inputs: workload {args.workload} ({p.name}), generated in {time.perf_counter() - t_gen:.1f}s")
     mask = None if c5 else torch.tensor(probe_box_mask(n), device=dev)
 
     def probe_loss(phi):
@@ -222,7 +226,7 @@ def main():
             prof = solver.profile_read()
             solver.profile(False)
         out = dict(ms_per_step=ms, solve_ms=statistics.median(solve_ms), solves=solves, prof=prof,
-                   prof_steps=args.steps, levels=solver.levels, solves_per_step=2)
+                   prof_steps=args.steps, levels=solver.levels, solves_per_step=2, phi=phi.cpu())
         del solver, phi, lam, grad, gphi
         torch.cuda.empty_cache()
         return out
@@ -281,6 +285,15 @@ def main():
         fp64 = run("fp64")
         log(f"fp64: {fp64['ms_per_step']:.2f} ms/step, iterations {[r.iterations for r in fp64['solves']]}")
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # 1 GiB read + 1 GiB written
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one device copy")
+        del src, dst
+
     # -- per-kernel table and roofline from the event pass ------------------
     s = 4
     restart = 10
@@ -325,7 +338,7 @@ def main():
     if dom is not None:
         name, ms_s, cnt, avg_ms, gbs, bpl = dom
         achieved = bpl / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic() if (name == "gs_fine_f32" and n == 512 and not c5) else None
+        traffic = measured_traffic() if (name == "gs_fine_f32" and n == 512 and args.workload == "c3") else None
         roofline = {
             "bound": "hbm",
             "kernel": name,
@@ -344,25 +357,27 @@ def main():
     if not args.no_cpu_baseline:
         from oracle.fgmres import solve_poisson
         m = args.cpu_n
-        q = make_config(5 if c5 else 3, n=m)
+        q = make_config(cfg, n=m)
         log(f"cpu baseline: oracle fp64 solve at {m}^3 ...")
         t0 = time.perf_counter()
         res = solve_poisson(q.a, q.f, q.h, q.phi_bot, q.phi_top, tol=args.tol, precision="fp64")
         dt = time.perf_counter() - t0
         cpu = {"value": m ** 3 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
                "sample": (f"one FP64 NumPy oracle solve to {args.tol:g} from a zero guess of the same "
-                          f"{'two-filament' if c5 else 'filament'} generator at {m}^3 ({res.iterations} "
+                          f"workload {args.workload} generator at {m}^3 ({res.iterations} "
                           f"steps, {dt:.1f} s; NumPy element-wise work on one thread, host has "
                           f"{os.cpu_count()} cpus)")}
         log(f"cpu baseline: {dt:.1f}s, {res.iterations} steps")
 
     sps = mixed["solves_per_step"]
     value = sps * N / (mixed["ms_per_step"] * 1e-3)
+    desc = {1: "constant a = 1, Gaussian source", 2: "filament, max(a)=1e3", 3: "filament, max(a)=1e4",
+            4: "filament, max(a)=1e3, probe-box loss", 5: "two filaments, max(a)=1e4"}[cfg]
     if c5:
-        workload = (f"two filaments {n}^3 time loop, max(a)=1e4, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
+        workload = (f"{desc} {n}^3 time loop, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
                     "(float32 V-cycle, float64 outer); step = advect (roll) + renewal + warm-started solve")
     else:
-        workload = (f"filament {n}^3, max(a)=1e4, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
+        workload = (f"{desc} {n}^3, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
                     "(float32 V-cycle, float64 outer); step = renewal + forward solve + adjoint "
                     "solve + dL/da")
     line = {
@@ -402,6 +417,9 @@ def main():
             "final_relres": [r.final_relres for r in fp64["solves"]],
         }
         line["mixed_speedup_vs_fp64"] = fp64["ms_per_step"] / mixed["ms_per_step"]
+        if "phi" in mixed and "phi" in fp64:  # forward solutions of the two precisions
+            d = (mixed["phi"] - fp64["phi"]).norm() / fp64["phi"].norm()
+            line["phi_rel_diff_mixed_vs_fp64"] = float(d)
     print(json.dumps(line), flush=True)
 
 
