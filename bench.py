@@ -39,7 +39,7 @@ if ROOT not in sys.path:
 METRIC = "converged cells/s per 1e-8 Poisson solve + HBM GB/s, FP64 vs mixed, 512^3"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SOURCES = ["gmg_common.hpp", "gmg_kernels.hpp", "gmg_fine.hpp", "gmg.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gs_fine_f32_filament512.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sym_fine_f32_filament512.md")
 
 
 def log(*a):
@@ -85,6 +85,10 @@ def split_name(name):
 
 def bytes_per_cell(base, level, s, nu_post=2):
     if level == 0:
+        if base == "sym":  # fused symmetric sweep: old X of the second colour, a, B read; X written
+            return 0.5 * s + s + s + s
+        if base == "sym_first":  # from x = 0: u (float64) and a read; B and X (both colours) written
+            return 8 + s + s + s
         if base == "gs":  # X of the other colour, a, B of the own colour read; X own colour written
             return 0.5 * s + s + 0.5 * s + 0.5 * s
         if base == "gs_first":  # u (float64) and a read; B (both colours) and X (own colour) written
@@ -134,8 +138,8 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the finest-level half-sweep from the committed
-    counter summary, if it was taken on the current kernel sources."""
+    """HBM bytes per launch of the finest-level symmetric sweep from the
+    committed counter summary, if it was taken on the current kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
@@ -338,7 +342,7 @@ def main():
     if dom is not None:
         name, ms_s, cnt, avg_ms, gbs, bpl = dom
         achieved = bpl / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic() if (name == "gs_fine_f32" and n == 512 and args.workload == "c3") else None
+        traffic = measured_traffic() if (name == "sym_fine_f32" and n == 512 and args.workload == "c3") else None
         roofline = {
             "bound": "hbm",
             "kernel": name,

@@ -57,7 +57,7 @@ struct LevelOffsets {
 struct Layout {
   std::vector<LevelShape> shapes;
   std::vector<LevelOffsets> lv;
-  size_t V, Z, a32, b0, partials, scal, cinv, bargs, total;
+  size_t V, Z, a32, b0, xs, partials, scal, cinv, bargs, total;
   size_t tsize;  // bytes of the V-cycle precision
   size_t ldv;    // elements between consecutive Krylov vectors (v_i and z_i)
   size_t hn;     // elements of one colour array of a colour-split finest-level field
@@ -105,6 +105,9 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   // finest-level right side in T (colour-split; natural when the finest
   // level is also the coarsest)
   L->b0 = take(L->ldv * L->tsize);
+  // second finest-level iterate: the fused symmetric sweeps ping-pong
+  // between it and z
+  L->xs = nl > 1 ? take(L->ldv * L->tsize) : 0;
   L->lv.assign(nl, LevelOffsets{});
   for (int l = 1; l < nl; ++l) {
     const LevelShape& s = L->shapes[l];
@@ -585,7 +588,12 @@ void vcycle_coarse(gmg_ctx* c, int l) {
 template <typename T, bool FIRST>
 void gs_split(gmg_ctx* c, T* X, T* B, const double* u, const double* bscale, const T* a, int colour) {
   const LevelShape& s = c->L.shapes[0];
-  const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+  // about 8192 * 256 threads, z-chunks of at least 8 planes
+  const int gx = (s.nx / 2 + BX - 1) / BX, gy = (s.ny + GS_ROWS - 1) / GS_ROWS;
+  const long long target = 8192LL * BY / GS_ROWS;
+  int kc = (int)std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
+  kc = std::min(kc, s.nz);
+  const Launch l{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(BX, GS_ROWS, 1), kc};
   const char* nm = kname(FIRST ? "gs_first" : "gs", 0, sizeof(T));
   if (FIRST && bscale)
     GMG_LAUNCH(c, nm, (k_gs_split<T, FIRST, true>), l, X, B, u, bscale, a, s.geom(), c->L.hn, l.kc, colour);
@@ -631,6 +639,54 @@ void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X) 
   }
 }
 
+// One fused symmetric sweep (k_sym_split) on the finest level: colour c1
+// from Xin into Xout, then the other colour from the new values.
+template <typename T, bool FIRST>
+void sym_split(gmg_ctx* c, const T* Xin, T* Xout, T* B, const double* u, const double* bscale, const T* a,
+               int c1) {
+  const LevelShape& s = c->L.shapes[0];
+  constexpr int R = SymRows<T>::value;
+  const int gx = (s.nx / 2 + SYM_IN_X - 1) / SYM_IN_X, gy = (s.ny + R - 3) / (R - 2);
+  const long long target = 2048LL * 16 / R;  // about 2048 * 1024 threads
+  int kc = (int)std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
+  kc = std::min(kc, s.nz);
+  const Launch l{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(BX, R, 1), kc};
+  const char* nm = kname(FIRST ? "sym_first" : "sym", 0, sizeof(T));
+  if (FIRST && bscale)
+    GMG_LAUNCH(c, nm, (k_sym_split<T, FIRST, true>), l, Xin, Xout, B, u, bscale, a, s.geom(), c->L.hn, l.kc, c1);
+  else
+    GMG_LAUNCH(c, nm, (k_sym_split<T, FIRST, false>), l, Xin, Xout, B, u, bscale, a, s.geom(), c->L.hn, l.kc, c1);
+}
+
+// z = M (s * u) with fused symmetric sweeps (nu_pre, nu_post >= 1): the
+// sweeps ping-pong between the scratch iterate and z so that the last one
+// lands in z.  Same arithmetic as vcycle_fine_split.
+template <typename T>
+void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z) {
+  const LevelShape& s = c->L.shapes[0];
+  const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
+  T* B = wsp<T>(c, c->L.b0);
+  T* XS = wsp<T>(c, c->L.xs);
+  const size_t hn = c->L.hn;
+  const int npre = c->opt.nu_pre, npost = c->opt.nu_post, L = npre + npost;
+  auto buf = [&](int p) { return ((L - p) % 2 == 0) ? Z : XS; };  // written by sweep p (1-based)
+  sym_split<T, true>(c, nullptr, buf(1), B, u, bscale, a, 0);
+  for (int p = 2; p <= npre; ++p) sym_split<T, false>(c, buf(p - 1), buf(p), B, nullptr, nullptr, a, 0);
+  T* X = buf(npre);
+  {
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), k_resid_restrict_split<T>, l, (const T*)X, (const T*)B, a,
+               s.geom(), hn, wsp<T>(c, c->L.lv[1].b), l.kc);
+  }
+  vcycle_coarse<T>(c, 1);
+  {
+    const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+    GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), k_prolong_split<T>, l, X, (const T*)wsp<T>(c, c->L.lv[1].x),
+               s.geom(), hn, 1, l.kc);
+  }
+  for (int p = npre + 1; p <= L; ++p) sym_split<T, false>(c, buf(p - 1), buf(p), B, nullptr, nullptr, a, 1);
+}
+
 // z = M (s * u) on the finest level with right side u scaled by *bscale
 // (null = 1); z in the V-cycle precision, colour-split when there are at
 // least two levels, in the natural layout otherwise.
@@ -652,7 +708,10 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     coarse_solve<T>(c, b0, z);
     return;
   }
-  vcycle_fine_split<T>(c, u, bscale, z);
+  if (c->opt.nu_pre >= 1 && c->opt.nu_post >= 1)
+    vcycle_fine_sym<T>(c, u, bscale, z);
+  else
+    vcycle_fine_split<T>(c, u, bscale, z);
 }
 
 void vcycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z) {

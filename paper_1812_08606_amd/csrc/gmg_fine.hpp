@@ -36,6 +36,7 @@ __device__ __forceinline__ size_t sidx(const Geom& g, int m, int j, int k) {
 // X_{1-c} is left as it is (the next half-sweep overwrites it without
 // reading it).
 constexpr int SPLIT_BATCH = 2;  // planes whose loads are issued together
+constexpr int GS_ROWS = 4;      // rows per block of the finest-level half-sweep
 
 template <typename T>
 struct SplitSide {
@@ -84,14 +85,14 @@ __device__ __forceinline__ void split_side_load(SplitSide<T>& S, const T* __rest
 }
 
 template <typename T, bool FIRST, bool SCALED>
-__global__ __launch_bounds__(NTHREADS) void k_gs_split(T* __restrict__ X, T* __restrict__ B,
+__global__ __launch_bounds__(BX* GS_ROWS) void k_gs_split(T* __restrict__ X, T* __restrict__ B,
                                                        const double* __restrict__ u,
                                                        const double* __restrict__ bscale, const T* __restrict__ a,
                                                        Geom g, size_t hn, int kc, int colour) {
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
   const int m = tl.x * BX + threadIdx.x;
-  const int j = tl.y * BY + threadIdx.y;
+  const int j = tl.y * GS_ROWS + threadIdx.y;
   const bool act = m < H && j < g.ny;
   const size_t sz = (size_t)g.nx * g.ny, tz = (size_t)H * g.ny;
   const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
@@ -170,6 +171,234 @@ __device__ __forceinline__ void split_pair(const T* __restrict__ X, size_t hn, s
   const TO v0 = (TO)X[q], v1 = (TO)X[q + hn];
   l = p ? v1 : v0;
   r = p ? v0 : v1;
+}
+
+// Barrier for data exchanged through LDS only: waits for this wave's LDS
+// operations, not for its global loads in flight (a __syncthreads would also
+// wait for those).  The signal fences keep the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt not waited for
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// One symmetric red-black sweep in one pass: colour c1 everywhere from the
+// old iterate Xin, then colour c2 from the new c1 values (pre-smoothing c1 =
+// red, post-smoothing c1 = black), written to Xout (colour-split, both
+// colours).  It equals two half-sweeps: the c1 update reads only old c2
+// values, the c2 update only new c1 values.
+//
+// Block: 64 lanes x R rows (R = 16 in float32, 8 in float64); lane tx owns
+// pair m = 62 bx + tx - 1 of row j = (R-2) by + ty - 1, marching a z-chunk.
+// Lanes 0 and 63 and rows 0 and R-1 are a halo: they compute the c1 values their neighbours need (the same
+// arithmetic as the block that owns those cells) but store nothing.  On
+// iteration k the block updates c1 on plane k (from global memory), puts the
+// new values into an LDS ring, waits at a barrier, and updates c2 on plane
+// k-1 from the new c1 values of planes k-2, k-1, k: its own column from
+// registers, rows j-1 and j+1 from LDS, the x-neighbour outside the pair
+// from the adjacent lane.  Planes k0-1 and k1 of the chunk are computed
+// (c1 only) for the same reason and not stored.  FIRST: the first sweep
+// from x = 0 (c1 = b / D; b from the natural-layout u times *bscale when
+// SCALED, stored by colour into B).
+// thread rows per block: 16 in float32 (1024 threads); 8 in float64, where
+// 1024 threads would leave too few registers per thread
+template <typename T>
+struct SymRows {
+  static constexpr int value = sizeof(T) == 4 ? 16 : 8;
+};
+constexpr int SYM_IN_X = BX - 2;  // pairs per block row that the block owns
+
+// Values one thread loads for iteration k: the column's plane k+1 and the
+// side values of plane k.
+template <typename T>
+struct SymLoad {
+  T at0, at1, xot;           // a pair and old c2 of the column on plane k+1
+  T rs0, rs1, rn0, rn1;      // a pairs of rows j-1, j+1 on plane k
+  T aout, xout, xs, xn;      // a / old c2 outside the pair; old c2 on rows j-1, j+1
+  T bv1, bv2;                // right side of the pair's c1 / c2 cells on plane k
+};
+
+template <typename T, bool FIRST, bool SCALED>
+__global__ __launch_bounds__(BX* SymRows<T>::value) void k_sym_split(const T* __restrict__ Xin, T* __restrict__ Xout,
+                                                            T* __restrict__ B, const double* __restrict__ u,
+                                                            const double* __restrict__ bscale,
+                                                            const T* __restrict__ a, Geom g, size_t hn, int kc,
+                                                            int c1) {
+  constexpr int R = SymRows<T>::value, IY = R - 2;  // rows per block, rows it owns
+  __shared__ T ring[3][R][BX];  // new c1 values of planes k-1, k, k+1 (mod 3)
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int lane = threadIdx.x, r = threadIdx.y;
+  const int m = tl.x * SYM_IN_X + lane - 1;
+  const int j = tl.y * IY + r - 1;
+  const bool ing = m >= 0 && m < H && j >= 0 && j < g.ny;
+  const bool owner = ing && lane >= 1 && lane <= SYM_IN_X && r >= 1 && r <= IY;
+  const int c2 = 1 - c1;
+  const size_t sy = (size_t)g.nx, tz = (size_t)H * g.ny;
+  const size_t ty = (size_t)H;
+  const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
+  const double s = SCALED ? *bscale : 1.0;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  // faces outside the pair (false for threads outside the grid, whose
+  // addresses are clamped to it)
+  const bool hw = m > 0 && m < H, he = m >= 0 && m < H - 1, hs = j > 0, hn_ = j < g.ny - 1;
+  // clamped (always valid) column of this thread
+  const int mm = min(max(m, 0), H - 1), jj = min(max(j, 0), g.ny - 1);
+  const size_t qcol = (size_t)jj * H + mm;  // colour-array index on plane 0
+  const size_t dys = jj > 0 ? ty : 0, dyn = jj < g.ny - 1 ? ty : 0;
+  const size_t das = jj > 0 ? sy : 0, dan = jj < g.ny - 1 ? sy : 0;
+  const T* __restrict__ Xo = Xin + (size_t)c2 * hn;  // old values of colour c2
+  T* __restrict__ Y1 = Xout + (size_t)c1 * hn;
+  T* __restrict__ Y2 = Xout + (size_t)c2 * hn;
+  T* __restrict__ B1 = B + (size_t)c1 * hn;
+  T* __restrict__ B2 = B + (size_t)c2 * hn;
+  auto pl = [&](int k) { return min(max(k, 0), g.nz - 1); };
+
+  auto load = [&](int k, SymLoad<T>& L) {
+    const int kp = pl(k + 1), kq = pl(k);
+    const size_t qn = (size_t)kp * tz + qcol, cnn = 2 * qn;
+    const size_t q = (size_t)kq * tz + qcol, cn = 2 * q;
+    const int e1 = (c1 + j + k) & 1;
+    const bool hout = e1 ? he : hw;
+    const size_t qo = hout ? (e1 ? q + 1 : q - 1) : q;
+    const size_t co = hout ? (e1 ? cn + 2 : cn - 1) : cn + e1;
+    L.at0 = a[cnn];
+    L.at1 = a[cnn + 1];
+    L.rs0 = a[cn - das];
+    L.rs1 = a[cn - das + 1];
+    L.rn0 = a[cn + dan];
+    L.rn1 = a[cn + dan + 1];
+    L.aout = a[co];
+    if (!FIRST) {
+      L.xot = Xo[qn];
+      L.xs = Xo[q - dys];
+      L.xn = Xo[q + dyn];
+      L.xout = Xo[qo];
+      L.bv1 = B1[q];
+      L.bv2 = B2[q];
+    } else {
+      L.xot = L.xs = L.xn = L.xout = T(0);
+      const T u0 = (T)(SCALED ? u[cn] * s : u[cn]), u1 = (T)(SCALED ? u[cn + 1] * s : u[cn + 1]);
+      L.bv1 = e1 ? u1 : u0;
+      L.bv2 = e1 ? u0 : u1;
+    }
+  };
+
+  // registers: a of the pair on planes k-2 .. k+1, old c2 of the column on
+  // k-1 .. k+1, a of the row pairs j-1 / j+1 on k-1, new c1 of the column on
+  // k-2 .. k, the c2 right side on k-1
+  T a0[4], a1[4], xo[2], as0 = T(0), as1 = T(0), an0 = T(0), an1 = T(0), c1n[3], b2 = T(0);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) c1n[t] = T(0);
+  {
+    // planes k0-2 and k0-1 (clamped): a into ring slots 2, 3 (rotated to
+    // k-2, k-1 at the top of the first iteration), old c2 into xo[0], xo[1]
+    for (int t = 0; t < 2; ++t) {
+      const int k = pl(k0 - 2 + t);
+      const size_t q = (size_t)k * tz + qcol, cn = 2 * q;
+      a0[t + 2] = a[cn];
+      a1[t + 2] = a[cn + 1];
+      xo[t] = FIRST ? T(0) : Xo[q];
+    }
+    a0[0] = a1[0] = a0[1] = a1[1] = T(0);
+  }
+
+  // iteration k: colour c1 on plane k, then colour c2 on plane k-1
+  auto iterate = [&](int k, const SymLoad<T>& L) {
+    const int e1 = (c1 + j + k) & 1;
+    const bool hout = e1 ? he : hw;
+    a0[0] = a0[1];
+    a1[0] = a1[1];
+    a0[1] = a0[2];
+    a1[1] = a1[2];
+    a0[2] = a0[3];
+    a1[2] = a1[3];
+    a0[3] = L.at0;
+    a1[3] = L.at1;
+    // (a0[3] is plane k+1, a0[2] plane k, a0[1] plane k-1, a0[0] plane k-2)
+    T v1;
+    {
+      const bool top = k >= g.nz - 1, bot = k <= 0;
+      const T acv = e1 ? a1[2] : a0[2], ain = e1 ? a0[2] : a1[2];
+      const T abv = e1 ? a1[1] : a0[1], atv = e1 ? a1[3] : a0[3];
+      const T wi = (acv + ain) * hx;
+      const T wo = hout ? (acv + L.aout) * hx : T(0);
+      const T ws = hs ? (acv + (e1 ? L.rs1 : L.rs0)) * hy : T(0);
+      const T wn = hn_ ? (acv + (e1 ? L.rn1 : L.rn0)) * hy : T(0);
+      const T wb = !bot ? (acv + abv) * hz : T(0);
+      const T wt = !top ? (acv + atv) * hz : T(0);
+      const T D = wi + wo + ws + wn + (!bot ? wb : pz * acv) + (!top ? wt : pz * acv);
+      if (FIRST) {
+        v1 = L.bv1 * recip(D);
+      } else {
+        // old c2: inner neighbour xo[1] (plane k), below xo[0], above L.xot
+        const T off = wi * xo[1] + (hout ? wo * L.xout : T(0)) + (hs ? ws * L.xs : T(0)) +
+                      (hn_ ? wn * L.xn : T(0)) + (!bot ? wb * xo[0] : T(0)) + (!top ? wt * L.xot : T(0));
+        v1 = (L.bv1 + off) * recip(D);
+      }
+      if (owner && k >= k0 && k < k1) {
+        const size_t q = (size_t)k * tz + qcol;
+        Y1[q] = v1;
+        if (FIRST) {
+          B1[q] = L.bv1;
+          B2[q] = L.bv2;
+        }
+      }
+    }
+    xo[0] = xo[1];
+    xo[1] = L.xot;
+    c1n[0] = c1n[1];
+    c1n[1] = c1n[2];
+    c1n[2] = v1;
+    ring[(k + 3) % 3][r][lane] = v1;
+    lds_barrier();
+    // --- colour c2 on plane kk = k-1 ---
+    const int kk = k - 1;
+    // x-neighbour outside the pair (the adjacent lane's values on plane kk)
+    const T c1w = __shfl_up(c1n[1], 1, 64), c1e = __shfl_down(c1n[1], 1, 64);
+    const T aw1 = __shfl_up(a1[1], 1, 64), ae0 = __shfl_down(a0[1], 1, 64);
+    if (owner && kk >= k0 && kk < k1) {
+      const int e2 = (c2 + j + kk) & 1;
+      const bool top = kk == g.nz - 1, bot = kk == 0;
+      const bool ho = e2 ? he : hw;
+      const T acv = e2 ? a1[1] : a0[1], ain = e2 ? a0[1] : a1[1];
+      const T abv = e2 ? a1[0] : a0[0], atv = e2 ? a1[2] : a0[2];
+      const T aov = e2 ? ae0 : aw1, cov = e2 ? c1e : c1w;
+      const T wi = (acv + ain) * hx;
+      const T wo = ho ? (acv + aov) * hx : T(0);
+      const T ws = hs ? (acv + (e2 ? as1 : as0)) * hy : T(0);
+      const T wn = hn_ ? (acv + (e2 ? an1 : an0)) * hy : T(0);
+      const T wb = !bot ? (acv + abv) * hz : T(0);
+      const T wt = !top ? (acv + atv) * hz : T(0);
+      const T D = wi + wo + ws + wn + (!bot ? wb : pz * acv) + (!top ? wt : pz * acv);
+      const int sl = (kk + 3) % 3;
+      const T ys = ring[sl][r - 1][lane], yn = ring[sl][r + 1][lane];
+      const T off = wi * c1n[1] + (ho ? wo * cov : T(0)) + (hs ? ws * ys : T(0)) + (hn_ ? wn * yn : T(0)) +
+                    (!bot ? wb * c1n[0] : T(0)) + (!top ? wt * c1n[2] : T(0));
+      Y2[(size_t)kk * tz + qcol] = (b2 + off) * recip(D);
+    }
+    // a pairs of rows j-1 / j+1 and the c2 right side, now of plane k
+    as0 = L.rs0;
+    as1 = L.rs1;
+    an0 = L.rn0;
+    an1 = L.rn1;
+    b2 = L.bv2;
+  };
+
+  // two iterations per trip: the loads of iteration k+1 are issued before
+  // iteration k runs (into the other buffer, so no copies of values in flight)
+  // (loads past k1 read a clamped valid plane and are not used)
+  SymLoad<T> L0, L1;
+  load(k0 - 1, L0);
+  for (int k = k0 - 1; k <= k1; k += 2) {
+    load(min(k + 1, k1), L1);
+    iterate(k, L0);
+    if (k + 1 > k1) break;
+    load(min(k + 2, k1), L0);
+    iterate(k + 1, L1);
+  }
 }
 
 // Residual and restriction from the colour-split iterate and right side:
