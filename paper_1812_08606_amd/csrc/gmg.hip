@@ -514,11 +514,13 @@ void resid_restrict_face(gmg_ctx* c, int l, const T* x, const T* b, const FaceCo
              pl.kc);
 }
 
+// Levels >= 1 that are not the coarsest (every dimension even): x += P xc.
 template <typename T>
 void prolong_add(gmg_ctx* c, int l, T* x, const T* xc) {
   const LevelShape& s = c->L.shapes[l];
-  const Launch lc = col_launch(s.nx, s.ny, s.nz, 1 << 16);
-  GMG_LAUNCH(c, kname("prolong_add", l, sizeof(T)), k_prolong_add<T>, lc, x, xc, s.geom(), lc.kc);
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2);
+  GMG_LAUNCH(c, kname("prolong_add", l, sizeof(T)), (k_prolong_pair<T, false>), pl, x, xc, s.geom(), (size_t)0, 0,
+             pl.kc);
 }
 
 template <typename T>
@@ -629,9 +631,9 @@ void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X) 
   }
   vcycle_coarse<T>(c, 1);
   {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
-    GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), k_prolong_split<T>, l, X, (const T*)wsp<T>(c, c->L.lv[1].x),
-               s.geom(), hn, npost > 0 ? 1 : 2, l.kc);
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), (k_prolong_pair<T, true>), l, X,
+               (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, npost > 0 ? 1 : 2, l.kc);
   }
   for (int it = 0; it < npost; ++it) {
     gs_split<T, false>(c, X, B, nullptr, nullptr, a, 1);
@@ -680,9 +682,9 @@ void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z) {
   }
   vcycle_coarse<T>(c, 1);
   {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
-    GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), k_prolong_split<T>, l, X, (const T*)wsp<T>(c, c->L.lv[1].x),
-               s.geom(), hn, 1, l.kc);
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), (k_prolong_pair<T, true>), l, X,
+               (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, 1, l.kc);
   }
   for (int p = npre + 1; p <= L; ++p) sym_split<T, false>(c, buf(p - 1), buf(p), B, nullptr, nullptr, a, 1);
 }
@@ -708,7 +710,10 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     coarse_solve<T>(c, b0, z);
     return;
   }
-  if (c->opt.nu_pre >= 1 && c->opt.nu_post >= 1)
+  // fused symmetric sweeps in float32 (measured faster there); one kernel
+  // per half-sweep in float64 (where the fused kernel's register demand
+  // halves its block size) and without pre- or post-smoothing
+  if (sizeof(T) == 4 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1)
     vcycle_fine_sym<T>(c, u, bscale, z);
   else
     vcycle_fine_split<T>(c, u, bscale, z);

@@ -521,11 +521,19 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_split(const T* __re
   }
 }
 
-// X_c += P x_coarse for the colours c < ncol (cell-centred trilinear, as
-// k_prolong_add).  Grid over (H, ny, nz) with z-chunks of kc planes.
-template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_prolong_split(T* __restrict__ X, const T* __restrict__ xc, Geom g,
-                                                            size_t hn, int ncol, int kc) {
+// x_fine += P x_coarse, cell-centred trilinear (per dimension 3/4 of the
+// parent and 1/4 of the nearer coarse neighbour; outside the grid the
+// neighbour is the parent (x, y: Neumann) or minus the parent (z: plates)).
+// Lane tx owns pair m of fine row j -- m is also the parent's coarse x-index
+// -- and marches the coarse planes of its z-chunk (kc of them), keeping the
+// row- and x-interpolated coarse values of planes K-1, K, K+1 in registers;
+// coarse plane K feeds fine planes 2K (with K-1) and 2K+1 (with K+1).  The
+// two cells of a pair differ only in their x-neighbour (m-1 for cell 2m, m+1
+// for cell 2m+1).  SPLIT: the fine x is colour-split and only the colours
+// c < ncol are corrected; otherwise the fine x is natural (every cell).
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, const T* __restrict__ xc, Geom g,
+                                                           size_t hn, int ncol, int kc) {
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
   const int m = tl.x * BX + threadIdx.x;
@@ -536,28 +544,51 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_split(T* __restrict__ X, c
   const int J = j >> 1;
   int J2 = J + ((j & 1) ? 1 : -1);
   if (J2 < 0 || J2 >= NY) J2 = J;
-  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int k = k0; k < k1; ++k) {
-    const int K = k >> 1;
-    int K2 = K + ((k & 1) ? 1 : -1);
-    T sk = T(1);
-    if (K2 < 0 || K2 >= NZ) {
-      K2 = K;
-      sk = T(-1);
+  const int Il = m > 0 ? m - 1 : m, Ir = m < NX - 1 ? m + 1 : m;
+  const size_t rJ = (size_t)J * NX, rJ2 = (size_t)J2 * NX, sZ = (size_t)NY * NX;
+  auto interp = [&](int K, T& left, T& right) {
+    const T* p = xc + (size_t)K * sZ;
+    const T c0 = p[rJ + m], cl = p[rJ + Il], cr = p[rJ + Ir];
+    const T d0 = p[rJ2 + m], dl = p[rJ2 + Il], dr = p[rJ2 + Ir];
+    left = q3 * (q3 * c0 + q1 * cl) + q1 * (q3 * d0 + q1 * dl);
+    right = q3 * (q3 * c0 + q1 * cr) + q1 * (q3 * d0 + q1 * dr);
+  };
+  const int K0 = tl.z * kc, K1 = min(NZ, K0 + kc);
+  T lb, rb, lc, rc, lt, rt;  // coarse planes K-1, K, K+1 (left / right variant)
+  interp(K0, lc, rc);
+  if (K0 > 0) {
+    interp(K0 - 1, lb, rb);
+  } else {
+    lb = -lc;
+    rb = -rc;
+  }
+  for (int K = K0; K < K1; ++K) {
+    if (K + 1 < NZ) {
+      interp(K + 1, lt, rt);
+    } else {
+      lt = -lc;
+      rt = -rc;
     }
-    const T* p = xc + (size_t)K * NY * NX;
-    const T* pq = xc + (size_t)K2 * NY * NX;
-    for (int c = 0; c < ncol; ++c) {
-      const int e = (c + j + k) & 1;  // the cell is i = 2m + e
-      const int I = m;                 // parent: i >> 1
-      int I2 = I + (e ? 1 : -1);
-      if (I2 < 0 || I2 >= NX) I2 = I;
-      const T pl = q3 * (q3 * p[(size_t)J * NX + I] + q1 * p[(size_t)J * NX + I2]) +
-                   q1 * (q3 * p[(size_t)J2 * NX + I] + q1 * p[(size_t)J2 * NX + I2]);
-      const T ql = q3 * (q3 * pq[(size_t)J * NX + I] + q1 * pq[(size_t)J * NX + I2]) +
-                   q1 * (q3 * pq[(size_t)J2 * NX + I] + q1 * pq[(size_t)J2 * NX + I2]);
-      X[(size_t)c * hn + sidx(g, m, j, k)] += q3 * pl + q1 * sk * ql;
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      const int k = 2 * K + sub;
+      const T vl = q3 * lc + q1 * (sub ? lt : lb);  // cell 2m
+      const T vr = q3 * rc + q1 * (sub ? rt : rb);  // cell 2m+1
+      if (SPLIT) {
+        for (int c = 0; c < ncol; ++c) {
+          const int e = (c + j + k) & 1;
+          x[(size_t)c * hn + sidx(g, m, j, k)] += e ? vr : vl;
+        }
+      } else {
+        const size_t cn = ((size_t)k * g.ny + j) * g.nx + 2 * m;
+        x[cn] += vl;
+        x[cn + 1] += vr;
+      }
     }
+    lb = lc;
+    rb = rc;
+    lc = lt;
+    rc = rt;
   }
 }
 

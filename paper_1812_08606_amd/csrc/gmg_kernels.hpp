@@ -589,44 +589,6 @@ __global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const
   }
 }
 
-// x_fine += P x_coarse, cell-centred trilinear: per dimension 3/4 of the
-// parent and 1/4 of the nearer coarse neighbour; outside the grid the
-// neighbour is the parent (x, y: Neumann) or minus the parent (z: plates).
-template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_prolong_add(T* __restrict__ x, const T* __restrict__ xc, Geom g,
-                                                          int kc) {
-  const Tile tl = xcd_tile();
-  const int i = tl.x * BX + threadIdx.x;
-  if (i >= g.nx) return;
-  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
-  const int I = i >> 1;
-  int I2 = I + ((i & 1) ? 1 : -1);
-  if (I2 < 0 || I2 >= NX) I2 = I;
-  const T q3 = T(0.75), q1 = T(0.25);
-  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
-  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-    const int J = j >> 1;
-    int J2 = J + ((j & 1) ? 1 : -1);
-    if (J2 < 0 || J2 >= NY) J2 = J;
-    for (int k = k0; k < k1; ++k) {
-      const int K = k >> 1;
-      int K2 = K + ((k & 1) ? 1 : -1);
-      T sk = T(1);
-      if (K2 < 0 || K2 >= NZ) {
-        K2 = K;
-        sk = T(-1);
-      }
-      const T* p = xc + (size_t)K * NY * NX;
-      const T* q = xc + (size_t)K2 * NY * NX;
-      const T pl = q3 * (q3 * p[(size_t)J * NX + I] + q1 * p[(size_t)J * NX + I2]) +
-                   q1 * (q3 * p[(size_t)J2 * NX + I] + q1 * p[(size_t)J2 * NX + I2]);
-      const T ql = q3 * (q3 * q[(size_t)J * NX + I] + q1 * q[(size_t)J * NX + I2]) +
-                   q1 * (q3 * q[(size_t)J2 * NX + I] + q1 * q[(size_t)J2 * NX + I2]);
-      const size_t c = cidx(g, i, j, k);
-      x[c] += q3 * pl + q1 * sk * ql;
-    }
-  }
-}
 
 // Coarsest level: x = A_L^{-1} b with the precomputed (symmetric) inverse;
 // thread r forms row r, reading column r of the symmetric inverse so that a
