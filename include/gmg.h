@@ -62,6 +62,11 @@ enum {
 
 enum { GMG_FP64 = 0, GMG_MIXED = 1 };
 
+/* Finest-level smoother kernels (both run the same red-black Gauss-Seidel
+ * arithmetic, so the choice changes speed only, and results at the level of
+ * float32 rounding). */
+enum { GMG_SWEEP_AUTO = 0, GMG_SWEEP_HALF = 1, GMG_SWEEP_FUSED = 2 };
+
 /* Solver options.  gmg_default_options fills the defaults given below. */
 typedef struct gmg_options {
   int restart;          /* Krylov dimension m of FGMRES(m), 1..32 (default 10)   */
@@ -72,7 +77,13 @@ typedef struct gmg_options {
                            (coefficients, smoother, transfers, coarse solve) in
                            float32, FGMRES in float64 (default GMG_MIXED)       */
   int coarse_max_cells; /* largest coarsest level solved directly (default 4096) */
-  int reserved[4];      /* must be zero */
+  int fine_sweep;       /* GMG_SWEEP_HALF: one kernel per red or black half-sweep;
+                           GMG_SWEEP_FUSED: one kernel per symmetric sweep
+                           (float32 V-cycle with nu_pre, nu_post >= 1 on a grid
+                           of at least two levels; half-sweeps otherwise);
+                           GMG_SWEEP_AUTO (default): fused where it was
+                           measured faster (float32, long z-chunks) */
+  int reserved[3];      /* must be zero */
 } gmg_options;
 
 void gmg_default_options(gmg_options* opt);

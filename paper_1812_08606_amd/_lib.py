@@ -18,7 +18,8 @@ class Options(ctypes.Structure):
         ("nu_post", c_int),
         ("precision", c_int),
         ("coarse_max_cells", c_int),
-        ("reserved", c_int * 4),
+        ("fine_sweep", c_int),
+        ("reserved", c_int * 3),
     ]
 
 

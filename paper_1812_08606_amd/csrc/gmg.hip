@@ -71,6 +71,7 @@ bool options_valid(const gmg_options* o) {
   if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8) return false;
   if (o->precision != GMG_FP64 && o->precision != GMG_MIXED) return false;
   if (o->coarse_max_cells < 1 || o->coarse_max_cells > 4096) return false;
+  if (o->fine_sweep < GMG_SWEEP_AUTO || o->fine_sweep > GMG_SWEEP_FUSED) return false;
   for (int r : o->reserved)
     if (r) return false;
   return true;
@@ -641,18 +642,25 @@ void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X) 
   }
 }
 
+// Launch of the fused symmetric sweep on the finest level: blocks of 64 x R
+// threads, about 2048 * 1024 threads in all, z-chunks of at least 8 planes.
+template <typename T>
+Launch sym_launch(const LevelShape& s) {
+  constexpr int R = SymRows<T>::value;
+  const int gx = (s.nx / 2 + SYM_IN_X - 1) / SYM_IN_X, gy = (s.ny + R - 3) / (R - 2);
+  const long long target = 2048LL * 16 / R;
+  int kc = (int)std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
+  kc = std::min(kc, s.nz);
+  return Launch{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(BX, R, 1), kc};
+}
+
 // One fused symmetric sweep (k_sym_split) on the finest level: colour c1
 // from Xin into Xout, then the other colour from the new values.
 template <typename T, bool FIRST>
 void sym_split(gmg_ctx* c, const T* Xin, T* Xout, T* B, const double* u, const double* bscale, const T* a,
                int c1) {
   const LevelShape& s = c->L.shapes[0];
-  constexpr int R = SymRows<T>::value;
-  const int gx = (s.nx / 2 + SYM_IN_X - 1) / SYM_IN_X, gy = (s.ny + R - 3) / (R - 2);
-  const long long target = 2048LL * 16 / R;  // about 2048 * 1024 threads
-  int kc = (int)std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
-  kc = std::min(kc, s.nz);
-  const Launch l{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(BX, R, 1), kc};
+  const Launch l = sym_launch<T>(s);
   const char* nm = kname(FIRST ? "sym_first" : "sym", 0, sizeof(T));
   if (FIRST && bscale)
     GMG_LAUNCH(c, nm, (k_sym_split<T, FIRST, true>), l, Xin, Xout, B, u, bscale, a, s.geom(), c->L.hn, l.kc, c1);
@@ -710,10 +718,17 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     coarse_solve<T>(c, b0, z);
     return;
   }
-  // fused symmetric sweeps in float32 (measured faster there); one kernel
-  // per half-sweep in float64 (where the fused kernel's register demand
-  // halves its block size) and without pre- or post-smoothing
-  if (sizeof(T) == 4 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1)
+  // Fused symmetric sweeps (float32 only, both smoothing phases present):
+  // on request, or by default when their z-chunks are long.  Each chunk of
+  // the fused sweep adds two planes of first-colour work and a pipeline
+  // fill, so it only wins with chunks of 32 planes or more (measured: 5% per
+  // V-cycle at 768^3, 2% at 512^3; 9-22% slower at 384^3 and 256^3, with 21-
+  // and 8-plane chunks).  In float64 the fused kernel's register demand
+  // halves its block size and it was slower at every size.
+  const int fs = c->opt.fine_sweep;
+  const bool fused = sizeof(T) == 4 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 &&
+                     (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(s).kc >= 32));
+  if (fused)
     vcycle_fine_sym<T>(c, u, bscale, z);
   else
     vcycle_fine_split<T>(c, u, bscale, z);
@@ -906,6 +921,7 @@ void gmg_default_options(gmg_options* opt) {
   opt->nu_post = 2;
   opt->precision = GMG_MIXED;
   opt->coarse_max_cells = 4096;
+  opt->fine_sweep = GMG_SWEEP_AUTO;
 }
 
 size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt) {

@@ -14,6 +14,7 @@ from . import _lib
 
 FP64, MIXED = 0, 1
 _PRECISION = {"fp64": FP64, "mixed": MIXED}
+_FINE_SWEEP = {"auto": 0, "half": 1, "fused": 2}
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -61,11 +62,13 @@ class GMGPoisson:
     (eq. e18), solved by FGMRES(restart) with one V-cycle per step.
 
     a: float64 CUDA/HIP tensor (nz, ny, nx), > 0.  h: (hx, hy, hz), default
-    unit cube.  precision: "mixed" (float32 V-cycle) or "fp64"."""
+    unit cube.  precision: "mixed" (float32 V-cycle) or "fp64".  fine_sweep:
+    finest-level smoother kernels, "half" (one per half-sweep), "fused" (one
+    per symmetric sweep, float32 only) or "auto"."""
 
     def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
                  max_iter: int = 200, nu_pre: int = 2, nu_post: int = 2,
-                 coarse_max_cells: int = 4096):
+                 coarse_max_cells: int = 4096, fine_sweep: str = "auto"):
         self._lib = _lib.load()
         if a.dim() != 3:
             raise ValueError("a must be 3-D (nz, ny, nx)")
@@ -77,12 +80,15 @@ class GMGPoisson:
         if precision not in _PRECISION:
             raise ValueError(f"precision must be one of {sorted(_PRECISION)}")
         self.precision = precision
+        if fine_sweep not in _FINE_SWEEP:
+            raise ValueError(f"fine_sweep must be one of {sorted(_FINE_SWEEP)}")
         opt = _lib.Options()
         self._lib.gmg_default_options(ctypes.byref(opt))
         opt.restart, opt.max_iter = int(restart), int(max_iter)
         opt.nu_pre, opt.nu_post = int(nu_pre), int(nu_post)
         opt.precision = _PRECISION[precision]
         opt.coarse_max_cells = int(coarse_max_cells)
+        opt.fine_sweep = _FINE_SWEEP[fine_sweep]
         self.options = opt
         nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
         if nbytes == 0:

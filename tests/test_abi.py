@@ -35,8 +35,8 @@ def test_default_options_and_workspace(lib):
     from paper_1812_08606_amd._lib import Options
     opt = Options()
     lib.gmg_default_options(ctypes.byref(opt))
-    assert (opt.restart, opt.max_iter, opt.nu_pre, opt.nu_post, opt.precision, opt.coarse_max_cells) == \
-        (10, 200, 2, 2, 1, 4096)
+    assert (opt.restart, opt.max_iter, opt.nu_pre, opt.nu_post, opt.precision, opt.coarse_max_cells,
+            opt.fine_sweep) == (10, 200, 2, 2, 1, 4096, 0)
     n64 = lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt))
     N = 64 ** 3
     # 11 float64 Krylov vectors + 10 float32 preconditioned vectors dominate
@@ -46,6 +46,11 @@ def test_default_options_and_workspace(lib):
     opt.restart = 0
     assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == 0
     opt.restart = 10
+    opt.fine_sweep = 3
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == 0
+    opt.fine_sweep = 2
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == n64
+    opt.fine_sweep = 0
     opt.precision = 0
     assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) > n64
 

@@ -84,16 +84,50 @@ def test_vcycle_mixed_matches_float32_oracle(shape):
     assert rel(z, ref) < 2e-5
 
 
-@pytest.mark.parametrize("shape", [(64, 32, 48), (130, 8, 4), (66, 10, 12), (256, 12, 8)])
-def test_vcycle_colour_split_finest_level(shape):
-    """The finest level's colour-split kernels (several 64-pair wave rows,
-    ragged last wave, thin grids) give the oracle's V-cycle."""
+@pytest.mark.parametrize("shape", [(64, 32, 48), (130, 8, 4), (66, 10, 12), (256, 12, 8), (200, 40, 48)])
+@pytest.mark.parametrize("sweep", ["half", "fused"])
+def test_vcycle_colour_split_finest_level(shape, sweep):
+    """The finest level's colour-split kernels (several wave rows and block
+    tiles, ragged last wave and tile, thin grids), with one kernel per
+    half-sweep or one per symmetric sweep, give the oracle's V-cycle."""
+    print(f"vcycle colour-split {shape} {sweep}", flush=True)
     a, f, h = _rand_problem(shape, 6)
-    s64 = gm.GMGPoisson(T(a), h=h, precision="fp64")
+    s64 = gm.GMGPoisson(T(a), h=h, precision="fp64", fine_sweep=sweep)
     assert rel(npy(s64.vcycle(T(f))), vcycle(build_hierarchy(a, h), f)) < 1e-12
-    s32 = gm.GMGPoisson(T(a), h=h, precision="mixed")
+    s32 = gm.GMGPoisson(T(a), h=h, precision="mixed", fine_sweep=sweep)
+    s32.profile(True)
+    z = npy(s32.vcycle(T(f)))
+    names = set(s32.profile_read())
+    s32.profile(False)
+    assert ("sym_fine_f32" in names) == (sweep == "fused") and ("gs_fine_f32" in names) == (sweep == "half")
     ref32 = vcycle(build_hierarchy(a, h, dtype=np.float32), f.astype(np.float32)).astype(np.float64)
-    assert rel(npy(s32.vcycle(T(f))), ref32) < 2e-5
+    assert rel(z, ref32) < 2e-5
+
+
+@pytest.mark.parametrize("n, fused_by_default", [(256, False), (512, True)])
+def test_fused_and_half_sweeps_agree_full_size(n, fused_by_default):
+    """Filament workload at 256^3 and 512^3 (max(a) = 1e3, 1e4): the float32
+    V-cycle with fused symmetric sweeps equals the one with half-sweep
+    kernels to float32 rounding, and the default picks the fused kernel only
+    on the long-chunk grid."""
+    print(f"fused vs half sweeps {n}^3", flush=True)
+    p = make_config(2 if n == 256 else 3, n=n)
+    a, f = T(p.a), T(p.f)
+    v = f / f.norm()
+    z = {}
+    for sweep in ("half", "fused", "auto"):
+        s = gm.GMGPoisson(a, precision="mixed", fine_sweep=sweep)
+        s.profile(True)
+        z[sweep] = s.vcycle(v)
+        names = set(s.profile_read())
+        s.profile(False)
+        if sweep == "auto":
+            assert ("sym_fine_f32" in names) == fused_by_default
+        del s
+    d = ((z["fused"] - z["half"]).norm() / z["half"].norm()).item()
+    print(f"  |z_fused - z_half| / |z_half| = {d:.2e}", flush=True)
+    assert d < 1e-5
+    assert torch.equal(z["auto"], z["fused" if fused_by_default else "half"])
 
 
 @pytest.mark.parametrize("nu", [(0, 1), (1, 0), (1, 1), (3, 2)])
