@@ -33,6 +33,13 @@ operators is not available, and its smoother is replaced, see below):
   coarsest mesh").
 * Preconditioner application: one V-cycle from a zero initial guess with
   the right side v_j (Sec. 3.2, last paragraph).
+* Full multigrid (Sec. 3.2: the first time step, solved from a zero guess,
+  uses FMG; the later ones V-cycles): the paper gives no steps, so ``fmg``
+  is the textbook cycle with this module's own transfers: right sides
+  restricted to every level, the coarsest solved, then on each finer level
+  one V-cycle from the interpolated coarser solution.  The right side is
+  restricted algebraically (it is a Krylov vector, not a boundary-value
+  problem), as in an algebraic FMG preconditioner.
 """
 from __future__ import annotations
 
@@ -169,14 +176,16 @@ def coarse_solve(hier: Hierarchy, b):
     return sla.cho_solve(hier.coarse_factor, b.ravel()).reshape(b.shape).astype(hier.dtype)
 
 
-def vcycle(hier: Hierarchy, b, level=0):
-    """One V-cycle for A_l x = b from x = 0 (Fig. multigriddiagram, applied
-    recursively as described below eq. e31)."""
+def vcycle(hier: Hierarchy, b, level=0, x0=None):
+    """One V-cycle for A_l x = b from x = 0, or from the guess x0 (Fig.
+    multigriddiagram, applied recursively as described below eq. e31; the
+    coarser levels always start from 0).  On the coarsest level the result is
+    the direct solve whatever the guess."""
     lev = hier.levels[level]
     b = np.asarray(b, dtype=hier.dtype)
     if level == len(hier.levels) - 1:
         return coarse_solve(hier, b)
-    x = np.zeros_like(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=hier.dtype)
     for _ in range(hier.nu_pre):
         rbgs_half_sweep(x, b, lev, 0)
         rbgs_half_sweep(x, b, lev, 1)
@@ -186,4 +195,26 @@ def vcycle(hier: Hierarchy, b, level=0):
     for _ in range(hier.nu_post):
         rbgs_half_sweep(x, b, lev, 1)
         rbgs_half_sweep(x, b, lev, 0)
+    return x
+
+
+def fmg(hier: Hierarchy, b):
+    """Full multigrid cycle for A x = b from no initial guess: the
+    preconditioner of the first, cold-started solve (Sec. 3.2, FMG on the
+    first time step).  The paper names the method without its steps; this is
+    the textbook cycle:
+
+    1. right sides of every level: b_0 = b, b_{l+1} = R b_l (mean of the 8
+       children, the V-cycle's restriction);
+    2. the coarsest level solved directly;
+    3. level by level towards the finest, the coarser solution interpolated
+       (the V-cycle's trilinear prolongation) is the initial guess of one
+       V-cycle for A_l x_l = b_l."""
+    nl = len(hier.levels)
+    bs = [np.asarray(b, dtype=hier.dtype)]
+    for _ in range(nl - 1):
+        bs.append(restrict(bs[-1]))
+    x = coarse_solve(hier, bs[-1])
+    for level in range(nl - 2, -1, -1):
+        x = vcycle(hier, bs[level], level, x0=prolong(x))
     return x

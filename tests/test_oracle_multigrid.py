@@ -272,3 +272,101 @@ def test_single_level_vcycle_is_direct_solve():
     b = rng.standard_normal(a.shape)
     x = vcycle(hier, b)
     np.testing.assert_allclose(apply_faces(x, face_coefficients(a), h), b, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- full multigrid
+def _interp_1d(n, dirichlet):
+    """Dense 1-D cell-centred linear interpolation (2n x n): fine 2I is
+    3/4 c_I + 1/4 c_{I-1}, fine 2I+1 is 3/4 c_I + 1/4 c_{I+1}; a ghost beyond
+    an end is the end value (Neumann) or its negative (Dirichlet)."""
+    P = np.zeros((2 * n, n))
+    s = -1.0 if dirichlet else 1.0
+    for I in range(n):
+        P[2 * I, I] += 0.75
+        P[2 * I + 1, I] += 0.75
+        if I > 0:
+            P[2 * I, I - 1] += 0.25
+        else:
+            P[2 * I, I] += 0.25 * s
+        if I < n - 1:
+            P[2 * I + 1, I + 1] += 0.25
+        else:
+            P[2 * I + 1, I] += 0.25 * s
+    return P
+
+
+def _mean_1d(n):
+    """Dense 1-D pairing (n/2 x n): coarse I is the mean of fine 2I, 2I+1."""
+    R = np.zeros((n // 2, n))
+    for I in range(n // 2):
+        R[I, 2 * I] = R[I, 2 * I + 1] = 0.5
+    return R
+
+
+def test_fmg_two_levels_closed_form():
+    """Two levels: FMG gives x = x0 + M (b - A x0) with x0 = P A_1^{-1} R b
+    (the coarse solution of the restricted right side, interpolated) and M
+    the V-cycle from zero (eq. eRichard: a V-cycle from a guess is x0 plus M
+    applied to the residual).  P, R and the coarse solve are formed here
+    from their definitions (Kronecker products of 1-D matrices, a dense
+    solve), not from the oracle's routines."""
+    from oracle.multigrid import fmg
+    rng = np.random.default_rng(21)
+    shape = (6, 4, 10)  # (nz, ny, nx)
+    a = rng.uniform(0.1, 10.0, shape)
+    h = (1 / 10, 1 / 4, 1 / 6)
+    hier = build_hierarchy(a, h)
+    assert len(hier.levels) == 2
+    nz, ny, nx = shape
+    Pm = np.kron(_interp_1d(nz // 2, True), np.kron(_interp_1d(ny // 2, False), _interp_1d(nx // 2, False)))
+    Rm = np.kron(_mean_1d(nz), np.kron(_mean_1d(ny), _mean_1d(nx)))
+    A0 = assemble_dense(face_coefficients(a), h)
+    coarse = hier.levels[1]
+    A1 = assemble_dense(coarse.faces, coarse.h)
+    b = rng.standard_normal(shape)
+    x0 = Pm @ np.linalg.solve(A1, Rm @ b.ravel())
+    want = x0 + vcycle(hier, (b.ravel() - A0 @ x0).reshape(shape)).ravel()
+    np.testing.assert_allclose(fmg(hier, b).ravel(), want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
+
+
+def test_fmg_single_level_is_direct_solve_and_linear():
+    from oracle.multigrid import fmg
+    rng = np.random.default_rng(22)
+    a = rng.uniform(0.5, 2, (3, 5, 7))
+    h = (1 / 7, 1 / 5, 1 / 3)
+    hier = build_hierarchy(a, h)
+    assert len(hier.levels) == 1
+    b = rng.standard_normal(a.shape)
+    np.testing.assert_allclose(apply_faces(fmg(hier, b), face_coefficients(a), h), b, rtol=1e-12, atol=1e-12)
+    a = rng.uniform(0.5, 2, (8, 8, 8))
+    hier = build_hierarchy(a, (1 / 8,) * 3)
+    u, v = rng.standard_normal((2, 8, 8, 8))
+    np.testing.assert_allclose(fmg(hier, 2 * u - 3 * v), 2 * fmg(hier, u) - 3 * fmg(hier, v),
+                               rtol=1e-12, atol=1e-13)
+
+
+def test_fmg_error_shrinks_with_refinement():
+    """The property FMG exists for: one cycle from no guess gives an
+    algebraic error that stays at the size of the discretisation error as
+    the grid is refined (relative error falling about like h^1.5 here),
+    whereas one V-cycle from zero leaves a fixed fraction of the solution.
+    Smooth manufactured solution with variable coefficient and homogeneous
+    plates (b = f: a lifted plate term would be doubled by the mean-of-8
+    restriction and spoil the coarse guess)."""
+    from oracle.exact import manufactured, sparse_solve
+    from oracle.multigrid import fmg
+    from oracle.operator import rhs
+    rel_fmg = []
+    for n in (16, 32):
+        phi, a, f = manufactured(n, 0.0)
+        h = (1 / n,) * 3
+        ph = sparse_solve(a, f, h, 0.0, 0.0)
+        b = rhs(f, a, h, 0.0, 0.0)
+        hier = build_hierarchy(a, h)
+        disc = np.linalg.norm(ph - phi)
+        alg_fmg = np.linalg.norm(fmg(hier, b) - ph)
+        alg_v = np.linalg.norm(vcycle(hier, b) - ph)
+        assert alg_fmg < 5 * disc, (n, alg_fmg, disc)
+        assert alg_v > 10 * alg_fmg, (n, alg_v, alg_fmg)
+        rel_fmg.append(alg_fmg / np.linalg.norm(ph))
+    assert rel_fmg[0] < 0.015 and rel_fmg[1] < 0.5 * rel_fmg[0], rel_fmg
