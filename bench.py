@@ -97,6 +97,10 @@ def bytes_per_cell(base, level, s, nu_post=2):
             return 3 * s + s / 8
         if base == "prolong_add":  # the red half of X read and written (both halves without post-sweeps)
             return (1 if nu_post > 0 else 2) * s + s / 8
+        if base == "restrict_rhs":  # u (float64) read; B and the coarse right side (1/8) written
+            return 8 + s + s / 8
+        if base == "prolong_set":  # coarse x read, X (both colours) written
+            return s + s / 8
         return None
     if level is not None and level > 0:  # face coefficients wx, wy, wz (plates neglected)
         if base == "gs":  # x, faces read; b, x of the own colour read / written
@@ -107,6 +111,10 @@ def bytes_per_cell(base, level, s, nu_post=2):
             return s + s + 3 * s + s / 8
         if base == "prolong_add":  # x read and written, coarse x read
             return 2 * s + s / 8
+        if base == "restrict":  # b read, coarse right side written
+            return s + s / 8
+        if base == "prolong_set":  # coarse x read, x written
+            return s + s / 8
     return None
 
 

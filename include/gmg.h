@@ -67,6 +67,11 @@ enum { GMG_FP64 = 0, GMG_MIXED = 1 };
  * float32 rounding). */
 enum { GMG_SWEEP_AUTO = 0, GMG_SWEEP_HALF = 1, GMG_SWEEP_FUSED = 2 };
 
+/* Preconditioner of a solve started without an initial guess (Sec. 3.2: FMG
+ * on the first time step, which starts from zero; V-cycles once the previous
+ * solution is the guess). */
+enum { GMG_CYCLE_V = 0, GMG_CYCLE_FMG = 1 };
+
 /* Solver options.  gmg_default_options fills the defaults given below. */
 typedef struct gmg_options {
   int restart;          /* Krylov dimension m of FGMRES(m), 1..32 (default 10)   */
@@ -83,7 +88,11 @@ typedef struct gmg_options {
                            of at least two levels; half-sweeps otherwise);
                            GMG_SWEEP_AUTO (default): fused where it was
                            measured faster (float32, long z-chunks) */
-  int reserved[3];      /* must be zero */
+  int cold_cycle;       /* preconditioner of a solve with use_x0 = 0: GMG_CYCLE_FMG
+                           (default) one full multigrid cycle per step,
+                           GMG_CYCLE_V one V-cycle per step.  Warm-started
+                           solves always use V-cycles. */
+  int reserved[2];      /* must be zero */
 } gmg_options;
 
 void gmg_default_options(gmg_options* opt);
@@ -144,6 +153,13 @@ int gmg_apply_operator(gmg_ctx* ctx, const double* x_dev, double* y_dev,
  * to float32 and the float32 result is promoted exactly).  v and z must not
  * overlap. */
 int gmg_vcycle(gmg_ctx* ctx, const double* v_dev, double* z_dev);
+
+/* One full multigrid cycle with right side v (Sec. 3.2, FMG for a solve
+ * without an initial guess): the right side restricted (mean of the 8
+ * children) to every level, the coarsest level solved directly, then on each
+ * finer level one V-cycle from the interpolated coarser result.  z = F v, a
+ * fixed linear map; precision, layout, overlap and errors as gmg_vcycle. */
+int gmg_fmg(gmg_ctx* ctx, const double* v_dev, double* z_dev);
 
 /* Gradient with respect to the coefficient of a loss L(phi) through the
  * solve, given phi (the solution for plate values phi_bot, phi_top) and the

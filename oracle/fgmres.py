@@ -114,7 +114,7 @@ def fgmres(A, b, M, x0=None, tol=1e-8, restart=10, max_iter=200,
 
 def solve_poisson(a, f, h, phi_bot=0.0, phi_top=1.0, tol=1e-8, restart=10,
                   max_iter=200, nu_pre=2, nu_post=2, precision="fp64",
-                  x0=None, coarse_max_cells=4096, cold="vcycle"):
+                  x0=None, coarse_max_cells=4096, cold="fmg"):
     """FGMRES(restart) with one multigrid cycle per step on A phi = f +
     lifting.
 

@@ -19,7 +19,8 @@ class Options(ctypes.Structure):
         ("precision", c_int),
         ("coarse_max_cells", c_int),
         ("fine_sweep", c_int),
-        ("reserved", c_int * 3),
+        ("cold_cycle", c_int),
+        ("reserved", c_int * 2),
     ]
 
 
@@ -35,6 +36,7 @@ SIGNATURES = {
                              P_int, P_double, c_int, P_int, P_double]),
     "gmg_apply_operator": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double]),
     "gmg_vcycle": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmg_fmg": (c_int, [c_void_p, c_void_p, c_void_p]),
     "gmg_face_flux_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p]),
     "gmg_get_levels": (c_int, [c_void_p, P_int, P_int, c_int]),
     "gmg_profile_enable": (c_int, [c_void_p, c_int]),
@@ -55,9 +57,12 @@ def load():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_1812_08606_amd.build` (hipcc, gfx950)")
+                          "`python paper_1812_08606_amd/build.py` (hipcc, gfx950)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
+        if not hasattr(lib, name):
+            raise ImportError(f"{LIB_PATH} does not export {name} (built from older sources): "
+                              "rebuild it with `python paper_1812_08606_amd/build.py`")
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args

@@ -1,6 +1,9 @@
 """Compile the HIP library libgmg.so in-tree for gfx950 with hipcc.
 
-    python -m paper_1812_08606_amd.build
+    python paper_1812_08606_amd/build.py
+
+(run as a script: importing the package loads the library, which may be
+missing or built from older sources).
 """
 import os
 import shutil
@@ -11,7 +14,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgmg.so")
 SOURCES = [os.path.join(HERE, "csrc", "gmg.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "gmg_kernels.hpp"), os.path.join(ROOT, "include", "gmg.h")]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -72,6 +72,7 @@ bool options_valid(const gmg_options* o) {
   if (o->precision != GMG_FP64 && o->precision != GMG_MIXED) return false;
   if (o->coarse_max_cells < 1 || o->coarse_max_cells > 4096) return false;
   if (o->fine_sweep < GMG_SWEEP_AUTO || o->fine_sweep > GMG_SWEEP_FUSED) return false;
+  if (o->cold_cycle != GMG_CYCLE_V && o->cold_cycle != GMG_CYCLE_FMG) return false;
   for (int r : o->reserved)
     if (r) return false;
   return true;
@@ -223,6 +224,7 @@ struct gmg_ctx {
   bool mixed;
   int nc;  // cells on the coarsest level
   int bottom_from;  // first level run by the one-workgroup bottom kernel (-1: none)
+  bool fmg_now;     // the running solve preconditions with full multigrid cycles
   double* pinned;
   hipError_t err;
   Profiler prof;
@@ -478,18 +480,24 @@ Launch pair_launch(int nx, int ny, int nz, long long target, int min_kc) {
 // Coarse level l (not the coarsest, so every dimension is even): red-black
 // smoothing, residual and restriction with the lane-pair kernels on the
 // stored face coefficients.
+// From x = 0, or from the guess in x when from_x.
 template <typename T>
-void smooth_pre_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co) {
+void smooth_pre_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co, bool from_x) {
   const LevelShape& s = c->L.shapes[l];
   const Geom g = s.geom();
   const int nu = c->opt.nu_pre;
   if (nu == 0) {
-    const Launch fl = flat_launch(s.n());
-    GMG_LAUNCH(c, kname("fill", l, sizeof(T)), k_fill<T>, fl, x, T(0), s.n());
+    if (!from_x) {
+      const Launch fl = flat_launch(s.n());
+      GMG_LAUNCH(c, kname("fill", l, sizeof(T)), k_fill<T>, fl, x, T(0), s.n());
+    }
     return;
   }
   const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
-  GMG_LAUNCH(c, kname("gs_first", l, sizeof(T)), (k_gs_pair_face<T, true>), pl, x, b, co, g, pl.kc, 0);
+  if (from_x)
+    GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, g, pl.kc, 0);
+  else
+    GMG_LAUNCH(c, kname("gs_first", l, sizeof(T)), (k_gs_pair_face<T, true>), pl, x, b, co, g, pl.kc, 0);
   GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, g, pl.kc, 1);
   for (int it = 1; it < nu; ++it) {
     GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, g, pl.kc, 0);
@@ -524,6 +532,24 @@ void prolong_add(gmg_ctx* c, int l, T* x, const T* xc) {
              pl.kc);
 }
 
+// Levels >= 1: x = P xc, the interpolated guess of a full multigrid cycle.
+template <typename T>
+void prolong_set(gmg_ctx* c, int l, T* x, const T* xc) {
+  const LevelShape& s = c->L.shapes[l];
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2);
+  GMG_LAUNCH(c, kname("prolong_set", l, sizeof(T)), (k_prolong_pair<T, false, true>), pl, x, xc, s.geom(),
+             (size_t)0, 0, pl.kc);
+}
+
+// Levels >= 1: right side of level l+1 = mean of the 8 children of level l's.
+template <typename T>
+void restrict_mean(gmg_ctx* c, int l) {
+  const LevelShape& s = c->L.shapes[l];
+  const Launch rl{dim3((s.nx / 2 + BX - 1) / BX, (s.ny / 2 + BY - 1) / BY, s.nz / 2), dim3(BX, BY, 1), 0};
+  GMG_LAUNCH(c, kname("restrict", l, sizeof(T)), k_restrict_mean<T>, rl, wsp<const T>(c, c->L.lv[l].b),
+             wsp<T>(c, c->L.lv[l + 1].b), s.geom());
+}
+
 template <typename T>
 void coarse_solve(gmg_ctx* c, const T* b, T* x) {
   const int n = c->nc;
@@ -532,13 +558,18 @@ void coarse_solve(gmg_ctx* c, const T* b, T* x) {
              wsp<const T>(c, c->L.cinv), b, x, n);
 }
 
-// The levels from l0 down to the coarsest in one workgroup (k_vcycle_bottom);
-// its arguments were written to the workspace at set-up.
+// The levels from l0 down to the coarsest in one workgroup (k_vcycle_bottom):
+// a V-cycle, or the full multigrid cycle over those levels when fmg; its
+// arguments were written to the workspace at set-up.
 template <typename T>
-void vcycle_bottom(gmg_ctx* c) {
+void vcycle_bottom(gmg_ctx* c, int fmg) {
   const Launch one{dim3(1), dim3(BottomThreads<T>::value, 1, 1), 0};
-  GMG_LAUNCH(c, kname("vcycle_bottom", c->bottom_from, sizeof(T)), k_vcycle_bottom<T>, one,
-             wsp<const BottomArgs<T>>(c, c->L.bargs));
+  if (fmg)
+    GMG_LAUNCH(c, kname("fmg_bottom", c->bottom_from, sizeof(T)), (k_vcycle_bottom<T, true>), one,
+               wsp<const BottomArgs<T>>(c, c->L.bargs));
+  else
+    GMG_LAUNCH(c, kname("vcycle_bottom", c->bottom_from, sizeof(T)), (k_vcycle_bottom<T, false>), one,
+               wsp<const BottomArgs<T>>(c, c->L.bargs));
 }
 
 // Arguments of the bottom kernel (fixed for the life of the context).
@@ -563,9 +594,12 @@ int write_bottom_args(gmg_ctx* c) {
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }
 
-// Levels >= 1 (face coefficients), right side in lv[l].b, result in lv[l].x.
+// Levels >= 1 (face coefficients), right side in lv[l].b, result in lv[l].x:
+// a V-cycle from x = 0, or from the guess in lv[l].x when from_x (the
+// coarsest level is solved directly either way; a guess is never passed to
+// the bottom kernel's first level).
 template <typename T>
-void vcycle_coarse(gmg_ctx* c, int l) {
+void vcycle_coarse(gmg_ctx* c, int l, bool from_x = false) {
   const int nl = (int)c->L.shapes.size();
   const LevelOffsets& o = c->L.lv[l];
   T* x = wsp<T>(c, o.x);
@@ -575,15 +609,35 @@ void vcycle_coarse(gmg_ctx* c, int l) {
     return;
   }
   if (l == c->bottom_from) {
-    vcycle_bottom<T>(c);
+    vcycle_bottom<T>(c, 0);
     return;
   }
   const FaceCoef<T> co = face_coef<T>(c, l);
-  smooth_pre_face<T>(c, l, x, b, co);
+  smooth_pre_face<T>(c, l, x, b, co, from_x);
   resid_restrict_face<T>(c, l, x, b, co, wsp<T>(c, c->L.lv[l + 1].b));
   vcycle_coarse<T>(c, l + 1);
   prolong_add<T>(c, l, x, wsp<T>(c, c->L.lv[l + 1].x));
   smooth_post_face<T>(c, l, x, b, co);
+}
+
+// Full multigrid cycle on the levels >= l0 for the right side in lv[l0].b,
+// result in lv[l0].x: right sides restricted down to the bottom kernel's
+// first level (or the coarsest), the bottom kernel's full multigrid cycle
+// over its levels (or the direct solve), then level by level upwards the
+// interpolated coarser result as the guess of one V-cycle.
+template <typename T>
+void fmg_coarse(gmg_ctx* c, int l0) {
+  const int nl = (int)c->L.shapes.size();
+  const int lb = c->bottom_from >= 0 ? c->bottom_from : nl - 1;
+  for (int l = l0; l < lb; ++l) restrict_mean<T>(c, l);
+  if (c->bottom_from >= 0)
+    vcycle_bottom<T>(c, 1);
+  else
+    coarse_solve<T>(c, wsp<const T>(c, c->L.lv[nl - 1].b), wsp<T>(c, c->L.lv[nl - 1].x));
+  for (int l = lb - 1; l >= l0; --l) {
+    prolong_set<T>(c, l, wsp<T>(c, c->L.lv[l].x), wsp<const T>(c, c->L.lv[l + 1].x));
+    vcycle_coarse<T>(c, l, true);
+  }
 }
 
 // Finest level on colour-split storage (at least two levels, so every
@@ -609,20 +663,23 @@ void gs_split(gmg_ctx* c, T* X, T* B, const double* u, const double* bscale, con
 // and restriction; coarse correction (added to the red cells only when a
 // black half-sweep follows, which overwrites the black cells without reading
 // them); post-smoothing black, red (nu_post times).
+// from_x: B already holds the right side and X the guess (both colours).
 template <typename T>
-void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X) {
+void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X, bool from_x) {
   const LevelShape& s = c->L.shapes[0];
   const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
   T* B = wsp<T>(c, c->L.b0);
   const size_t hn = c->L.hn;
   const int npre = c->opt.nu_pre, npost = c->opt.nu_post;
-  gs_split<T, true>(c, X, B, u, bscale, a, 0);
-  if (npre == 0) {  // no pre-smoothing: x = 0 (B is kept)
-    const Launch fl = flat_launch(2 * hn);
-    GMG_LAUNCH(c, kname("fill", 0, sizeof(T)), k_fill<T>, fl, X, T(0), 2 * hn);
+  if (!from_x) {
+    gs_split<T, true>(c, X, B, u, bscale, a, 0);
+    if (npre == 0) {  // no pre-smoothing: x = 0 (B is kept)
+      const Launch fl = flat_launch(2 * hn);
+      GMG_LAUNCH(c, kname("fill", 0, sizeof(T)), k_fill<T>, fl, X, T(0), 2 * hn);
+    }
   }
   for (int it = 0; it < npre; ++it) {
-    if (it > 0) gs_split<T, false>(c, X, B, nullptr, nullptr, a, 0);
+    if (it > 0 || from_x) gs_split<T, false>(c, X, B, nullptr, nullptr, a, 0);
     gs_split<T, false>(c, X, B, nullptr, nullptr, a, 1);
   }
   {
@@ -668,19 +725,30 @@ void sym_split(gmg_ctx* c, const T* Xin, T* Xout, T* B, const double* u, const d
     GMG_LAUNCH(c, nm, (k_sym_split<T, FIRST, false>), l, Xin, Xout, B, u, bscale, a, s.geom(), c->L.hn, l.kc, c1);
 }
 
-// z = M (s * u) with fused symmetric sweeps (nu_pre, nu_post >= 1): the
+// Buffer of sweep p (1-based; p = 0 the guess) of vcycle_fine_sym: the
 // sweeps ping-pong between the scratch iterate and z so that the last one
-// lands in z.  Same arithmetic as vcycle_fine_split.
+// lands in z.
 template <typename T>
-void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z) {
+T* sym_buffer(gmg_ctx* c, T* Z, int p) {
+  const int L = c->opt.nu_pre + c->opt.nu_post;
+  return ((L - p) % 2 == 0) ? Z : wsp<T>(c, c->L.xs);
+}
+
+// z = M (s * u) with fused symmetric sweeps (nu_pre, nu_post >= 1).  Same
+// arithmetic as vcycle_fine_split.  from_x: B already holds the right side
+// and sym_buffer(c, Z, 0) the guess.
+template <typename T>
+void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z, bool from_x) {
   const LevelShape& s = c->L.shapes[0];
   const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
   T* B = wsp<T>(c, c->L.b0);
-  T* XS = wsp<T>(c, c->L.xs);
   const size_t hn = c->L.hn;
   const int npre = c->opt.nu_pre, npost = c->opt.nu_post, L = npre + npost;
-  auto buf = [&](int p) { return ((L - p) % 2 == 0) ? Z : XS; };  // written by sweep p (1-based)
-  sym_split<T, true>(c, nullptr, buf(1), B, u, bscale, a, 0);
+  auto buf = [&](int p) { return sym_buffer<T>(c, Z, p); };
+  if (from_x)
+    sym_split<T, false>(c, buf(0), buf(1), B, nullptr, nullptr, a, 0);
+  else
+    sym_split<T, true>(c, nullptr, buf(1), B, u, bscale, a, 0);
   for (int p = 2; p <= npre; ++p) sym_split<T, false>(c, buf(p - 1), buf(p), B, nullptr, nullptr, a, 0);
   T* X = buf(npre);
   {
@@ -695,6 +763,20 @@ void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z) {
                (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, 1, l.kc);
   }
   for (int p = npre + 1; p <= L; ++p) sym_split<T, false>(c, buf(p - 1), buf(p), B, nullptr, nullptr, a, 1);
+}
+
+// Fused symmetric sweeps on the finest level (float32 only, both smoothing
+// phases present): on request, or by default when their z-chunks are long.
+// Each chunk of the fused sweep adds two planes of first-colour work and a
+// pipeline fill, so it only wins with chunks of 32 planes or more (measured:
+// 5% per V-cycle at 768^3, 2% at 512^3; 9-22% slower at 384^3 and 256^3,
+// with 21- and 8-plane chunks).  In float64 the fused kernel's register
+// demand halves its block size and it was slower at every size.
+template <typename T>
+bool fused_sweeps(gmg_ctx* c) {
+  const int fs = c->opt.fine_sweep;
+  return sizeof(T) == 4 && c->L.shapes.size() > 1 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 &&
+         (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(c->L.shapes[0]).kc >= 32));
 }
 
 // z = M (s * u) on the finest level with right side u scaled by *bscale
@@ -718,27 +800,57 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     coarse_solve<T>(c, b0, z);
     return;
   }
-  // Fused symmetric sweeps (float32 only, both smoothing phases present):
-  // on request, or by default when their z-chunks are long.  Each chunk of
-  // the fused sweep adds two planes of first-colour work and a pipeline
-  // fill, so it only wins with chunks of 32 planes or more (measured: 5% per
-  // V-cycle at 768^3, 2% at 512^3; 9-22% slower at 384^3 and 256^3, with 21-
-  // and 8-plane chunks).  In float64 the fused kernel's register demand
-  // halves its block size and it was slower at every size.
-  const int fs = c->opt.fine_sweep;
-  const bool fused = sizeof(T) == 4 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 &&
-                     (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(s).kc >= 32));
-  if (fused)
-    vcycle_fine_sym<T>(c, u, bscale, z);
+  if (fused_sweeps<T>(c))
+    vcycle_fine_sym<T>(c, u, bscale, z, false);
   else
-    vcycle_fine_split<T>(c, u, bscale, z);
+    vcycle_fine_split<T>(c, u, bscale, z, false);
 }
 
-void vcycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z) {
-  if (c->mixed)
-    vcycle_fine<float>(c, u, bscale, (float*)z);
+// Full multigrid cycle z = F (s * u) on the whole hierarchy: the right side
+// B (colour-split) and its restriction in one pass, the full multigrid cycle
+// on levels >= 1, then the interpolated level-1 result as the guess of one
+// finest-level V-cycle.
+template <typename T>
+void fmg_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
+  if (c->L.shapes.size() == 1) {  // one level: the direct solve
+    vcycle_fine<T>(c, u, bscale, z);
+    return;
+  }
+  const LevelShape& s = c->L.shapes[0];
+  const size_t hn = c->L.hn;
+  T* B = wsp<T>(c, c->L.b0);
+  {
+    const Launch rl{dim3((s.nx / 2 + BX - 1) / BX, (s.ny / 2 + BY - 1) / BY, s.nz / 2), dim3(BX, BY, 1), 0};
+    GMG_LAUNCH(c, kname("restrict_rhs", 0, sizeof(T)), k_restrict_split_rhs<T>, rl, u, bscale, B,
+               wsp<T>(c, c->L.lv[1].b), s.geom(), hn);
+  }
+  fmg_coarse<T>(c, 1);
+  const bool fused = fused_sweeps<T>(c);
+  T* X0 = fused ? sym_buffer<T>(c, z, 0) : z;
+  {
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    GMG_LAUNCH(c, kname("prolong_set", 0, sizeof(T)), (k_prolong_pair<T, true, true>), l, X0,
+               (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, 2, l.kc);
+  }
+  if (fused)
+    vcycle_fine_sym<T>(c, u, bscale, z, true);
   else
-    vcycle_fine<double>(c, u, bscale, (double*)z);
+    vcycle_fine_split<T>(c, u, bscale, z, true);
+}
+
+// One preconditioner application: V-cycle, or full multigrid when fmg.
+void cycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z, bool fmg) {
+  if (c->mixed) {
+    if (fmg)
+      fmg_fine<float>(c, u, bscale, (float*)z);
+    else
+      vcycle_fine<float>(c, u, bscale, (float*)z);
+  } else {
+    if (fmg)
+      fmg_fine<double>(c, u, bscale, (double*)z);
+    else
+      vcycle_fine<double>(c, u, bscale, (double*)z);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -854,7 +966,7 @@ void arnoldi_step(gmg_ctx* c, int j) {
   char* Zb = c->ws + c->L.Z + (size_t)j * N * c->L.tsize;
   double* vs = scal_vscale(c);
   double* hc = scal_hcol(c, j);
-  vcycle_any(c, V + (size_t)j * N, vs + j, Zb);
+  cycle_any(c, V + (size_t)j * N, vs + j, Zb, c->fmg_now);
   const Launch rl = opdot_launch(c);
   const Launch fl = red_flat(c);
   double* w = V + (size_t)(j + 1) * N;
@@ -922,6 +1034,7 @@ void gmg_default_options(gmg_options* opt) {
   opt->precision = GMG_MIXED;
   opt->coarse_max_cells = 4096;
   opt->fine_sweep = GMG_SWEEP_AUTO;
+  opt->cold_cycle = GMG_CYCLE_FMG;
 }
 
 size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt) {
@@ -1016,6 +1129,7 @@ int fgmres_solve(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top
     const Launch fl = flat_launch(c->N);
     GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
   }
+  c->fmg_now = !use_x0 && c->opt.cold_cycle == GMG_CYCLE_FMG;
   double* misc = scal_misc(c);
   bool first = true;
   double bnorm = 0.0;
@@ -1094,12 +1208,13 @@ int gmg_apply_operator(gmg_ctx* c, const double* x_dev, double* y_dev, double ph
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }
 
-int gmg_vcycle(gmg_ctx* c, const double* v_dev, double* z_dev) {
+namespace {
+int cycle_api(gmg_ctx* c, const double* v_dev, double* z_dev, bool fmg) {
   if (!valid_ctx(c) || !v_dev || !z_dev) return GMG_ERR_ARG;
   const bool split = c->L.shapes.size() > 1;
   if (c->mixed) {
     float* z32 = wsp<float>(c, c->L.Z);
-    vcycle_fine<float>(c, v_dev, nullptr, z32);
+    cycle_any(c, v_dev, nullptr, z32, fmg);
     const Launch fl = flat_launch(c->N);
     if (split) {  // z = 0 + 1 * z32, exact, into the natural layout
       GMG_LAUNCH(c, "fill", k_fill<double>, fl, z_dev, 0.0, c->N);
@@ -1111,18 +1226,23 @@ int gmg_vcycle(gmg_ctx* c, const double* v_dev, double* z_dev) {
     }
   } else if (split) {
     double* z64 = wsp<double>(c, c->L.Z);
-    vcycle_fine<double>(c, v_dev, nullptr, z64);
+    cycle_any(c, v_dev, nullptr, z64, fmg);
     const Launch fl = flat_launch(c->N);
     GMG_LAUNCH(c, "fill", k_fill<double>, fl, z_dev, 0.0, c->N);
     Coeffs16 one{};
     one.v[0] = 1.0;
     launch_update<double, 1>(c, fl, z_dev, z64, one);
   } else {
-    vcycle_fine<double>(c, v_dev, nullptr, z_dev);
+    cycle_any(c, v_dev, nullptr, z_dev, fmg);
   }
   note(c, hipStreamSynchronize(c->stream));
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }
+}  // namespace
+
+int gmg_vcycle(gmg_ctx* c, const double* v_dev, double* z_dev) { return cycle_api(c, v_dev, z_dev, false); }
+
+int gmg_fmg(gmg_ctx* c, const double* v_dev, double* z_dev) { return cycle_api(c, v_dev, z_dev, true); }
 
 int gmg_face_flux_grad(gmg_ctx* c, const double* phi_dev, const double* lam_dev, double phi_bot, double phi_top,
                        double* dLda_dev) {

@@ -531,7 +531,9 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_split(const T* __re
 // two cells of a pair differ only in their x-neighbour (m-1 for cell 2m, m+1
 // for cell 2m+1).  SPLIT: the fine x is colour-split and only the colours
 // c < ncol are corrected; otherwise the fine x is natural (every cell).
-template <typename T, bool SPLIT>
+// SET: x = P xc (the interpolated initial guess of a full multigrid cycle)
+// instead of x += P xc.
+template <typename T, bool SPLIT, bool SET = false>
 __global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, const T* __restrict__ xc, Geom g,
                                                            size_t hn, int ncol, int kc) {
   const Tile tl = xcd_tile();
@@ -577,12 +579,13 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, co
       if (SPLIT) {
         for (int c = 0; c < ncol; ++c) {
           const int e = (c + j + k) & 1;
-          x[(size_t)c * hn + sidx(g, m, j, k)] += e ? vr : vl;
+          T& dst = x[(size_t)c * hn + sidx(g, m, j, k)];
+          dst = SET ? (e ? vr : vl) : dst + (e ? vr : vl);
         }
       } else {
         const size_t cn = ((size_t)k * g.ny + j) * g.nx + 2 * m;
-        x[cn] += vl;
-        x[cn + 1] += vr;
+        x[cn] = SET ? vl : x[cn] + vl;
+        x[cn + 1] = SET ? vr : x[cn + 1] + vr;
       }
     }
     lb = lc;
@@ -590,6 +593,58 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, co
     lc = lt;
     rc = rt;
   }
+}
+
+// Right sides of a full multigrid cycle on the finest level: B = s u stored
+// by colour (s = *bscale, or 1 when bscale is null; rounded to T) and the
+// next level's right side bc = mean over the 8 children of the rounded
+// values.  One thread per coarse cell, reading its children as x-pairs.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_restrict_split_rhs(const double* __restrict__ u,
+                                                                 const double* __restrict__ bscale,
+                                                                 T* __restrict__ B, T* __restrict__ bc, Geom g,
+                                                                 size_t hn) {
+  const int H = g.nx >> 1, NY = g.ny >> 1;
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int J = blockIdx.y * BY + threadIdx.y;
+  const int K = blockIdx.z;
+  if (I >= H || J >= NY) return;
+  const double s = bscale ? *bscale : 1.0;
+  T sum = T(0);
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+      const int j = 2 * J + dj, k = 2 * K + dk;
+      const size_t cn = ((size_t)k * g.ny + j) * g.nx + 2 * I;
+      const double2 v = *reinterpret_cast<const double2*>(u + cn);
+      const T v0 = (T)(v.x * s), v1 = (T)(v.y * s);
+      const size_t q = sidx(g, I, j, k);
+      const int e = (j + k) & 1;  // colour of cell 2I
+      B[(size_t)e * hn + q] = v0;
+      B[(size_t)(1 - e) * hn + q] = v1;
+      sum += v0 + v1;
+    }
+  bc[((size_t)K * NY + J) * H + I] = sum * T(0.125);
+}
+
+// bc = mean over the 8 children of b (natural layout, every dimension even).
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_restrict_mean(const T* __restrict__ b, T* __restrict__ bc, Geom g) {
+  const int NX = g.nx >> 1, NY = g.ny >> 1;
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int J = blockIdx.y * BY + threadIdx.y;
+  const int K = blockIdx.z;
+  if (I >= NX || J >= NY) return;
+  T sum = T(0);
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+      const size_t cn = ((size_t)(2 * K + dk) * g.ny + 2 * J + dj) * g.nx + 2 * I;
+      sum += b[cn] + b[cn + 1];
+    }
+  bc[((size_t)K * NY + J) * NX + I] = sum * T(0.125);
 }
 
 // w = A z (z colour-split, promoted to float64) and the dots (w, u_v),

@@ -483,30 +483,73 @@ __device__ __forceinline__ void bottom_half_sweep(T* __restrict__ x, const T* __
   }
 }
 
+// x += P xc (or x = P xc when set) on level g from the next level in LDS:
+// cell-centred trilinear interpolation with mirrored ghosts on the sides and
+// negated ones through the plates.
 template <typename T>
-__global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const BottomArgs<T>* __restrict__ A) {
-  __shared__ T lx[BOTTOM_LDS_CELLS], lb[BOTTOM_LDS_CELLS];
-  const int L = A->nlev - 1;  // index of the coarsest level
-  const int nu_pre = A->nu_pre, nu_post = A->nu_post;
-  {
-    const int n0 = geom_cells(A->g[0]);
-    for (int c = threadIdx.x; c < n0; c += BottomThreads<T>::value) lb[c] = A->b0[c];
-    __syncthreads();
+__device__ __forceinline__ void bottom_prolong(T* __restrict__ x, const T* __restrict__ xc, const Geom& g, bool set) {
+  const int n = geom_cells(g);
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  for (int c = threadIdx.x; c < n; c += BottomThreads<T>::value) {
+    const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    int I2 = I + ((i & 1) ? 1 : -1);
+    if (I2 < 0 || I2 >= NX) I2 = I;
+    int J2 = J + ((j & 1) ? 1 : -1);
+    if (J2 < 0 || J2 >= NY) J2 = J;
+    int K2 = K + ((k & 1) ? 1 : -1);
+    T sk = T(1);
+    if (K2 < 0 || K2 >= NZ) {
+      K2 = K;
+      sk = T(-1);
+    }
+    const T q3 = T(0.75), q1 = T(0.25);
+    const T* p = xc + K * NY * NX;
+    const T* q = xc + K2 * NY * NX;
+    const T pl = q3 * (q3 * p[J * NX + I] + q1 * p[J * NX + I2]) + q1 * (q3 * p[J2 * NX + I] + q1 * p[J2 * NX + I2]);
+    const T ql = q3 * (q3 * q[J * NX + I] + q1 * q[J * NX + I2]) + q1 * (q3 * q[J2 * NX + I] + q1 * q[J2 * NX + I2]);
+    const T v = q3 * pl + q1 * sk * ql;
+    x[c] = set ? v : x[c] + v;
   }
-  int off = 0;  // LDS offset of level l
-  for (int l = 0; l < L; ++l) {
+}
+
+// Coarsest level in LDS: x = A_L^{-1} b.
+template <typename T>
+__device__ __forceinline__ void bottom_coarsest(T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ Ainv,
+                                                int n) {
+  for (int r = threadIdx.x; r < n; r += BottomThreads<T>::value) {
+    T acc = T(0);
+    for (int c = 0; c < n; ++c) acc += Ainv[(size_t)c * n + r] * b[c];
+    x[r] = acc;
+  }
+}
+
+// V-cycle on the levels l0 .. L of the bottom kernel (L the coarsest), right
+// side of level l0 in lb + off0; from x = 0, or from the guess in lx + off0
+// when from_x (the coarser levels start from 0 either way).  Levels are
+// stored one after the other in lx / lb.
+template <typename T>
+__device__ __forceinline__ void bottom_cycle(T* __restrict__ lx, T* __restrict__ lb,
+                                             const BottomArgs<T>* __restrict__ A, int l0, int off0, bool from_x) {
+  const int L = A->nlev - 1;
+  const int nu_pre = A->nu_pre, nu_post = A->nu_post;
+  int off = off0;
+  for (int l = l0; l < L; ++l) {
     const Geom g = A->g[l];
     const FaceCoef<T> co = A->co[l];
     T* x = lx + off;
     T* b = lb + off;
-    bottom_half_sweep<T>(x, b, co, g, 0, true);  // red from x = 0 (black set to 0)
-    if (nu_pre == 0) {
+    const bool guess = from_x && l == l0;
+    if (!guess) {
+      bottom_half_sweep<T>(x, b, co, g, 0, true);  // red from x = 0 (black set to 0)
+      if (nu_pre == 0) {
+        __syncthreads();
+        for (int c = threadIdx.x; c < geom_cells(g); c += BottomThreads<T>::value) x[c] = T(0);
+      }
       __syncthreads();
-      for (int c = threadIdx.x; c < geom_cells(g); c += BottomThreads<T>::value) x[c] = T(0);
     }
-    __syncthreads();
     for (int it = 0; it < nu_pre; ++it) {
-      if (it > 0) {
+      if (it > 0 || guess) {
         bottom_half_sweep<T>(x, b, co, g, 0, false);
         __syncthreads();
       }
@@ -532,55 +575,69 @@ __global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const
     __syncthreads();
     off += geom_cells(g);
   }
-  // coarsest: x = A_L^{-1} b
-  {
-    const int n = geom_cells(A->g[L]);
-    const T* b = lb + off;
-    T* x = lx + off;
-    const T* Ainv = A->Ainv;
-    for (int r = threadIdx.x; r < n; r += BottomThreads<T>::value) {
-      T acc = T(0);
-      for (int c = 0; c < n; ++c) acc += Ainv[(size_t)c * n + r] * b[c];
-      x[r] = acc;
-    }
-    __syncthreads();
-  }
-  for (int l = L - 1; l >= 0; --l) {
+  bottom_coarsest<T>(lx + off, lb + off, A->Ainv, geom_cells(A->g[L]));
+  __syncthreads();
+  for (int l = L - 1; l >= l0; --l) {
     const Geom g = A->g[l];
     const FaceCoef<T> co = A->co[l];
-    const int n = geom_cells(g);
     const int offc = off;  // level l+1
-    off -= n;              // level l
+    off -= geom_cells(g);  // level l
     T* x = lx + off;
     const T* b = lb + off;
-    const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
-    const T* xc = lx + offc;
-    for (int c = threadIdx.x; c < n; c += BottomThreads<T>::value) {
-      const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
-      const int I = i >> 1, J = j >> 1, K = k >> 1;
-      int I2 = I + ((i & 1) ? 1 : -1);
-      if (I2 < 0 || I2 >= NX) I2 = I;
-      int J2 = J + ((j & 1) ? 1 : -1);
-      if (J2 < 0 || J2 >= NY) J2 = J;
-      int K2 = K + ((k & 1) ? 1 : -1);
-      T sk = T(1);
-      if (K2 < 0 || K2 >= NZ) {
-        K2 = K;
-        sk = T(-1);
-      }
-      const T q3 = T(0.75), q1 = T(0.25);
-      const T* p = xc + K * NY * NX;
-      const T* q = xc + K2 * NY * NX;
-      const T pl = q3 * (q3 * p[J * NX + I] + q1 * p[J * NX + I2]) + q1 * (q3 * p[J2 * NX + I] + q1 * p[J2 * NX + I2]);
-      const T ql = q3 * (q3 * q[J * NX + I] + q1 * q[J * NX + I2]) + q1 * (q3 * q[J2 * NX + I] + q1 * q[J2 * NX + I2]);
-      x[c] += q3 * pl + q1 * sk * ql;
-    }
+    bottom_prolong<T>(x, lx + offc, g, false);
     __syncthreads();
     for (int it = 0; it < nu_post; ++it) {
       bottom_half_sweep<T>(x, b, co, g, 1, false);
       __syncthreads();
       bottom_half_sweep<T>(x, b, co, g, 0, false);
       __syncthreads();
+    }
+  }
+}
+
+// The levels from the first bottom level (<= 4096 cells) to the coarsest in
+// one workgroup, iterates and right sides in LDS.  FMG false: one V-cycle
+// from zero for the right side b0.  FMG true: the full multigrid cycle over these
+// levels: b0 restricted (mean of 8) to every level, the coarsest solved, then
+// on each finer level one V-cycle from the interpolated coarser solution.
+// The result of the first bottom level goes to x0.  (Two instantiations, so
+// that each inlines the V-cycle once: register pressure.)
+template <typename T, bool FMG>
+__global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const BottomArgs<T>* __restrict__ A) {
+  __shared__ T lx[BOTTOM_LDS_CELLS], lb[BOTTOM_LDS_CELLS];
+  const int L = A->nlev - 1;  // index of the coarsest level
+  {
+    const int n0 = geom_cells(A->g[0]);
+    for (int c = threadIdx.x; c < n0; c += BottomThreads<T>::value) lb[c] = A->b0[c];
+    __syncthreads();
+  }
+  if (!FMG) {
+    bottom_cycle<T>(lx, lb, A, 0, 0, false);
+  } else {
+    int off = 0;
+    for (int l = 0; l < L; ++l) {  // right sides of every level
+      const Geom g = A->g[l], gc = A->g[l + 1];
+      const T* b = lb + off;
+      T* bc = lb + off + geom_cells(g);
+      const int nc = geom_cells(gc);
+      for (int C = threadIdx.x; C < nc; C += BottomThreads<T>::value) {
+        const int I = C % gc.nx, J = (C / gc.nx) % gc.ny, K = C / (gc.nx * gc.ny);
+        T sum = T(0);
+        for (int d = 0; d < 8; ++d)
+          sum += b[cidx(g, 2 * I + (d & 1), 2 * J + ((d >> 1) & 1), 2 * K + (d >> 2))];
+        bc[C] = sum * T(0.125);
+      }
+      __syncthreads();
+      off += geom_cells(g);
+    }
+    bottom_coarsest<T>(lx + off, lb + off, A->Ainv, geom_cells(A->g[L]));
+    __syncthreads();
+    for (int l = L - 1; l >= 0; --l) {
+      const int offc = off;
+      off -= geom_cells(A->g[l]);
+      bottom_prolong<T>(lx + off, lx + offc, A->g[l], true);
+      __syncthreads();
+      bottom_cycle<T>(lx, lb, A, l, off, true);
     }
   }
   {

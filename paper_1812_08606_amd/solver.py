@@ -15,6 +15,7 @@ from . import _lib
 FP64, MIXED = 0, 1
 _PRECISION = {"fp64": FP64, "mixed": MIXED}
 _FINE_SWEEP = {"auto": 0, "half": 1, "fused": 2}
+_COLD_CYCLE = {"vcycle": 0, "fmg": 1}
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -64,11 +65,13 @@ class GMGPoisson:
     a: float64 CUDA/HIP tensor (nz, ny, nx), > 0.  h: (hx, hy, hz), default
     unit cube.  precision: "mixed" (float32 V-cycle) or "fp64".  fine_sweep:
     finest-level smoother kernels, "half" (one per half-sweep), "fused" (one
-    per symmetric sweep, float32 only) or "auto"."""
+    per symmetric sweep, float32 only) or "auto".  cold_cycle: preconditioner
+    of a solve without an initial guess, "fmg" (full multigrid, the default)
+    or "vcycle"; warm-started solves use V-cycles."""
 
     def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
                  max_iter: int = 200, nu_pre: int = 2, nu_post: int = 2,
-                 coarse_max_cells: int = 4096, fine_sweep: str = "auto"):
+                 coarse_max_cells: int = 4096, fine_sweep: str = "auto", cold_cycle: str = "fmg"):
         self._lib = _lib.load()
         if a.dim() != 3:
             raise ValueError("a must be 3-D (nz, ny, nx)")
@@ -82,6 +85,8 @@ class GMGPoisson:
         self.precision = precision
         if fine_sweep not in _FINE_SWEEP:
             raise ValueError(f"fine_sweep must be one of {sorted(_FINE_SWEEP)}")
+        if cold_cycle not in _COLD_CYCLE:
+            raise ValueError(f"cold_cycle must be one of {sorted(_COLD_CYCLE)}")
         opt = _lib.Options()
         self._lib.gmg_default_options(ctypes.byref(opt))
         opt.restart, opt.max_iter = int(restart), int(max_iter)
@@ -89,6 +94,7 @@ class GMGPoisson:
         opt.precision = _PRECISION[precision]
         opt.coarse_max_cells = int(coarse_max_cells)
         opt.fine_sweep = _FINE_SWEEP[fine_sweep]
+        opt.cold_cycle = _COLD_CYCLE[cold_cycle]
         self.options = opt
         nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
         if nbytes == 0:
@@ -183,13 +189,20 @@ class GMGPoisson:
 
     def vcycle(self, v: torch.Tensor) -> torch.Tensor:
         """One V-cycle from a zero guess: z = M v."""
+        return self._cycle(v, "gmg_vcycle")
+
+    def fmg(self, v: torch.Tensor) -> torch.Tensor:
+        """One full multigrid cycle: z = F v."""
+        return self._cycle(v, "gmg_fmg")
+
+    def _cycle(self, v: torch.Tensor, entry: str) -> torch.Tensor:
         _check_field(v, self.shape, "v", self.device)
         z = torch.empty_like(v)
         with torch.cuda.device(self.device):
             self._sync_stream()
-            st = self._lib.gmg_vcycle(self._ctx, _ptr(v), _ptr(z))
+            st = getattr(self._lib, entry)(self._ctx, _ptr(v), _ptr(z))
         if st != OK:
-            raise GMGError(st, "gmg_vcycle")
+            raise GMGError(st, entry)
         return z
 
     def face_flux_grad(self, phi: torch.Tensor, lam: torch.Tensor, phi_bot: float, phi_top: float):
@@ -216,7 +229,7 @@ class GMGPoisson:
         self._lib.gmg_profile_reset(self._ctx)
 
     def profile_read(self) -> dict:
-        cap = 64
+        cap = 256
         names = (ctypes.c_char_p * cap)()
         ms = (ctypes.c_double * cap)()
         cnt = (ctypes.c_longlong * cap)()
