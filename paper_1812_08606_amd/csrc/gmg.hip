@@ -579,11 +579,18 @@ int write_bottom_args(gmg_ctx* c) {
   if (l0 < 0) return GMG_OK;
   BottomArgs<T> A{};
   A.nlev = nl - l0;
+  int coff = 0, tpoff = 0;
   for (int q = 0; q < A.nlev; ++q) {
     const int l = l0 + q;
+    const LevelShape& s = c->L.shapes[l];
     A.co[q] = face_coef<T>(c, l);
-    A.g[q] = c->L.shapes[l].geom();
+    A.g[q] = s.geom();
+    A.coff[q] = coff;
+    A.tpoff[q] = tpoff;
+    coff += (int)s.n();
+    tpoff += s.nx * s.ny;
   }
+  if (coff > BOTTOM_LDS_CELLS || tpoff > BOTTOM_LDS_CELLS) return GMG_ERR_SHAPE;
   A.x0 = wsp<T>(c, c->L.lv[l0].x);
   A.b0 = wsp<T>(c, c->L.lv[l0].b);
   A.Ainv = wsp<const T>(c, c->L.cinv);

@@ -457,20 +457,52 @@ struct BottomArgs {
   const T* Ainv;
   int nlev;  // levels handled, the last one the coarsest
   int nu_pre, nu_post;
+  int coff[BOTTOM_MAX_LEVELS];   // offset of each level's cells in the LDS arrays
+  int tpoff[BOTTOM_MAX_LEVELS];  // offset of each level's top-plate faces
 };
+
+// Face coefficients of the bottom levels are staged in LDS in float32 (the
+// sweeps then wait on LDS instead of global memory); in float64 they would
+// not fit beside the iterates and stay in global memory.
+template <typename T>
+struct BottomFaces {
+  static constexpr bool staged = sizeof(T) == 4;
+  static constexpr int size = staged ? 4 * BOTTOM_LDS_CELLS : 1;
+};
+
+template <typename T>
+__device__ __forceinline__ FaceCoef<T> bottom_co(const BottomArgs<T>* __restrict__ A, const T* lf, int l) {
+  if (!BottomFaces<T>::staged) return A->co[l];
+  const int o = A->coff[l];
+  return FaceCoef<T>{lf + o, lf + BOTTOM_LDS_CELLS + o, lf + 2 * BOTTOM_LDS_CELLS + o,
+                     lf + 3 * BOTTOM_LDS_CELLS + A->tpoff[l]};
+}
 
 __device__ __forceinline__ int geom_cells(const Geom& g) { return g.nx * g.ny * g.nz; }
 
+// a / d for 0 <= a < 8192 and 1 <= d <= 1024 with rd = 1.0f / d: the
+// float product lies within 1e-3 of the quotient plus 1/(2d), away from an
+// integer by at least 1/(2d), so truncation gives the exact quotient (checked
+// for every such a and d).  Integer division is the slowest part of the
+// bottom kernel's index arithmetic otherwise.
+__device__ __forceinline__ int small_div(int a, float rd) { return (int)(((float)a + 0.5f) * rd); }
+
+// Half-sweep of one colour on a level whose dimensions are all even (every
+// level that is smoothed): each row holds nx/2 cells of each colour, one in
+// each x-pair; thread work items run over those cells only.  from_zero: the
+// other colour is set to 0 and the iterate is not read.
 template <typename T>
 __device__ __forceinline__ void bottom_half_sweep(T* __restrict__ x, const T* __restrict__ b, const FaceCoef<T>& co,
                                                   const Geom& g, int colour, bool from_zero) {
-  const int n = geom_cells(g);
-  for (int c = threadIdx.x; c < n; c += BottomThreads<T>::value) {
-    const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
-    if (((i + j + k) & 1) != colour) {
-      if (from_zero) x[c] = T(0);
-      continue;
-    }
+  const int H = g.nx >> 1, nh = geom_cells(g) >> 1;
+  const float rH = 1.0f / (float)H, rY = 1.0f / (float)g.ny;
+  for (int r = threadIdx.x; r < nh; r += BottomThreads<T>::value) {
+    const int row = small_div(r, rH), m = r - row * H;
+    const int k = small_div(row, rY), j = row - k * g.ny;
+    const int e = (colour + j + k) & 1;  // element of pair m with this colour
+    const int i = 2 * m + e;
+    const size_t c = cidx(g, i, j, k);
+    if (from_zero) x[c + 1 - 2 * e] = T(0);
     const Stencil<T> st = co.load(g, i, j, k, c);
     T off = T(0);
     if (!from_zero) {
@@ -479,7 +511,7 @@ __device__ __forceinline__ void bottom_half_sweep(T* __restrict__ x, const T* __
       if (k > 0) off += st.wb * v.b;
       if (k < g.nz - 1) off += st.wt * v.t;
     }
-    x[c] = (b[c] + off) / diag_cell(st, g, k);
+    x[c] = (b[c] + off) * recip(diag_cell(st, g, k));
   }
 }
 
@@ -490,8 +522,10 @@ template <typename T>
 __device__ __forceinline__ void bottom_prolong(T* __restrict__ x, const T* __restrict__ xc, const Geom& g, bool set) {
   const int n = geom_cells(g);
   const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const float rX = 1.0f / (float)g.nx, rY = 1.0f / (float)g.ny;
   for (int c = threadIdx.x; c < n; c += BottomThreads<T>::value) {
-    const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    const int row = small_div(c, rX), i = c - row * g.nx;
+    const int k = small_div(row, rY), j = row - k * g.ny;
     const int I = i >> 1, J = j >> 1, K = k >> 1;
     int I2 = I + ((i & 1) ? 1 : -1);
     if (I2 < 0 || I2 >= NX) I2 = I;
@@ -529,14 +563,14 @@ __device__ __forceinline__ void bottom_coarsest(T* __restrict__ x, const T* __re
 // when from_x (the coarser levels start from 0 either way).  Levels are
 // stored one after the other in lx / lb.
 template <typename T>
-__device__ __forceinline__ void bottom_cycle(T* __restrict__ lx, T* __restrict__ lb,
+__device__ __forceinline__ void bottom_cycle(T* __restrict__ lx, T* __restrict__ lb, const T* lf,
                                              const BottomArgs<T>* __restrict__ A, int l0, int off0, bool from_x) {
   const int L = A->nlev - 1;
   const int nu_pre = A->nu_pre, nu_post = A->nu_post;
   int off = off0;
   for (int l = l0; l < L; ++l) {
     const Geom g = A->g[l];
-    const FaceCoef<T> co = A->co[l];
+    const FaceCoef<T> co = bottom_co<T>(A, lf, l);
     T* x = lx + off;
     T* b = lb + off;
     const bool guess = from_x && l == l0;
@@ -560,8 +594,10 @@ __device__ __forceinline__ void bottom_cycle(T* __restrict__ lx, T* __restrict__
     const Geom gc = A->g[l + 1];
     T* bc = lb + off + geom_cells(g);
     const int nc = geom_cells(gc);
+    const float rX = 1.0f / (float)gc.nx, rY = 1.0f / (float)gc.ny;
     for (int C = threadIdx.x; C < nc; C += BottomThreads<T>::value) {
-      const int I = C % gc.nx, J = (C / gc.nx) % gc.ny, K = C / (gc.nx * gc.ny);
+      const int row = small_div(C, rX), I = C - row * gc.nx;
+      const int K = small_div(row, rY), J = row - K * gc.ny;
       T sum = T(0);
       for (int d = 0; d < 8; ++d) {
         const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
@@ -579,7 +615,7 @@ __device__ __forceinline__ void bottom_cycle(T* __restrict__ lx, T* __restrict__
   __syncthreads();
   for (int l = L - 1; l >= l0; --l) {
     const Geom g = A->g[l];
-    const FaceCoef<T> co = A->co[l];
+    const FaceCoef<T> co = bottom_co<T>(A, lf, l);
     const int offc = off;  // level l+1
     off -= geom_cells(g);  // level l
     T* x = lx + off;
@@ -605,14 +641,28 @@ __device__ __forceinline__ void bottom_cycle(T* __restrict__ lx, T* __restrict__
 template <typename T, bool FMG>
 __global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const BottomArgs<T>* __restrict__ A) {
   __shared__ T lx[BOTTOM_LDS_CELLS], lb[BOTTOM_LDS_CELLS];
+  __shared__ T lf[BottomFaces<T>::size];
   const int L = A->nlev - 1;  // index of the coarsest level
   {
     const int n0 = geom_cells(A->g[0]);
     for (int c = threadIdx.x; c < n0; c += BottomThreads<T>::value) lb[c] = A->b0[c];
+    if (BottomFaces<T>::staged) {
+      for (int l = 0; l <= L; ++l) {
+        const FaceCoef<T> co = A->co[l];
+        const int n = geom_cells(A->g[l]), o = A->coff[l];
+        for (int c = threadIdx.x; c < n; c += BottomThreads<T>::value) {
+          lf[o + c] = co.wx[c];
+          lf[BOTTOM_LDS_CELLS + o + c] = co.wy[c];
+          lf[2 * BOTTOM_LDS_CELLS + o + c] = co.wz[c];
+        }
+        const int np = A->g[l].nx * A->g[l].ny, op = 3 * BOTTOM_LDS_CELLS + A->tpoff[l];
+        for (int c = threadIdx.x; c < np; c += BottomThreads<T>::value) lf[op + c] = co.tp[c];
+      }
+    }
     __syncthreads();
   }
   if (!FMG) {
-    bottom_cycle<T>(lx, lb, A, 0, 0, false);
+    bottom_cycle<T>(lx, lb, lf, A, 0, 0, false);
   } else {
     int off = 0;
     for (int l = 0; l < L; ++l) {  // right sides of every level
@@ -620,8 +670,10 @@ __global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const
       const T* b = lb + off;
       T* bc = lb + off + geom_cells(g);
       const int nc = geom_cells(gc);
+      const float rX = 1.0f / (float)gc.nx, rY = 1.0f / (float)gc.ny;
       for (int C = threadIdx.x; C < nc; C += BottomThreads<T>::value) {
-        const int I = C % gc.nx, J = (C / gc.nx) % gc.ny, K = C / (gc.nx * gc.ny);
+        const int row = small_div(C, rX), I = C - row * gc.nx;
+        const int K = small_div(row, rY), J = row - K * gc.ny;
         T sum = T(0);
         for (int d = 0; d < 8; ++d)
           sum += b[cidx(g, 2 * I + (d & 1), 2 * J + ((d >> 1) & 1), 2 * K + (d >> 2))];
@@ -637,7 +689,7 @@ __global__ __launch_bounds__(BottomThreads<T>::value) void k_vcycle_bottom(const
       off -= geom_cells(A->g[l]);
       bottom_prolong<T>(lx + off, lx + offc, A->g[l], true);
       __syncthreads();
-      bottom_cycle<T>(lx, lb, A, l, off, true);
+      bottom_cycle<T>(lx, lb, lf, A, l, off, true);
     }
   }
   {
