@@ -3,8 +3,10 @@
 
 Default workload (c3): the 512^3 single-filament problem (max(a) = 1e4,
 f = 50 (n_p - n_e)), unit cube, phi = 0 / 1 on the plates, tolerance 1e-8,
-FGMRES(10) with one V(2,2)-cycle per step.  One benchmark step is one pass
-of the whole hot path: coefficient renewal (hierarchy rebuild), the forward
+FGMRES(10) with one multigrid cycle per step (V(2,2) smoothing): full
+multigrid cycles in a solve from no initial guess, V-cycles in a
+warm-started one (the library defaults).  One benchmark step is one pass of
+the whole hot path: coefficient renewal (hierarchy rebuild), the forward
 solve from a zero guess, the adjoint solve for a fixed dL/dphi and the dL/da
 face-flux kernel.  Each step therefore holds two converged 1e-8 solves;
 ``value`` counts cells x solves per second over the timed steps (inputs
@@ -386,12 +388,12 @@ def main():
     desc = {1: "constant a = 1, Gaussian source", 2: "filament, max(a)=1e3", 3: "filament, max(a)=1e4",
             4: "filament, max(a)=1e3, probe-box loss", 5: "two filaments, max(a)=1e4"}[cfg]
     if c5:
-        workload = (f"{desc} {n}^3 time loop, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
-                    "(float32 V-cycle, float64 outer); step = advect (roll) + renewal + warm-started solve")
+        workload = (f"{desc} {n}^3 time loop, tol {args.tol:g}, FGMRES(10) + V(2,2)-cycle mixed "
+                    "(float32 cycle, float64 outer); step = advect (roll) + renewal + warm-started solve")
     else:
-        workload = (f"{desc} {n}^3, tol {args.tol:g}, FGMRES(10) + V(2,2) mixed "
-                    "(float32 V-cycle, float64 outer); step = renewal + forward solve + adjoint "
-                    "solve + dL/da")
+        workload = (f"{desc} {n}^3, tol {args.tol:g}, FGMRES(10) + full multigrid cycle (V(2,2) "
+                    "smoothing) mixed (float32 cycle, float64 outer); step = renewal + forward solve + "
+                    "adjoint solve + dL/da, both from no initial guess")
     line = {
         "metric": METRIC,
         "value": value,
