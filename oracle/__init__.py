@@ -11,11 +11,13 @@ paper:
 * ``operator``  -- the finite-volume operator of eq. e18 (Sec. 2.2) with the
   plate and side boundary conditions of Sec. 1, and its right-side lifting;
 * ``multigrid`` -- the level hierarchy, red-black Gauss-Seidel smoother,
-  transfers, direct coarse solve and the zero-guess V-cycle used as the
-  preconditioner (Sec. 3.2, Appendix A);
+  transfers, direct coarse solve, the zero-guess V-cycle and the full
+  multigrid cycle used as preconditioners (Sec. 3.2, Appendix A);
 * ``fgmres``    -- FGMRES(m) of Algorithm 1 (Sec. 3.1) with the stopping rule
   of eq. criterion (Sec. 5.2);
 * ``adjoint``   -- gradient of a loss through the solve (derived from e18);
+* ``semi_implicit`` -- coefficient and right side of the elliptic problem of
+  a semi-implicit step, and E = -grad phi (Sec. 2.1-2.2);
 * ``exact``     -- independent exact references (spectral DCT/DST solve for
   constant a, sparse direct solve, manufactured solution) used to pin the
   pieces above.
