@@ -40,7 +40,7 @@ if ROOT not in sys.path:
 
 METRIC = "converged cells/s per 1e-8 Poisson solve + HBM GB/s, FP64 vs mixed, 512^3"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-KERNEL_SOURCES = ["gmg_common.hpp", "gmg_kernels.hpp", "gmg_fine.hpp", "gmg.hip"]
+KERNEL_SOURCES = ["gmg_common.hpp", "gmg_kernels.hpp", "gmg_fine.hpp", "gmg_step.hpp", "gmg.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sym_fine_f32_filament512.md")
 
 

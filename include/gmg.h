@@ -172,6 +172,35 @@ int gmg_face_flux_grad(gmg_ctx* ctx, const double* phi_dev,
                        const double* lam_dev, double phi_bot, double phi_top,
                        double* dLda_dev);
 
+/* Parameters of the elliptic problem of one semi-implicit step (Sec. 2.1,
+ * eq. semi2 / e15; Sec. 2.2, definition of P^n and eq. e18). */
+typedef struct gmg_step_params {
+  double eps0_over_e; /* eps0 / e: the vacuum part of the coefficient         */
+  double tau_eff;     /* tau_n / 2 for the predictor of the second-order scheme
+                         (eq. semi2), tau_n for the first-order scheme (e15)   */
+  double mu_e, mu_p;  /* electron and ion mobilities                           */
+  double De[3];       /* electron diffusion coefficients D_x, D_y, D_z         */
+} gmg_step_params;
+
+/* Coefficient and right side of the elliptic problem of a semi-implicit step
+ * from the densities (Sec. 2.2): a = P = eps0/e + tau_eff (mu_p n_p + mu_e n_e)
+ * and f = n_p - n_e - tau_eff sum_d D_d / h_d^2 delta_d^2 n_e (eq. e18), the
+ * second differences with ghost cells equal to the boundary cells (the
+ * homogeneous Neumann condition of n_e, Sec. 1).  ne, np, a, f: nz*ny*nx
+ * float64 on the context's grid (x fastest); a and f must not overlap ne or
+ * np.  a then goes to gmg_update_coefficient and f to fgmres_solve.  Errors:
+ * GMG_ERR_ARG for null pointers or non-finite parameters. */
+int gmg_assemble_elliptic(gmg_ctx* ctx, const double* ne_dev, const double* np_dev, const gmg_step_params* prm,
+                          double* a_dev, double* f_dev);
+
+/* Electric field E = -grad phi by central differences (Sec. 2.2, after eq.
+ * e18) and |E|: ghost cells equal to the boundary cells on the x and y sides
+ * (Neumann), mirrored through the plates (2 phi_b - phi_c) with plate values
+ * phi_bot, phi_top.  All arrays nz*ny*nx float64; the outputs must not overlap
+ * phi.  Errors: GMG_ERR_ARG for null pointers or non-finite plate values. */
+int gmg_electric_field(gmg_ctx* ctx, const double* phi_dev, double phi_bot, double phi_top, double* ex_dev,
+                       double* ey_dev, double* ez_dev, double* emag_dev);
+
 /* Hierarchy description: number of levels and, for level l < cap, its
  * (nx, ny, nz) in shapes[3l..3l+2]. */
 int gmg_get_levels(gmg_ctx* ctx, int* nlevels, int* shapes, int cap);

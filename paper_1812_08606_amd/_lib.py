@@ -24,6 +24,16 @@ class Options(ctypes.Structure):
     ]
 
 
+class StepParams(ctypes.Structure):
+    _fields_ = [
+        ("eps0_over_e", c_double),
+        ("tau_eff", c_double),
+        ("mu_e", c_double),
+        ("mu_p", c_double),
+        ("De", c_double * 3),
+    ]
+
+
 SIGNATURES = {
     "gmg_default_options": (None, [ctypes.POINTER(Options)]),
     "gmg_workspace_bytes": (c_size_t, [c_int, c_int, c_int, ctypes.POINTER(Options)]),
@@ -38,6 +48,10 @@ SIGNATURES = {
     "gmg_vcycle": (c_int, [c_void_p, c_void_p, c_void_p]),
     "gmg_fmg": (c_int, [c_void_p, c_void_p, c_void_p]),
     "gmg_face_flux_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p]),
+    "gmg_assemble_elliptic": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(StepParams), c_void_p,
+                                      c_void_p]),
+    "gmg_electric_field": (c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p,
+                                   c_void_p]),
     "gmg_get_levels": (c_int, [c_void_p, P_int, P_int, c_int]),
     "gmg_profile_enable": (c_int, [c_void_p, c_int]),
     "gmg_profile_reset": (c_int, [c_void_p]),

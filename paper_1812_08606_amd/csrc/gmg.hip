@@ -16,6 +16,7 @@
 
 #include "gmg.h"
 #include "gmg_fine.hpp"
+#include "gmg_step.hpp"
 
 using namespace gmg;
 
@@ -179,6 +180,15 @@ Launch col_launch(int nx, int ny, int nz, int max_blocks = MAX_RED_BLOCKS) {
   const int kc = (nz + gz - 1) / gz;
   gz = (nz + kc - 1) / kc;
   return Launch{dim3(gx, gy, gz), dim3(BX, BY, 1), kc};
+}
+
+// One lane per cell of a row, rows of BY threads, z-chunks of at least
+// min_kc planes, about `target` blocks.
+Launch cell_launch(int nx, int ny, int nz, long long target, int min_kc) {
+  const int gx = (nx + BX - 1) / BX, gy = (ny + BY - 1) / BY;
+  int kc = (int)std::max<long long>(min_kc, ((long long)nz * gx * gy + target - 1) / target);
+  kc = std::min(kc, nz);
+  return Launch{dim3(gx, gy, (nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
 }
 
 Launch flat_launch(size_t n) {
@@ -1257,6 +1267,33 @@ int gmg_face_flux_grad(gmg_ctx* c, const double* phi_dev, const double* lam_dev,
   const Launch lc = col_launch(c->nx, c->ny, c->nz, 1 << 16);
   GMG_LAUNCH(c, "face_grad", k_face_grad, lc, phi_dev, lam_dev, c->L.shapes[0].geom(), phi_bot, phi_top,
              dLda_dev, lc.kc);
+  note(c, hipStreamSynchronize(c->stream));
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+int gmg_assemble_elliptic(gmg_ctx* c, const double* ne_dev, const double* np_dev, const gmg_step_params* prm,
+                          double* a_dev, double* f_dev) {
+  if (!valid_ctx(c) || !ne_dev || !np_dev || !prm || !a_dev || !f_dev) return GMG_ERR_ARG;
+  const double vals[] = {prm->eps0_over_e, prm->tau_eff, prm->mu_e, prm->mu_p, prm->De[0], prm->De[1], prm->De[2]};
+  for (double v : vals)
+    if (!std::isfinite(v)) return GMG_ERR_ARG;
+  if (c->ny > 65535 * BY) return GMG_ERR_SHAPE;
+  const StepCoef p{prm->eps0_over_e, prm->tau_eff, prm->mu_e, prm->mu_p,
+                   prm->De[0] / (c->hx * c->hx), prm->De[1] / (c->hy * c->hy), prm->De[2] / (c->hz * c->hz)};
+  const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
+  GMG_LAUNCH(c, "assemble_step", k_assemble_step, l, ne_dev, np_dev, c->L.shapes[0].geom(), p, a_dev, f_dev, l.kc);
+  note(c, hipStreamSynchronize(c->stream));
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+int gmg_electric_field(gmg_ctx* c, const double* phi_dev, double phi_bot, double phi_top, double* ex_dev,
+                       double* ey_dev, double* ez_dev, double* emag_dev) {
+  if (!valid_ctx(c) || !phi_dev || !ex_dev || !ey_dev || !ez_dev || !emag_dev) return GMG_ERR_ARG;
+  if (!std::isfinite(phi_bot) || !std::isfinite(phi_top)) return GMG_ERR_ARG;
+  if (c->ny > 65535 * BY) return GMG_ERR_SHAPE;
+  const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
+  GMG_LAUNCH(c, "electric_field", k_electric_field, l, phi_dev, c->L.shapes[0].geom(), c->hx, c->hy, c->hz,
+             phi_bot, phi_top, ex_dev, ey_dev, ez_dev, emag_dev, l.kc);
   note(c, hipStreamSynchronize(c->stream));
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }

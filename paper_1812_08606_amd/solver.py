@@ -205,6 +205,40 @@ class GMGPoisson:
             raise GMGError(st, entry)
         return z
 
+    def assemble_elliptic(self, n_e: torch.Tensor, n_p: torch.Tensor, eps0_over_e: float, tau_eff: float,
+                          mu_e: float, mu_p: float, De=(0.0, 0.0, 0.0), out=None):
+        """Coefficient a = P and right side f of the elliptic problem of a
+        semi-implicit step from the densities (Sec. 2.2, eq. e18); returns
+        (a, f), written into ``out`` = (a, f) when given."""
+        _check_field(n_e, self.shape, "n_e", self.device)
+        _check_field(n_p, self.shape, "n_p", self.device)
+        a, f = out if out is not None else (torch.empty_like(n_e), torch.empty_like(n_e))
+        _check_field(a, self.shape, "a", self.device)
+        _check_field(f, self.shape, "f", self.device)
+        prm = _lib.StepParams(float(eps0_over_e), float(tau_eff), float(mu_e), float(mu_p),
+                              (ctypes.c_double * 3)(*[float(v) for v in De]))
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.gmg_assemble_elliptic(self._ctx, _ptr(n_e), _ptr(n_p), ctypes.byref(prm), _ptr(a),
+                                                 _ptr(f))
+        if st != OK:
+            raise GMGError(st, "gmg_assemble_elliptic")
+        return a, f
+
+    def electric_field(self, phi: torch.Tensor, phi_bot: float, phi_top: float, out=None):
+        """E = -grad phi by central differences and |E|: (E_x, E_y, E_z, |E|)."""
+        _check_field(phi, self.shape, "phi", self.device)
+        outs = out if out is not None else tuple(torch.empty_like(phi) for _ in range(4))
+        for o, nm in zip(outs, ("E_x", "E_y", "E_z", "|E|")):
+            _check_field(o, self.shape, nm, self.device)
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.gmg_electric_field(self._ctx, _ptr(phi), float(phi_bot), float(phi_top),
+                                              *[_ptr(o) for o in outs])
+        if st != OK:
+            raise GMGError(st, "gmg_electric_field")
+        return outs
+
     def face_flux_grad(self, phi: torch.Tensor, lam: torch.Tensor, phi_bot: float, phi_top: float):
         """dL/da from the solution phi and the adjoint lam."""
         return self.face_flux_grad_into(phi, lam, phi_bot, phi_top, torch.empty_like(phi))

@@ -494,3 +494,71 @@ def test_gradient_finite_differences_config4():
             worst = max(worst, abs(fd - g) / abs(g))
         assert abs(fd - g) <= 1e-4 * abs(g) + 1e-7 * fmax, ((k, j, i), fd, g)
     print(f"worst relative FD mismatch {worst:.2e}", flush=True)
+
+
+# ---------------------------------------------------------------- semi-implicit step
+STEP_SHAPES = [(70, 12, 8), (5, 3, 2), (1, 1, 1), (33, 17, 7), (64, 64, 64)]
+STEP_PRM = dict(eps0_over_e=0.02, tau_eff=0.35, mu_e=1.7, mu_p=0.017, De=(0.3, 0.5, 0.7))
+
+
+def _densities(shape_xyz, seed):
+    nx, ny, nz = shape_xyz
+    rng = np.random.default_rng(seed)
+    return rng.random((nz, ny, nx)), rng.random((nz, ny, nx))
+
+
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+def test_assemble_elliptic_matches_oracle(shape):
+    """Coefficient P and right side of e18 from the densities (Sec. 2.2)."""
+    from oracle.semi_implicit import coefficient, right_side
+    n_e, n_p = _densities(shape, 41)
+    a0 = np.ones_like(n_e)
+    h = (1.0 / shape[0], 1.3 / shape[1], 0.9 / shape[2])
+    s = gm.GMGPoisson(T(a0), h=h, precision="fp64")
+    a, f = s.assemble_elliptic(T(n_e), T(n_p), **STEP_PRM)
+    p = STEP_PRM
+    np.testing.assert_allclose(npy(a), coefficient(n_e, n_p, p["eps0_over_e"], p["tau_eff"], p["mu_e"], p["mu_p"]),
+                               rtol=1e-15)
+    ref = right_side(n_e, n_p, h, p["tau_eff"], p["De"])
+    np.testing.assert_allclose(npy(f), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+def test_electric_field_matches_oracle(shape):
+    from oracle.semi_implicit import electric_field
+    rng = np.random.default_rng(42)
+    nx, ny, nz = shape
+    phi = rng.standard_normal((nz, ny, nx))
+    h = (1.0 / nx, 1.3 / ny, 0.9 / nz)
+    s = gm.GMGPoisson(T(np.ones_like(phi)), h=h, precision="fp64")
+    got = s.electric_field(T(phi), 0.4, -1.2)
+    for g_, r_ in zip(got, electric_field(phi, h, 0.4, -1.2)):
+        np.testing.assert_allclose(npy(g_), r_, rtol=1e-14, atol=1e-14 * np.abs(r_).max())
+
+
+def test_semi_implicit_step_full_size():
+    """512^3: the densities of the filament workload assembled into a and f,
+    the solve, and E of the solution, each against the oracle's formula on
+    the whole grid (the solve by its residual)."""
+    from oracle.semi_implicit import coefficient, electric_field, right_side
+    from workloads.streamer import config_filament
+    p = config_filament(512, a_max=1e4, seed_number=3)
+    kappa = p.meta["kappa"]
+    n_e = (p.a - 1.0) / kappa
+    n_p = p.f / 50.0 + n_e
+    prm = dict(eps0_over_e=0.02, tau_eff=1.0, mu_e=kappa / 50.0, mu_p=kappa / 5000.0, De=(1e-6, 1e-6, 1e-6))
+    print("semi-implicit step 512^3", flush=True)
+    s = gm.GMGPoisson(T(np.ones_like(n_e)), precision="mixed")
+    a, f = s.assemble_elliptic(T(n_e), T(n_p), **prm)
+    h = (1 / 512,) * 3
+    a_ref = coefficient(n_e, n_p, prm["eps0_over_e"], prm["tau_eff"], prm["mu_e"], prm["mu_p"])
+    assert rel(npy(a), a_ref) < 1e-15
+    f_ref = right_side(n_e, n_p, h, prm["tau_eff"], prm["De"])
+    assert rel(npy(f), f_ref) < 1e-14
+    s.update_coefficient(a)
+    res = s.solve(f, 0.0, 1.0, tol=1e-8)
+    assert res.converged
+    E = s.electric_field(res.phi, 0.0, 1.0)
+    E_ref = electric_field(npy(res.phi), h, 0.0, 1.0)
+    for g_, r_ in zip(E, E_ref):
+        assert rel(npy(g_), r_) < 1e-14
