@@ -131,6 +131,10 @@ def outer_bytes(name, nv, s_z):
         return 16 + s_z * nv
     if name == "face_grad":  # phi, lam read; dL/da written
         return 24
+    if name == "assemble_step":  # n_e, n_p read; a, f written
+        return 32
+    if name == "electric_field":  # phi read; E_x, E_y, E_z, |E| written
+        return 40
     return None
 
 
@@ -246,19 +250,34 @@ def main():
         return out
 
     def run_c5(precision):
+        # the densities behind the generator's a = 1 + kappa n_e, f = 50 (n_p - n_e)
+        kappa = p.meta["kappa"]
+        ne0 = (a0 - 1.0) / kappa
+        np0 = f0 / 50.0 + ne0
+        # elliptic side (Sec. 2.2): P = eps0/e + tau_eff (mu_p n_p + mu_e n_e)
+        # is the generator's coefficient divided by 50 plus an ion term (ions
+        # 100 times slower than electrons); the right side of e18 is the
+        # generator's divided by 50 plus the diffusion term (tau_eff D / h^2 =
+        # 0.59 at 768^3)
+        step_prm = dict(eps0_over_e=1.0 / 50.0, tau_eff=1.0, mu_e=kappa / 50.0, mu_p=kappa / 5000.0,
+                        De=(1e-6, 1e-6, 1e-6))
         solver = gm.GMGPoisson(a0, precision=precision)
         phi = torch.zeros_like(a0)
         a_t = torch.empty_like(a0)
         f_t = torch.empty_like(f0)
+        E = tuple(torch.empty_like(a0) for _ in range(4))
         state = {"t": 0, "first": True, "solves": []}
 
         def step():
             t = state["t"]
-            a_t.copy_(torch.roll(a0, t, dims=0))
-            f_t.copy_(torch.roll(f0, t, dims=0))
+            ne_t = torch.roll(ne0, t, dims=0)
+            np_t = torch.roll(np0, t, dims=0)
+            solver.assemble_elliptic(ne_t, np_t, out=(a_t, f_t), **step_prm)
+            del ne_t, np_t
             solver.update_coefficient(a_t)
             r = solver.solve(f_t, p.phi_bot, p.phi_top, args.tol, out=phi,
                              x0=None if state["first"] else phi)
+            solver.electric_field(phi, p.phi_bot, p.phi_top, out=E)
             state["first"] = False
             state["t"] = t + 1
             state["solves"].append(r)
@@ -283,7 +302,7 @@ def main():
             solver.profile(False)
         out = dict(ms_per_step=ms, solve_ms=None, solves=solves, prof=prof, prof_steps=2,
                    prof_solves=list(state["solves"][-2:]), levels=solver.levels, solves_per_step=1)
-        del solver, phi, a_t, f_t
+        del solver, phi, a_t, f_t, E, ne0, np0
         torch.cuda.empty_cache()
         return out
 
@@ -389,7 +408,8 @@ def main():
             4: "filament, max(a)=1e3, probe-box loss", 5: "two filaments, max(a)=1e4"}[cfg]
     if c5:
         workload = (f"{desc} {n}^3 time loop, tol {args.tol:g}, FGMRES(10) + V(2,2)-cycle mixed "
-                    "(float32 cycle, float64 outer); step = advect (roll) + renewal + warm-started solve")
+                    "(float32 cycle, float64 outer); step = advect the densities (roll) + coefficient "
+                    "and right side of e18 from them + renewal + warm-started solve + E = -grad phi")
     else:
         workload = (f"{desc} {n}^3, tol {args.tol:g}, FGMRES(10) + full multigrid cycle (V(2,2) "
                     "smoothing) mixed (float32 cycle, float64 outer); step = renewal + forward solve + "
