@@ -57,7 +57,8 @@ enum {
   GMG_ERR_SHAPE = -2,    /* grid does not coarsen to <= coarse_max_cells cells */
   GMG_ERR_NONFINITE = -3,/* NaN or Inf in a, f, phi (x0) or during the iteration */
   GMG_ERR_WORKSPACE = -4,/* workspace null, too small or misaligned (256 B) */
-  GMG_ERR_HIP = -5       /* a HIP runtime call failed */
+  GMG_ERR_HIP = -5,      /* a HIP runtime call failed */
+  GMG_ERR_BREAKDOWN = -6 /* gmg_krylov_solve: a zero denominator in a method's recurrences */
 };
 
 enum { GMG_FP64 = 0, GMG_MIXED = 1 };
@@ -141,6 +142,35 @@ int fgmres_solve(gmg_ctx* ctx, const double* f_dev, double phi_bot,
                  double phi_top, double tol, double* phi_dev, int use_x0,
                  int* iterations, double* res_hist, int res_hist_cap,
                  int* res_hist_len, double* final_true_relres);
+
+/* Krylov methods with the same multigrid preconditioner, for the comparison
+ * of Sec. 5.3 (Table t1).  GMRES is right-preconditioned (Arnoldi on A M, the
+ * update applies M to V y); CG is the preconditioned conjugate gradient; FCG
+ * its flexible form with the new direction made A-orthogonal to the last one;
+ * CGS and BiCGSTAB are right-preconditioned. */
+enum {
+  GMG_KRYLOV_FGMRES = 0,
+  GMG_KRYLOV_GMRES = 1,
+  GMG_KRYLOV_CG = 2,
+  GMG_KRYLOV_FCG = 3,
+  GMG_KRYLOV_CGS = 4,
+  GMG_KRYLOV_BICGSTAB = 5
+};
+
+/* Solve A phi = b (as fgmres_solve) with `method`, one V-cycle from zero per
+ * preconditioner application whatever the initial guess (the comparison uses
+ * the same preconditioner for every method).  Stops on the relative residual
+ * of eq. criterion: the recursively updated residual triggers the check, the
+ * true residual b - A phi decides it (a method restarts from phi when it
+ * fails), or after opt->max_iter iterations.  iterations (may be NULL): the
+ * method's iterations (CGS and BiCGSTAB apply the preconditioner twice per
+ * iteration); precond_apps (may be NULL): preconditioner applications;
+ * final_true_relres (may be NULL).  CG and FCG use basis slots 0-3, CGS and
+ * BiCGSTAB 0-7 of the workspace: they need restart >= 3 and >= 7
+ * (GMG_ERR_ARG otherwise).  Returns GMG_OK, GMG_NOT_CONVERGED,
+ * GMG_ERR_BREAKDOWN (a zero denominator in the recurrences) or an error. */
+int gmg_krylov_solve(gmg_ctx* ctx, int method, const double* f_dev, double phi_bot, double phi_top, double tol,
+                     double* phi_dev, int use_x0, int* iterations, int* precond_apps, double* final_true_relres);
 
 /* y = A x - lifting: the left side of e18 on cell values x with plate values
  * phi_bot, phi_top (so y = f exactly when x solves the problem).  x and y

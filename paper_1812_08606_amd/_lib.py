@@ -44,6 +44,8 @@ SIGNATURES = {
     "gmg_set_stream": (c_int, [c_void_p, c_void_p]),
     "fgmres_solve": (c_int, [c_void_p, c_void_p, c_double, c_double, c_double, c_void_p, c_int,
                              P_int, P_double, c_int, P_int, P_double]),
+    "gmg_krylov_solve": (c_int, [c_void_p, c_int, c_void_p, c_double, c_double, c_double, c_void_p, c_int,
+                                 P_int, P_int, P_double]),
     "gmg_apply_operator": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double]),
     "gmg_vcycle": (c_int, [c_void_p, c_void_p, c_void_p]),
     "gmg_fmg": (c_int, [c_void_p, c_void_p, c_void_p]),

@@ -17,6 +17,7 @@
 #include "gmg.h"
 #include "gmg_fine.hpp"
 #include "gmg_step.hpp"
+#include "gmg_krylov.hpp"
 
 using namespace gmg;
 
@@ -235,6 +236,8 @@ struct gmg_ctx {
   int nc;  // cells on the coarsest level
   int bottom_from;  // first level run by the one-workgroup bottom kernel (-1: none)
   bool fmg_now;     // the running solve preconditions with full multigrid cycles
+  bool gmres_mode;  // GMRES: one preconditioned-vector slot, x updated by M (V y)
+  int nprec;        // preconditioner applications of the running solve
   double* pinned;
   hipError_t err;
   Profiler prof;
@@ -980,10 +983,11 @@ void update_nv(int nv, gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, c
 void arnoldi_step(gmg_ctx* c, int j) {
   const size_t N = c->L.ldv;
   double* V = wsp<double>(c, c->L.V);
-  char* Zb = c->ws + c->L.Z + (size_t)j * N * c->L.tsize;
+  char* Zb = c->ws + c->L.Z + (size_t)(c->gmres_mode ? 0 : j) * N * c->L.tsize;
   double* vs = scal_vscale(c);
   double* hc = scal_hcol(c, j);
   cycle_any(c, V + (size_t)j * N, vs + j, Zb, c->fmg_now);
+  ++c->nprec;
   const Launch rl = opdot_launch(c);
   const Launch fl = red_flat(c);
   double* w = V + (size_t)(j + 1) * N;
@@ -1033,6 +1037,276 @@ int read_back(gmg_ctx* c, const double* dev, int n) {
 }
 
 bool valid_ctx(gmg_ctx* c) { return c != nullptr; }
+
+// ---------------------------------------------------------------------------
+// The other Krylov methods (Sec. 5.3, Table t1) on natural float64 vectors
+// held in the basis slots V[0..], scalars in misc[4..15].
+// ---------------------------------------------------------------------------
+double* kvec(gmg_ctx* c, int slot) { return wsp<double>(c, c->L.V) + (size_t)slot * c->L.ldv; }
+double* kscal(gmg_ctx* c) { return scal_misc(c) + 4; }
+
+// out = M u (one V-cycle from zero) in the natural layout, float64.
+void precond_natural(gmg_ctx* c, const double* u, double* out) {
+  char* Zb = c->ws + c->L.Z;
+  cycle_any(c, u, nullptr, Zb, false);
+  ++c->nprec;
+  if (c->L.shapes.size() > 1) {
+    const LevelShape& s = c->L.shapes[0];
+    const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+    if (c->mixed)
+      GMG_LAUNCH(c, "split_to_natural", k_split_to_natural<float>, l, (const float*)Zb, c->L.hn, s.geom(), out, l.kc);
+    else
+      GMG_LAUNCH(c, "split_to_natural", k_split_to_natural<double>, l, (const double*)Zb, c->L.hn, s.geom(), out,
+                 l.kc);
+  } else {
+    const Launch fl = flat_launch(c->N);
+    if (c->mixed)
+      GMG_LAUNCH(c, "convert_f32_f64", (k_convert<double, float>), fl, (const float*)Zb, out, c->N);
+    else
+      GMG_LAUNCH(c, "convert_f64_f64", (k_convert<double, double>), fl, (const double*)Zb, out, c->N);
+  }
+}
+
+// y = c0 x0 + c1 x1 + c2 x2; ||y||^2 into *norm2 (device) when given.
+void lincomb(gmg_ctx* c, double* y, const double* x0, double c0, const double* x1, double c1, const double* x2,
+             double c2, double* norm2) {
+  const Launch fl = red_flat(c);
+  GMG_LAUNCH(c, "lincomb", k_lincomb3, fl, y, x0, x1, x2, c0, c1, c2, c->N, norm2 ? 1 : 0,
+             wsp<double>(c, c->L.partials));
+  if (norm2) finalize(c, fl.nblocks(), 1, 0, norm2, nullptr, nullptr);
+}
+
+// (w, u_q) for nv (1 or 2) vectors u_q at stride ldv from U, into out (device).
+void kdots(gmg_ctx* c, const double* w, const double* U, int nv, double* out) {
+  const Launch fl = red_flat(c);
+  if (nv == 1)
+    launch_dot<1>(c, fl, w, U);
+  else
+    launch_dot<2>(c, fl, w, U);
+  finalize(c, fl.nblocks(), nv, 0, out, nullptr, nullptr);
+}
+
+// w = A x (homogeneous plates) with the dots (w, u_q), q < nv (1 or 2), into out.
+void kapply(gmg_ctx* c, const double* x, double* w, const double* U, int nv, double* out) {
+  const Launch rl = red_launch(c);
+  if (nv == 1)
+    GMG_LAUNCH(c, "op_natural", k_op_natural<1>, rl, x, c->a, c->L.shapes[0].geom(), w, U, c->L.ldv,
+               wsp<double>(c, c->L.partials), rl.kc);
+  else
+    GMG_LAUNCH(c, "op_natural", k_op_natural<2>, rl, x, c->a, c->L.shapes[0].geom(), w, U, c->L.ldv,
+               wsp<double>(c, c->L.partials), rl.kc);
+  finalize(c, rl.nblocks(), nv, 0, out, nullptr, nullptr);
+}
+
+// GMRES solution update: u = sum_i y_i v_i (v_i = vscale_i V_i) into the
+// basis slot V[k], then phi += M u.
+template <size_t... I>
+void natural_update_nv(int nv, gmg_ctx* c, const Launch& fl, double* u, const double* V, const Coeffs16& y,
+                       std::index_sequence<I...>) {
+  using F = void (*)(double*, size_t, const double*, size_t, Coeffs16);
+  static constexpr F table[] = {&k_update<double, (int)I + 1>...};
+  hipLaunchKernelGGL(table[nv - 1], fl.grid, fl.block, 0, c->stream, u, c->N, V, c->L.ldv, y);
+}
+
+void gmres_update(gmg_ctx* c, double* phi, int k) {
+  if (read_back(c, scal_vscale(c), k) != GMG_OK) return;
+  std::vector<double> vs(c->pinned, c->pinned + k);
+  double* u = kvec(c, k);
+  const Launch fl = flat_launch(c->N);
+  GMG_LAUNCH(c, "fill", k_fill<double>, fl, u, 0.0, c->N);
+  const auto seq = std::make_index_sequence<MAXV>{};
+  for (int q0 = 0; q0 < k; q0 += MAXV) {
+    const int nq = std::min(MAXV, k - q0);
+    Coeffs16 y{};
+    for (int q = 0; q < nq; ++q) y.v[q] = c->y[q0 + q] * vs[q0 + q];
+    natural_update_nv(nq, c, fl, u, kvec(c, q0), y, seq);
+    note(c, hipGetLastError());
+  }
+  char* Zb = c->ws + c->L.Z;
+  cycle_any(c, u, nullptr, Zb, false);
+  ++c->nprec;
+  Coeffs16 one{};
+  one.v[0] = 1.0;
+  if (c->mixed)
+    launch_update<float, 1>(c, fl, phi, (const float*)Zb, one);
+  else
+    launch_update<double, 1>(c, fl, phi, (const double*)Zb, one);
+}
+
+struct KrylovOut {
+  int it = 0;
+  double relres = NAN;
+};
+
+// r = b - A x into V[0] (x null: x = 0), ||b|| and ||r|| on the host.
+int true_residual(gmg_ctx* c, const double* f, const double* x, double pb, double pt, double& bnorm, double& rnorm) {
+  init_residual(c, f, x, pb, pt, true);
+  if (read_back(c, scal_misc(c), 3) != GMG_OK) return GMG_ERR_HIP;
+  bnorm = std::sqrt(c->pinned[0]);
+  rnorm = c->pinned[2];
+  if (!std::isfinite(bnorm) || !std::isfinite(rnorm)) return GMG_ERR_NONFINITE;
+  return GMG_OK;
+}
+
+// Preconditioned CG, or FCG (new direction A-orthogonalised against the last
+// one) when flexible.  Slots: r 0, q 1, z 2, p 3.
+int krylov_cg(gmg_ctx* c, const double* f, double pb, double pt, double tol, double* x, int max_iter, bool flexible,
+              KrylovOut& out) {
+  double* r = kvec(c, 0);
+  double* q = kvec(c, 1);
+  double* z = kvec(c, 2);
+  double* p = kvec(c, 3);
+  double* s = kscal(c);
+  while (true) {
+    double bnorm, rn;
+    int st = true_residual(c, f, x, pb, pt, bnorm, rn);
+    if (st != GMG_OK) return st;
+    if (bnorm == 0.0) {
+      out.relres = 0.0;
+      return GMG_OK;
+    }
+    out.relres = rn / bnorm;
+    if (rn < tol * bnorm) return GMG_OK;
+    if (out.it >= max_iter) return GMG_NOT_CONVERGED;
+    precond_natural(c, r, z);
+    lincomb(c, p, z, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr);
+    kdots(c, z, r, 1, s);  // rho = (r, z)
+    if (read_back(c, s, 1) != GMG_OK) return GMG_ERR_HIP;
+    double rho = c->pinned[0];
+    while (out.it < max_iter) {
+      kapply(c, p, q, p, 1, s);  // q = A p, (q, p)
+      if (read_back(c, s, 1) != GMG_OK) return GMG_ERR_HIP;
+      const double pq = c->pinned[0];
+      if (!std::isfinite(pq) || pq == 0.0) return GMG_ERR_BREAKDOWN;
+      const double alpha = rho / pq;
+      lincomb(c, x, x, 1.0, p, alpha, nullptr, 0.0, nullptr);
+      lincomb(c, r, r, 1.0, q, -alpha, nullptr, 0.0, s);
+      ++out.it;
+      if (read_back(c, s, 1) != GMG_OK) return GMG_ERR_HIP;
+      const double rr = std::sqrt(c->pinned[0]);
+      if (!std::isfinite(rr)) return GMG_ERR_NONFINITE;
+      if (rr < tol * bnorm) break;
+      precond_natural(c, r, z);
+      kdots(c, z, r, 2, s);  // (z, r), (z, q): r and q are adjacent slots
+      if (read_back(c, s, 2) != GMG_OK) return GMG_ERR_HIP;
+      const double rho_new = c->pinned[0];
+      const double beta = flexible ? -c->pinned[1] / pq : rho_new / rho;
+      lincomb(c, p, z, 1.0, p, beta, nullptr, 0.0, nullptr);
+      rho = rho_new;
+    }
+  }
+}
+
+// Right-preconditioned CGS.  Slots: r 0, r~ 1, p 2, u 3, q 4, v 5, M-vector 6,
+// scratch 7.
+int krylov_cgs(gmg_ctx* c, const double* f, double pb, double pt, double tol, double* x, int max_iter,
+               KrylovOut& out) {
+  double *r = kvec(c, 0), *rs = kvec(c, 1), *p = kvec(c, 2), *u = kvec(c, 3), *q = kvec(c, 4), *v = kvec(c, 5);
+  double *mh = kvec(c, 6), *w = kvec(c, 7);
+  double* s = kscal(c);
+  while (true) {
+    double bnorm, rn;
+    int st = true_residual(c, f, x, pb, pt, bnorm, rn);
+    if (st != GMG_OK) return st;
+    if (bnorm == 0.0) {
+      out.relres = 0.0;
+      return GMG_OK;
+    }
+    out.relres = rn / bnorm;
+    if (rn < tol * bnorm) return GMG_OK;
+    if (out.it >= max_iter) return GMG_NOT_CONVERGED;
+    lincomb(c, rs, r, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr);
+    lincomb(c, p, r, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr);
+    lincomb(c, u, r, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr);
+    double rho = rn * rn;  // (r, r~) with r~ = r
+    while (out.it < max_iter) {
+      precond_natural(c, p, mh);
+      kapply(c, mh, v, rs, 1, s);  // v = A M p, (v, r~)
+      if (read_back(c, s, 1) != GMG_OK) return GMG_ERR_HIP;
+      const double sigma = c->pinned[0];
+      if (!std::isfinite(sigma) || sigma == 0.0) return GMG_ERR_BREAKDOWN;
+      const double alpha = rho / sigma;
+      lincomb(c, q, u, 1.0, v, -alpha, nullptr, 0.0, nullptr);
+      lincomb(c, w, u, 1.0, q, 1.0, nullptr, 0.0, nullptr);
+      precond_natural(c, w, mh);  // u^ = M (u + q)
+      lincomb(c, x, x, 1.0, mh, alpha, nullptr, 0.0, nullptr);
+      kapply(c, mh, w, rs, 1, s);  // w = A u^
+      lincomb(c, r, r, 1.0, w, -alpha, nullptr, 0.0, s + 1);
+      kdots(c, r, rs, 1, s + 2);  // rho' = (r, r~)
+      ++out.it;
+      if (read_back(c, s, 3) != GMG_OK) return GMG_ERR_HIP;
+      const double rr = std::sqrt(c->pinned[1]), rho_new = c->pinned[2];
+      if (!std::isfinite(rr)) return GMG_ERR_NONFINITE;
+      if (rr < tol * bnorm) break;
+      const double beta = rho_new / rho;
+      lincomb(c, u, r, 1.0, q, beta, nullptr, 0.0, nullptr);
+      lincomb(c, p, u, 1.0, q, beta, p, beta * beta, nullptr);
+      rho = rho_new;
+    }
+  }
+}
+
+// Right-preconditioned BiCGSTAB.  Slots: r 0, r~ 1, p 2, v 3, s 4, t 5,
+// M p 6, M s 7.
+int krylov_bicgstab(gmg_ctx* c, const double* f, double pb, double pt, double tol, double* x, int max_iter,
+                    KrylovOut& out) {
+  double *r = kvec(c, 0), *rs = kvec(c, 1), *p = kvec(c, 2), *v = kvec(c, 3), *sv = kvec(c, 4), *t = kvec(c, 5);
+  double *ph = kvec(c, 6), *sh = kvec(c, 7);
+  double* s = kscal(c);
+  while (true) {
+    double bnorm, rn;
+    int st = true_residual(c, f, x, pb, pt, bnorm, rn);
+    if (st != GMG_OK) return st;
+    if (bnorm == 0.0) {
+      out.relres = 0.0;
+      return GMG_OK;
+    }
+    out.relres = rn / bnorm;
+    if (rn < tol * bnorm) return GMG_OK;
+    if (out.it >= max_iter) return GMG_NOT_CONVERGED;
+    lincomb(c, rs, r, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr);
+    const Launch fl = flat_launch(c->N);
+    GMG_LAUNCH(c, "fill", k_fill<double>, fl, p, 0.0, c->N);
+    GMG_LAUNCH(c, "fill", k_fill<double>, fl, v, 0.0, c->N);
+    double rho = 1.0, alpha = 1.0, omega = 1.0, rho_new = rn * rn;  // (r~, r) with r~ = r
+    while (out.it < max_iter) {
+      const double beta = (rho_new / rho) * (alpha / omega);
+      lincomb(c, p, r, 1.0, p, beta, v, -beta * omega, nullptr);
+      precond_natural(c, p, ph);
+      kapply(c, ph, v, rs, 1, s);  // v = A M p, (v, r~)
+      if (read_back(c, s, 1) != GMG_OK) return GMG_ERR_HIP;
+      const double rv = c->pinned[0];
+      if (!std::isfinite(rv) || rv == 0.0) return GMG_ERR_BREAKDOWN;
+      alpha = rho_new / rv;
+      lincomb(c, sv, r, 1.0, v, -alpha, nullptr, 0.0, s);
+      if (read_back(c, s, 1) != GMG_OK) return GMG_ERR_HIP;
+      if (std::sqrt(c->pinned[0]) < tol * bnorm) {  // converged half-way
+        lincomb(c, x, x, 1.0, ph, alpha, nullptr, 0.0, nullptr);
+        lincomb(c, r, sv, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr);
+        ++out.it;
+        break;
+      }
+      precond_natural(c, sv, sh);
+      kapply(c, sh, t, sv, 1, s);  // t = A M s, (t, s)
+      kdots(c, t, t, 1, s + 1);   // (t, t)
+      if (read_back(c, s, 2) != GMG_OK) return GMG_ERR_HIP;
+      const double ts = c->pinned[0], tt = c->pinned[1];
+      if (!std::isfinite(tt) || tt == 0.0) return GMG_ERR_BREAKDOWN;
+      omega = ts / tt;
+      lincomb(c, x, x, 1.0, ph, alpha, sh, omega, nullptr);
+      lincomb(c, r, sv, 1.0, t, -omega, nullptr, 0.0, s);
+      kdots(c, r, rs, 1, s + 1);
+      ++out.it;
+      if (read_back(c, s, 2) != GMG_OK) return GMG_ERR_HIP;
+      const double rr = std::sqrt(c->pinned[0]);
+      if (!std::isfinite(rr)) return GMG_ERR_NONFINITE;
+      rho = rho_new;
+      rho_new = c->pinned[1];
+      if (rr < tol * bnorm) break;
+      if (omega == 0.0) return GMG_ERR_BREAKDOWN;
+    }
+  }
+}
 
 }  // namespace
 
@@ -1124,9 +1398,17 @@ int gmg_set_stream(gmg_ctx* c, void* hip_stream) {
   return GMG_OK;
 }
 
-int fgmres_solve(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top, double tol, double* phi_dev,
-                 int use_x0, int* iterations, double* res_hist, int res_hist_cap, int* res_hist_len,
-                 double* final_true_relres) {
+}  // extern "C"
+
+namespace {
+
+void gmres_update(gmg_ctx* c, double* phi, int k);
+
+// FGMRES (Algorithm 1) or, with gmres, right-preconditioned GMRES (one slot
+// for the preconditioned vector; the solution update applies M to V y).
+int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top, double tol, double* phi_dev,
+                int use_x0, int* iterations, double* res_hist, int res_hist_cap, int* res_hist_len,
+                double* final_true_relres, bool allow_fmg, bool gmres) {
   if (!valid_ctx(c) || !f_dev || !phi_dev) return GMG_ERR_ARG;
   if (!(tol >= 0.0) || !std::isfinite(phi_bot) || !std::isfinite(phi_top)) return GMG_ERR_ARG;
   if (res_hist_cap < 0 || (res_hist_cap > 0 && !res_hist)) return GMG_ERR_ARG;
@@ -1146,7 +1428,9 @@ int fgmres_solve(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top
     const Launch fl = flat_launch(c->N);
     GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
   }
-  c->fmg_now = !use_x0 && c->opt.cold_cycle == GMG_CYCLE_FMG;
+  c->fmg_now = allow_fmg && !use_x0 && c->opt.cold_cycle == GMG_CYCLE_FMG;
+  c->gmres_mode = gmres;
+  c->nprec = 0;
   double* misc = scal_misc(c);
   bool first = true;
   double bnorm = 0.0;
@@ -1213,8 +1497,65 @@ int fgmres_solve(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top
       const double rii = c->R[(size_t)i * m + i];
       c->y[i] = rii != 0.0 ? s / rii : 0.0;
     }
-    if (k > 0) update_solution(c, phi_dev, k);
+    if (k > 0) {
+      if (gmres)
+        gmres_update(c, phi_dev, k);
+      else
+        update_solution(c, phi_dev, k);
+    }
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int fgmres_solve(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top, double tol, double* phi_dev,
+                 int use_x0, int* iterations, double* res_hist, int res_hist_cap, int* res_hist_len,
+                 double* final_true_relres) {
+  return fgmres_core(c, f_dev, phi_bot, phi_top, tol, phi_dev, use_x0, iterations, res_hist, res_hist_cap,
+                     res_hist_len, final_true_relres, true, false);
+}
+
+int gmg_krylov_solve(gmg_ctx* c, int method, const double* f_dev, double phi_bot, double phi_top, double tol,
+                     double* phi_dev, int use_x0, int* iterations, int* precond_apps, double* final_true_relres) {
+  if (!valid_ctx(c) || !f_dev || !phi_dev) return GMG_ERR_ARG;
+  if (method < GMG_KRYLOV_FGMRES || method > GMG_KRYLOV_BICGSTAB) return GMG_ERR_ARG;
+  if (!(tol >= 0.0) || !std::isfinite(phi_bot) || !std::isfinite(phi_top)) return GMG_ERR_ARG;
+  const int slots = c->opt.restart + 1;
+  if ((method == GMG_KRYLOV_CG || method == GMG_KRYLOV_FCG) && slots < 4) return GMG_ERR_ARG;
+  if ((method == GMG_KRYLOV_CGS || method == GMG_KRYLOV_BICGSTAB) && slots < 8) return GMG_ERR_ARG;
+  int st;
+  int its = 0;
+  double rel = NAN;
+  if (method == GMG_KRYLOV_FGMRES || method == GMG_KRYLOV_GMRES) {
+    st = fgmres_core(c, f_dev, phi_bot, phi_top, tol, phi_dev, use_x0, &its, nullptr, 0, nullptr, &rel, false,
+                     method == GMG_KRYLOV_GMRES);
+  } else {
+    c->fmg_now = false;
+    c->gmres_mode = false;
+    c->nprec = 0;
+    if (!use_x0) {
+      const Launch fl = flat_launch(c->N);
+      GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
+    }
+    KrylovOut out;
+    const int mi = c->opt.max_iter;
+    if (method == GMG_KRYLOV_CG || method == GMG_KRYLOV_FCG)
+      st = krylov_cg(c, f_dev, phi_bot, phi_top, tol, phi_dev, mi, method == GMG_KRYLOV_FCG, out);
+    else if (method == GMG_KRYLOV_CGS)
+      st = krylov_cgs(c, f_dev, phi_bot, phi_top, tol, phi_dev, mi, out);
+    else
+      st = krylov_bicgstab(c, f_dev, phi_bot, phi_top, tol, phi_dev, mi, out);
+    its = out.it;
+    rel = out.relres;
+    note(c, hipStreamSynchronize(c->stream));
+    if (c->err != hipSuccess) st = GMG_ERR_HIP;
+  }
+  if (iterations) *iterations = its;
+  if (precond_apps) *precond_apps = c->nprec;
+  if (final_true_relres) *final_true_relres = rel;
+  return st;
 }
 
 int gmg_apply_operator(gmg_ctx* c, const double* x_dev, double* y_dev, double phi_bot, double phi_top) {
@@ -1375,6 +1716,7 @@ const char* gmg_status_string(int s) {
     case GMG_ERR_NONFINITE: return "non-finite value in the coefficient, right side, initial guess or iteration";
     case GMG_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
     case GMG_ERR_HIP: return "HIP runtime error";
+    case GMG_ERR_BREAKDOWN: return "breakdown: zero denominator in the Krylov recurrences";
     default: return "unknown status";
   }
 }

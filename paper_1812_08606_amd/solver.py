@@ -205,6 +205,34 @@ class GMGPoisson:
             raise GMGError(st, entry)
         return z
 
+    KRYLOV = {"fgmres": 0, "gmres": 1, "cg": 2, "fcg": 3, "cgs": 4, "bicgstab": 5}
+
+    def krylov_solve(self, f: torch.Tensor, phi_bot: float, phi_top: float, method: str = "cg",
+                     tol: float = 1e-8, x0: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                     raise_on_error: bool = True):
+        """Solve with one of the Krylov methods of the comparison in Sec. 5.3
+        (fgmres, gmres, cg, fcg, cgs, bicgstab), one V-cycle per
+        preconditioner application.  Returns (SolveResult, preconditioner
+        applications)."""
+        if method not in self.KRYLOV:
+            raise ValueError(f"method must be one of {sorted(self.KRYLOV)}")
+        _check_field(f, self.shape, "f", self.device)
+        phi = out if out is not None else torch.empty_like(f)
+        _check_field(phi, self.shape, "out", self.device)
+        if x0 is not None:
+            _check_field(x0, self.shape, "x0", self.device)
+            if x0.data_ptr() != phi.data_ptr():
+                phi.copy_(x0)
+        its, napp, rel = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        with torch.cuda.device(self.device):
+            self._sync_stream()
+            st = self._lib.gmg_krylov_solve(self._ctx, self.KRYLOV[method], _ptr(f), float(phi_bot),
+                                            float(phi_top), float(tol), _ptr(phi), int(x0 is not None),
+                                            ctypes.byref(its), ctypes.byref(napp), ctypes.byref(rel))
+        if st < 0 and raise_on_error:
+            raise GMGError(st, "gmg_krylov_solve")
+        return SolveResult(phi=phi, status=st, iterations=its.value, final_relres=rel.value), napp.value
+
     def assemble_elliptic(self, n_e: torch.Tensor, n_p: torch.Tensor, eps0_over_e: float, tau_eff: float,
                           mu_e: float, mu_p: float, De=(0.0, 0.0, 0.0), out=None):
         """Coefficient a = P and right side f of the elliptic problem of a

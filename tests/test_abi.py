@@ -56,7 +56,7 @@ def test_default_options_and_workspace(lib):
 
 
 def test_status_strings(lib):
-    for s in (0, 1, -1, -2, -3, -4, -5, 99):
+    for s in (0, 1, -1, -2, -3, -4, -5, -6, 99):
         assert lib.gmg_status_string(s)
 
 

@@ -562,3 +562,50 @@ def test_semi_implicit_step_full_size():
     E_ref = electric_field(npy(res.phi), h, 0.0, 1.0)
     for g_, r_ in zip(E, E_ref):
         assert rel(npy(g_), r_) < 1e-14
+
+
+# ---------------------------------------------------------------- other Krylov methods
+KRYLOV = ["gmres", "cg", "fcg", "cgs", "bicgstab"]
+
+
+@pytest.mark.parametrize("method", KRYLOV)
+@pytest.mark.parametrize("case", [(3, 32, 4), (5, 32, 3)])
+def test_krylov_methods_fixed_steps_match_oracle(method, case):
+    """Each method of the comparison (Sec. 5.3) after a fixed number of
+    iterations, float64, against the oracle's implementation with the
+    oracle's V-cycle."""
+    from oracle.krylov import bicgstab, cg, cgs, gmres
+    cfg, n, k = case
+    print(f"krylov {method} workload {cfg} n={n} k={k}", flush=True)
+    p = make_config(cfg, n=n)
+    s = gm.GMGPoisson(T(p.a), precision="fp64", max_iter=k)
+    res, napp = s.krylov_solve(T(p.f), p.phi_bot, p.phi_top, method=method, tol=0.0)
+    hier = build_hierarchy(p.a, p.h)
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+
+    def A(x):
+        return apply_operator(x, p.a, p.h)
+
+    def M(v):
+        return vcycle(hier, v)
+    fn = {"gmres": gmres, "cg": cg, "fcg": lambda *a, **kw: cg(*a, flexible=True, **kw), "cgs": cgs,
+          "bicgstab": bicgstab}[method]
+    ref = fn(A, b, M, tol=0.0, max_iter=k)
+    assert res.status == gm.solver.NOT_CONVERGED and res.iterations == ref.iterations == k
+    assert napp == ref.precond
+    assert rel(npy(res.phi), ref.x) < 1e-9
+    assert abs(res.final_relres - ref.true_relres) <= 1e-6 * ref.true_relres
+
+
+@pytest.mark.parametrize("method", ["fgmres"] + KRYLOV)
+def test_krylov_methods_converge_mixed(method):
+    """Mixed precision, filament workload 64^3 (max(a) = 1e4): every method
+    reaches the 1e-8 relative residual, checked with the oracle's operator."""
+    p = make_config(3, n=64)
+    s = gm.GMGPoisson(T(p.a), precision="mixed")
+    res, napp = s.krylov_solve(T(p.f), p.phi_bot, p.phi_top, method=method, tol=1e-8)
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    r = np.linalg.norm(b - apply_operator(npy(res.phi), p.a, p.h)) / np.linalg.norm(b)
+    print(f"krylov {method}: {res.iterations} iterations, {napp} preconditioner applications, "
+          f"true relres {r:.2e}", flush=True)
+    assert res.converged and r < 1e-8 and abs(r - res.final_relres) <= 1e-3 * r
