@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=160, help="edge of the CPU-oracle sample grid")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--no-krylov", action="store_true", help="skip the comparison of Krylov methods")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (scale of the hardware traffic counters)")
     args = ap.parse_args()
@@ -318,6 +319,35 @@ def main():
         fp64 = run("fp64")
         log(f"fp64: {fp64['ms_per_step']:.2f} ms/step, iterations {[r.iterations for r in fp64['solves']]}")
 
+    # -- the Krylov methods of the comparison in Sec. 5.3 (Table t1): the
+    # forward solve from zero with each method, one V-cycle per
+    # preconditioner application, event-timed (median of 3) ----------------
+    krylov = None
+    if not c5 and not args.no_krylov:
+        log("Krylov method comparison (mixed, V-cycle preconditioner) ...")
+        solver = gm.GMGPoisson(a0, precision="mixed")
+        phi = torch.empty_like(a0)
+        krylov = {}
+        for method in ("fgmres", "gmres", "cg", "fcg", "cgs", "bicgstab"):
+            res, napp = solver.krylov_solve(f0, p.phi_bot, p.phi_top, method=method, tol=args.tol, out=phi)
+            times = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                res, napp = solver.krylov_solve(f0, p.phi_bot, p.phi_top, method=method, tol=args.tol, out=phi)
+                e1.record()
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            krylov[method] = dict(solve_ms=statistics.median(times), iterations=res.iterations,
+                                  preconditioner_applications=napp, converged=res.converged,
+                                  final_relres=res.final_relres)
+        for method, d in krylov.items():
+            d["ratio_to_fgmres"] = d["solve_ms"] / krylov["fgmres"]["solve_ms"]
+            log(f"  {method:9s} {d['solve_ms']:8.2f} ms  {d['iterations']:3d} it  "
+                f"{d['preconditioner_applications']:3d} M  ratio {d['ratio_to_fgmres']:.3f}")
+        del solver, phi
+        torch.cuda.empty_cache()
+
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -440,6 +470,7 @@ def main():
         "model_gbs": (total_bytes / ps) / (mixed["ms_per_step"] * 1e-3) / 1e9 if total_bytes else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "krylov_methods": krylov,
     }
     if fp64 is not None:
         line["fp64"] = {
