@@ -10,8 +10,12 @@ if ROOT not in sys.path:
 # Load what is built; build only if nothing is.
 _LIB = os.path.join(ROOT, "paper_1812_08606_amd", "libgmg.so")
 if not os.path.exists(_LIB):
-    from paper_1812_08606_amd import build as _build
+    import importlib.util
 
+    # by path: importing the package would try to load the missing library
+    _spec = importlib.util.spec_from_file_location("gmg_build", os.path.join(ROOT, "paper_1812_08606_amd", "build.py"))
+    _build = importlib.util.module_from_spec(_spec)
+    _spec.loader.exec_module(_build)
     _build.build()
 
 
