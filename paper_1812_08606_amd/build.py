@@ -23,6 +23,7 @@ FLAGS = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
+    "-pthread",
 ]
 
 

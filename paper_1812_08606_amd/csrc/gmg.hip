@@ -11,6 +11,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -295,34 +296,62 @@ void note(gmg_ctx* c, hipError_t e) {
 
 // Cholesky factor and inverse of the symmetric positive definite n x n
 // matrix M (row-major), in place; returns false if not positive definite.
+// The inverse is formed column by column from L L^T x = e_c (the forward
+// solve starts at row c, where e_c's solution becomes nonzero), the columns
+// split over host threads; L^T is kept row-major for the backward solves.
+// sum_{k in [k0, k1)} x[k] y[k] in four interleaved partial sums (lets the
+// host compiler vectorise the loop without reassociating it itself)
+double dot4(const double* x, const double* y, int k0, int k1) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = k0;
+  for (; k + 3 < k1; k += 4) {
+    s0 += x[k] * y[k];
+    s1 += x[k + 1] * y[k + 1];
+    s2 += x[k + 2] * y[k + 2];
+    s3 += x[k + 3] * y[k + 3];
+  }
+  for (; k < k1; ++k) s0 += x[k] * y[k];
+  return (s0 + s1) + (s2 + s3);
+}
+
 bool spd_inverse(std::vector<double>& M, int n) {
   std::vector<double> Lf(M);
   for (int j = 0; j < n; ++j) {
-    double d = Lf[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) d -= Lf[(size_t)j * n + k] * Lf[(size_t)j * n + k];
+    const double* lj = &Lf[(size_t)j * n];
+    double d = Lf[(size_t)j * n + j] - dot4(lj, lj, 0, j);
     if (!(d > 0.0)) return false;
     d = std::sqrt(d);
     Lf[(size_t)j * n + j] = d;
     for (int i = j + 1; i < n; ++i) {
-      double s = Lf[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) s -= Lf[(size_t)i * n + k] * Lf[(size_t)j * n + k];
-      Lf[(size_t)i * n + j] = s / d;
+      const double* li = &Lf[(size_t)i * n];
+      Lf[(size_t)i * n + j] = (li[j] - dot4(li, lj, 0, j)) / d;
     }
   }
-  // columns of the inverse: solve L L^T x = e_c
-  std::vector<double> col(n);
-  for (int c = 0; c < n; ++c) {
-    for (int i = 0; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) s -= Lf[(size_t)i * n + k] * col[k];
-      col[i] = s / Lf[(size_t)i * n + i];
+  std::vector<double> Lt((size_t)n * n, 0.0);  // Lt[i][k] = L[k][i]
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k <= i; ++k) Lt[(size_t)k * n + i] = Lf[(size_t)i * n + k];
+  auto columns = [&](int c0, int c1) {
+    std::vector<double> col(n);
+    for (int c = c0; c < c1; ++c) {
+      std::fill(col.begin(), col.begin() + c, 0.0);
+      for (int i = c; i < n; ++i) {
+        const double* li = &Lf[(size_t)i * n];
+        col[i] = ((i == c ? 1.0 : 0.0) - dot4(li, col.data(), c, i)) / li[i];
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        const double* ti = &Lt[(size_t)i * n];
+        col[i] = (col[i] - dot4(ti, col.data(), i + 1, n)) / ti[i];
+      }
+      for (int i = 0; i < n; ++i) M[(size_t)i * n + c] = col[i];
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = col[i];
-      for (int k = i + 1; k < n; ++k) s -= Lf[(size_t)k * n + i] * col[k];
-      col[i] = s / Lf[(size_t)i * n + i];
-    }
-    for (int i = 0; i < n; ++i) M[(size_t)i * n + c] = col[i];
+  };
+  const int nt = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+  if (n < 256 || nt == 1) {
+    columns(0, n);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t) pool.emplace_back(columns, (int)((long long)n * t / nt), (int)((long long)n * (t + 1) / nt));
+    for (auto& th : pool) th.join();
   }
   // symmetrise the rounding
   for (int i = 0; i < n; ++i)
