@@ -93,7 +93,13 @@ typedef struct gmg_options {
                            (default) one full multigrid cycle per step,
                            GMG_CYCLE_V one V-cycle per step.  Warm-started
                            solves always use V-cycles. */
-  int reserved[2];      /* must be zero */
+  int graphs;           /* 1: each preconditioner application is captured
+                           once into a HIP graph and replayed; 0 (default):
+                           its kernels are launched one by one.  Results are
+                           the same (the replays were not faster here: the
+                           coarse-level kernels wait on the GPU's dispatch
+                           latency, not on the host). */
+  int reserved[1];      /* must be zero */
 } gmg_options;
 
 void gmg_default_options(gmg_options* opt);

@@ -20,7 +20,8 @@ class Options(ctypes.Structure):
         ("coarse_max_cells", c_int),
         ("fine_sweep", c_int),
         ("cold_cycle", c_int),
-        ("reserved", c_int * 2),
+        ("graphs", c_int),
+        ("reserved", c_int * 1),
     ]
 
 

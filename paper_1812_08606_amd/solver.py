@@ -67,11 +67,13 @@ class GMGPoisson:
     finest-level smoother kernels, "half" (one per half-sweep), "fused" (one
     per symmetric sweep, float32 only) or "auto".  cold_cycle: preconditioner
     of a solve without an initial guess, "fmg" (full multigrid, the default)
-    or "vcycle"; warm-started solves use V-cycles."""
+    or "vcycle"; warm-started solves use V-cycles.  graphs: replay each
+    preconditioner application from a captured HIP graph (same results)."""
 
     def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
                  max_iter: int = 200, nu_pre: int = 2, nu_post: int = 2,
-                 coarse_max_cells: int = 4096, fine_sweep: str = "auto", cold_cycle: str = "fmg"):
+                 coarse_max_cells: int = 4096, fine_sweep: str = "auto", cold_cycle: str = "fmg",
+                 graphs: bool = False):
         self._lib = _lib.load()
         if a.dim() != 3:
             raise ValueError("a must be 3-D (nz, ny, nx)")
@@ -95,6 +97,7 @@ class GMGPoisson:
         opt.coarse_max_cells = int(coarse_max_cells)
         opt.fine_sweep = _FINE_SWEEP[fine_sweep]
         opt.cold_cycle = _COLD_CYCLE[cold_cycle]
+        opt.graphs = int(bool(graphs))
         self.options = opt
         nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
         if nbytes == 0:

@@ -36,7 +36,7 @@ def test_default_options_and_workspace(lib):
     opt = Options()
     lib.gmg_default_options(ctypes.byref(opt))
     assert (opt.restart, opt.max_iter, opt.nu_pre, opt.nu_post, opt.precision, opt.coarse_max_cells,
-            opt.fine_sweep) == (10, 200, 2, 2, 1, 4096, 0)
+            opt.fine_sweep, opt.cold_cycle, opt.graphs) == (10, 200, 2, 2, 1, 4096, 0, 1, 0)
     n64 = lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt))
     N = 64 ** 3
     # 11 float64 Krylov vectors + 10 float32 preconditioned vectors dominate
