@@ -723,28 +723,52 @@ __global__ __launch_bounds__(NTHREADS) void k_init_residual(const double* __rest
                                                             const double* __restrict__ x0, Geom g, double pb,
                                                             double pt, double* __restrict__ r_out,
                                                             double* __restrict__ partials, int kc) {
+  // z-marching columns: x0 and a of the planes below / above in registers,
+  // x- and y-neighbours from clamped addresses (zero flux through the sides)
   const Tile tl = xcd_tile();
   double acc[2] = {0.0, 0.0};
   const int i = tl.x * BX + threadIdx.x;
-  const CellCoef<double> co{a};
   if (i < g.nx) {
+    const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+    const double hx = 0.5 * g.ihx2, hy = 0.5 * g.ihy2, hz = 0.5 * g.ihz2, pz = 2.0 * g.ihz2;
+    const size_t dw = i > 0 ? 1 : 0, de = i < g.nx - 1 ? 1 : 0;
     const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
     for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-      for (int k = k0; k < k1; ++k) {
-        const size_t c = cidx(g, i, j, k);
-        const double ac = a[c];
+      const size_t ds = j > 0 ? sy : 0, dn = j < g.ny - 1 ? sy : 0;
+      size_t c = cidx(g, i, j, k0);
+      double ac = a[c], ab = a[k0 > 0 ? c - sz : c];
+      double xc = 0.0, xb = 0.0;
+      if (x0) {
+        xc = x0[c];
+        xb = x0[k0 > 0 ? c - sz : c];
+      }
+      for (int k = k0; k < k1; ++k, c += sz) {
+        const bool top = k == g.nz - 1;
+        const size_t ct = top ? c : c + sz;
+        const double at = a[ct];
         double bv = f[c];
         if (k == 0) bv += 2.0 * ac * pb * g.ihz2;
-        if (k == g.nz - 1) bv += 2.0 * ac * pt * g.ihz2;
-        double r = bv;
+        if (top) bv += 2.0 * ac * pt * g.ihz2;
+        double r = bv, xt = 0.0;
         if (x0) {
-          const Stencil<double> st = co.load(g, i, j, k, c);
-          const Nbrs<double> v = load_nbrs<double>(x0, g, i, j, k, c, 0.0, 0.0);
-          r -= apply_cell(st, v);
+          xt = x0[ct];
+          const double xw = x0[c - dw], aw = a[c - dw], xe = x0[c + de], ae = a[c + de];
+          const double xs = x0[c - ds], as = a[c - ds], xn = x0[c + dn], an = a[c + dn];
+          double s = (ac + aw) * hx * (xc - xw);
+          s += (ac + ae) * hx * (xc - xe);
+          s += (ac + as) * hy * (xc - xs);
+          s += (ac + an) * hy * (xc - xn);
+          s += k > 0 ? (ac + ab) * hz * (xc - xb) : pz * ac * xc;
+          s += !top ? (ac + at) * hz * (xc - xt) : pz * ac * xc;
+          r -= s;
         }
         if (r_out) r_out[c] = r;
         acc[0] += bv * bv;
         acc[1] += r * r;
+        xb = xc;
+        xc = xt;
+        ab = ac;
+        ac = at;
       }
     }
   }
@@ -918,26 +942,37 @@ __global__ __launch_bounds__(NTHREADS) void k_apply_bc(const double* __restrict_
 __global__ __launch_bounds__(NTHREADS) void k_face_grad(const double* __restrict__ phi,
                                                         const double* __restrict__ lam, Geom g, double pb,
                                                         double pt, double* __restrict__ out, int kc) {
+  // z-marching columns with the planes below / above in registers; x- and
+  // y-neighbours from clamped addresses, whose terms vanish on the sides
   const Tile tl = xcd_tile();
   const int i = tl.x * BX + threadIdx.x;
   if (i >= g.nx) return;
   const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const size_t dw = i > 0 ? 1 : 0, de = i < g.nx - 1 ? 1 : 0;
   const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
   for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
-    for (int k = k0; k < k1; ++k) {
-      const size_t c = cidx(g, i, j, k);
-      const double pc = phi[c], lc = lam[c];
-      double s = 0.0;
-      if (i > 0) s += (phi[c - 1] - pc) * (lam[c - 1] - lc) * g.ihx2;
-      if (i < g.nx - 1) s += (phi[c + 1] - pc) * (lam[c + 1] - lc) * g.ihx2;
-      if (j > 0) s += (phi[c - sy] - pc) * (lam[c - sy] - lc) * g.ihy2;
-      if (j < g.ny - 1) s += (phi[c + sy] - pc) * (lam[c + sy] - lc) * g.ihy2;
-      if (k > 0) s += (phi[c - sz] - pc) * (lam[c - sz] - lc) * g.ihz2;
-      if (k < g.nz - 1) s += (phi[c + sz] - pc) * (lam[c + sz] - lc) * g.ihz2;
+    const size_t ds = j > 0 ? sy : 0, dn = j < g.ny - 1 ? sy : 0;
+    size_t c = cidx(g, i, j, k0);
+    double pc = phi[c], lc = lam[c];
+    double pbv = phi[k0 > 0 ? c - sz : c], lbv = lam[k0 > 0 ? c - sz : c];
+    for (int k = k0; k < k1; ++k, c += sz) {
+      const bool top = k == g.nz - 1;
+      const size_t ct = top ? c : c + sz;
+      const double ptv = phi[ct], ltv = lam[ct];
+      double s = (phi[c - dw] - pc) * (lam[c - dw] - lc) * g.ihx2;
+      s += (phi[c + de] - pc) * (lam[c + de] - lc) * g.ihx2;
+      s += (phi[c - ds] - pc) * (lam[c - ds] - lc) * g.ihy2;
+      s += (phi[c + dn] - pc) * (lam[c + dn] - lc) * g.ihy2;
+      s += (pbv - pc) * (lbv - lc) * g.ihz2;  // zero at k = 0 (clamped to the cell)
+      s += (ptv - pc) * (ltv - lc) * g.ihz2;  // zero on the top layer
       double gsum = -0.5 * s;
       if (k == 0) gsum -= 2.0 * (pc - pb) * lc * g.ihz2;
-      if (k == g.nz - 1) gsum -= 2.0 * (pc - pt) * lc * g.ihz2;
+      if (top) gsum -= 2.0 * (pc - pt) * lc * g.ihz2;
       out[c] = gsum;
+      pbv = pc;
+      lbv = lc;
+      pc = ptv;
+      lc = ltv;
     }
   }
 }
