@@ -1204,12 +1204,16 @@ void kapply(gmg_ctx* c, const double* x, double* w, const double* U, int nv, dou
 
 // GMRES solution update: u = sum_i y_i v_i (v_i = vscale_i V_i) into the
 // basis slot V[k], then phi += M u.
+template <int NV>
+void launch_update_natural(gmg_ctx* c, const Launch& fl, double* u, const double* V, const Coeffs16& y) {
+  GMG_LAUNCH(c, "update_natural", (k_update<double, NV>), fl, u, c->N, V, c->L.ldv, y);
+}
 template <size_t... I>
 void natural_update_nv(int nv, gmg_ctx* c, const Launch& fl, double* u, const double* V, const Coeffs16& y,
                        std::index_sequence<I...>) {
-  using F = void (*)(double*, size_t, const double*, size_t, Coeffs16);
-  static constexpr F table[] = {&k_update<double, (int)I + 1>...};
-  hipLaunchKernelGGL(table[nv - 1], fl.grid, fl.block, 0, c->stream, u, c->N, V, c->L.ldv, y);
+  using F = void (*)(gmg_ctx*, const Launch&, double*, const double*, const Coeffs16&);
+  static constexpr F table[] = {&launch_update_natural<(int)I + 1>...};
+  table[nv - 1](c, fl, u, V, y);
 }
 
 void gmres_update(gmg_ctx* c, double* phi, int k) {
@@ -1224,7 +1228,6 @@ void gmres_update(gmg_ctx* c, double* phi, int k) {
     Coeffs16 y{};
     for (int q = 0; q < nq; ++q) y.v[q] = c->y[q0 + q] * vs[q0 + q];
     natural_update_nv(nq, c, fl, u, kvec(c, q0), y, seq);
-    note(c, hipGetLastError());
   }
   char* Zb = c->ws + c->L.Z;
   cycle_any(c, u, nullptr, Zb, false);
