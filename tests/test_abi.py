@@ -68,3 +68,7 @@ def test_null_arguments_rejected(lib):
     assert lib.gmg_setup(8, 8, 8, 0.1, 0.1, 0.1, None, ctypes.byref(opt), None, 0, None,
                          ctypes.byref(out)) == -1
     assert lib.fgmres_solve(None, None, 0.0, 1.0, 1e-8, None, 0, None, None, 0, None, None) == -1
+    assert lib.gmg_krylov_solve(None, 2, None, 0.0, 1.0, 1e-8, None, 0, None, None, None) == -1
+    assert lib.gmg_assemble_elliptic(None, None, None, None, None, None) == -1
+    assert lib.gmg_electric_field(None, None, 0.0, 1.0, None, None, None, None) == -1
+    assert lib.gmg_fmg(None, None, None) == -1
