@@ -105,8 +105,8 @@ def bytes_per_cell(base, level, s, nu_post=2):
             return (1 if nu_post > 0 else 2) * s + s / 8
         if base == "restrict_rhs":  # u (float64) read; B and the coarse right side (1/8) written
             return 8 + s + s / 8
-        if base == "prolong_set":  # coarse x read, X (both colours) written
-            return s + s / 8
+        if base == "prolong_set":  # coarse x read, the black half of X written (the guess the red sweep reads)
+            return 0.5 * s + s / 8
         return None
     if level is not None and level > 0:  # face coefficients wx, wy, wz (plates neglected)
         if base == "gs":  # x, faces read; b, x of the own colour read / written

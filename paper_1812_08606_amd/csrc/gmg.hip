@@ -755,7 +755,7 @@ void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X, 
   {
     const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
     GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), (k_prolong_pair<T, true>), l, X,
-               (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, npost > 0 ? 1 : 2, l.kc);
+               (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, npost > 0 ? 1 : 3, l.kc);
   }
   for (int it = 0; it < npost; ++it) {
     gs_split<T, false>(c, X, B, nullptr, nullptr, a, 1);
@@ -893,8 +893,10 @@ void fmg_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
   T* X0 = fused ? sym_buffer<T>(c, z, 0) : z;
   {
     const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    // the first pre-smoothing half-sweep (red) reads only the black guess;
+    // without pre-smoothing the residual reads both colours
     GMG_LAUNCH(c, kname("prolong_set", 0, sizeof(T)), (k_prolong_pair<T, true, true>), l, X0,
-               (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, 2, l.kc);
+               (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, c->opt.nu_pre > 0 ? 2 : 3, l.kc);
   }
   if (fused)
     vcycle_fine_sym<T>(c, u, bscale, z, true);

@@ -530,12 +530,13 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_split(const T* __re
 // coarse plane K feeds fine planes 2K (with K-1) and 2K+1 (with K+1).  The
 // two cells of a pair differ only in their x-neighbour (m-1 for cell 2m, m+1
 // for cell 2m+1).  SPLIT: the fine x is colour-split and only the colours
-// c < ncol are corrected; otherwise the fine x is natural (every cell).
+// in the bit mask cmask (1 red, 2 black) are written; otherwise the fine x
+// is natural (every cell).
 // SET: x = P xc (the interpolated initial guess of a full multigrid cycle)
 // instead of x += P xc.
 template <typename T, bool SPLIT, bool SET = false>
 __global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, const T* __restrict__ xc, Geom g,
-                                                           size_t hn, int ncol, int kc) {
+                                                           size_t hn, int cmask, int kc) {
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
   const int m = tl.x * BX + threadIdx.x;
@@ -577,7 +578,8 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, co
       const T vl = q3 * lc + q1 * (sub ? lt : lb);  // cell 2m
       const T vr = q3 * rc + q1 * (sub ? rt : rb);  // cell 2m+1
       if (SPLIT) {
-        for (int c = 0; c < ncol; ++c) {
+        for (int c = 0; c < 2; ++c) {
+          if (!((cmask >> c) & 1)) continue;
           const int e = (c + j + k) & 1;
           T& dst = x[(size_t)c * hn + sidx(g, m, j, k)];
           dst = SET ? (e ? vr : vl) : dst + (e ? vr : vl);
