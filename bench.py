@@ -19,6 +19,12 @@ filaments t cells in +z (the step-0 fields rolled along z on the device),
 renews the coefficient and solves warm-started from the previous phi; one
 solve per step.
 
+Besides the step, the other Krylov methods of Sec. 5.3 (Table t1) are timed
+on the workload's forward problem, and again on the streamer channel meshed
+256 x 256 x 320 and 512 x 512 x 640 on the unit cube (the comparison's
+meshes, h_z < h_x = h_y), with its variable coefficient and with a = 1
+(Table t2's constant-coefficient problem).
+
 Prints one JSON line on stdout; progress goes to stderr.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c1..c5] [--n N]
@@ -64,6 +70,9 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=160, help="edge of the CPU-oracle sample grid")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-krylov", action="store_true", help="skip the comparison of Krylov methods")
+    ap.add_argument("--krylov-meshes", default="256x256x320,512x512x640",
+                    help="comma-separated nx x ny x nz meshes of the unit cube for the Krylov comparison "
+                         "('' skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (scale of the hardware traffic counters)")
     args = ap.parse_args()
@@ -170,6 +179,32 @@ def measured_traffic():
     if not (m_b and m_h) or m_h.group(1) != kernel_source_hash():
         return None
     return float(m_b.group(1))
+
+
+def time_krylov_methods(torch, solver, f, pb, pt, tol):
+    """Each Krylov method of the comparison from no initial guess, one
+    V-cycle per preconditioner application: one untimed solve, then the
+    median of 3 event-timed solves."""
+    phi = torch.empty_like(f)
+    out = {}
+    for method in ("fgmres", "gmres", "cg", "fcg", "cgs", "bicgstab"):
+        res, napp = solver.krylov_solve(f, pb, pt, method=method, tol=tol, out=phi)
+        times = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            res, napp = solver.krylov_solve(f, pb, pt, method=method, tol=tol, out=phi)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        out[method] = dict(solve_ms=statistics.median(times), iterations=res.iterations,
+                           preconditioner_applications=napp, converged=res.converged,
+                           final_relres=res.final_relres)
+    for method, d in out.items():
+        d["ratio_to_fgmres"] = d["solve_ms"] / out["fgmres"]["solve_ms"]
+        log(f"  {method:9s} {d['solve_ms']:8.2f} ms  {d['iterations']:3d} it  "
+            f"{d['preconditioner_applications']:3d} M  ratio {d['ratio_to_fgmres']:.3f}")
+    return out
 
 
 def main():
@@ -342,27 +377,34 @@ def main():
     if not c5 and not args.no_krylov:
         log("Krylov method comparison (mixed, V-cycle preconditioner) ...")
         solver = gm.GMGPoisson(a0, precision="mixed")
-        phi = torch.empty_like(a0)
-        krylov = {}
-        for method in ("fgmres", "gmres", "cg", "fcg", "cgs", "bicgstab"):
-            res, napp = solver.krylov_solve(f0, p.phi_bot, p.phi_top, method=method, tol=args.tol, out=phi)
-            times = []
-            for _ in range(3):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                res, napp = solver.krylov_solve(f0, p.phi_bot, p.phi_top, method=method, tol=args.tol, out=phi)
-                e1.record()
-                e1.synchronize()
-                times.append(e0.elapsed_time(e1))
-            krylov[method] = dict(solve_ms=statistics.median(times), iterations=res.iterations,
-                                  preconditioner_applications=napp, converged=res.converged,
-                                  final_relres=res.final_relres)
-        for method, d in krylov.items():
-            d["ratio_to_fgmres"] = d["solve_ms"] / krylov["fgmres"]["solve_ms"]
-            log(f"  {method:9s} {d['solve_ms']:8.2f} ms  {d['iterations']:3d} it  "
-                f"{d['preconditioner_applications']:3d} M  ratio {d['ratio_to_fgmres']:.3f}")
-        del solver, phi
+        krylov = time_krylov_methods(torch, solver, f0, p.phi_bot, p.phi_top, args.tol)
+        del solver
         torch.cuda.empty_cache()
+
+    # -- the same comparison on the meshes of Table t1 / t2 (unit cube,
+    # h_z < h_x = h_y), variable a (the semi-implicit scheme's problem) and
+    # a = 1 (the explicit scheme's constant-coefficient problem) ------------
+    krylov_meshes = None
+    if not c5 and not args.no_krylov and args.krylov_meshes:
+        from workloads import config_streamer_mesh
+        krylov_meshes = {}
+        for spec in args.krylov_meshes.split(","):
+            mx, my, mz = (int(v) for v in spec.split("x"))
+            t_gen = time.perf_counter()
+            q = config_streamer_mesh(mx, my, mz)
+            aq = torch.tensor(q.a, device=dev)
+            fq = torch.tensor(q.f, device=dev)
+            del q.a, q.f
+            log(f"Krylov comparison on the {spec} mesh (inputs in {time.perf_counter() - t_gen:.1f}s) ...")
+            entry = {"cells": mx * my * mz, "h": list(q.h)}
+            for label, coef in (("variable_a", aq), ("constant_a", torch.ones_like(aq))):
+                solver = gm.GMGPoisson(coef, precision="mixed")
+                log(f"  {label} (max a = {float(coef.max()):g}, levels {len(solver.levels)})")
+                entry[label] = time_krylov_methods(torch, solver, fq, q.phi_bot, q.phi_top, args.tol)
+                del solver
+            krylov_meshes[spec] = entry
+            del aq, fq
+            torch.cuda.empty_cache()
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -490,6 +532,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "krylov_methods": krylov,
+        "krylov_meshes": krylov_meshes,
     }
     if fp64 is not None:
         line["fp64"] = {

@@ -117,3 +117,34 @@ def test_nonsymmetric_methods_reach_the_exact_solution(method):
     x_star = np.linalg.solve(Ad, b)
     assert np.linalg.norm(res.x - x_star) <= 1e-8 * np.linalg.norm(x_star)
     assert res.true_relres < 1e-10 and abs(res.res_hist[-1] - res.true_relres) < 1e-11
+
+
+@pytest.mark.parametrize("constant_a", [True, False])
+@pytest.mark.parametrize("method", ["fgmres", "gmres", "cg", "fcg", "cgs", "bicgstab"])
+def test_methods_on_the_anisotropic_comparison_mesh(method, constant_a):
+    """The streamer channel on a 16 x 16 x 20 mesh of the unit cube (the
+    aspect of the 256 x 256 x 320 mesh of Table t1, h_z < h_x = h_y): each
+    method with the oracle's V-cycle reaches the exact discrete solution,
+    the spectral (cosine/sine transform) solution for a = 1 and a sparse
+    direct solve for the variable coefficient."""
+    from oracle.exact import sparse_solve, spectral_solve
+    from workloads import config_streamer_mesh
+    p = config_streamer_mesh(16, 16, 20, constant_a=constant_a)
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    hier = build_hierarchy(p.a, p.h)
+    assert hier.levels[-1].shape == (4, 4, 5)
+
+    def A(x):
+        return apply_operator(x, p.a, p.h)
+
+    def M(v):
+        return vcycle(hier, v)
+    fn = {"fgmres": fgmres, "gmres": gmres, "cg": cg, "fcg": lambda *a, **k: cg(*a, flexible=True, **k),
+          "cgs": cgs, "bicgstab": bicgstab}[method]
+    res = fn(A, b, M, tol=1e-11, max_iter=100)
+    assert res.converged
+    if constant_a:
+        exact = spectral_solve(b, p.h)
+    else:
+        exact = sparse_solve(p.a, p.f, p.h, p.phi_bot, p.phi_top)
+    assert np.linalg.norm(res.x - exact) <= 1e-9 * np.linalg.norm(exact)

@@ -23,6 +23,7 @@ from .streamer import (  # noqa: F401
     config_gaussian_source,
     config_filament,
     config_two_filaments,
+    config_streamer_mesh,
     probe_box_mask,
     make_config,
     CONFIG_SIZES,

@@ -128,6 +128,36 @@ def config_two_filaments(n: int = 768, a_max: float = 1e4, seed_number: int = 5,
                          "kappa": kappa, "step": step})
 
 
+def config_streamer_mesh(nx: int = 256, ny: int = 256, nz: int = 320, a_max: float = 1e4,
+                         seed_number: int = 6, sigma: float = 0.03,
+                         constant_a: bool = False) -> Problem:
+    """The channel of a double-headed streamer on the unit cube meshed with
+    nx x ny x nz cells (the meshes of the scalability and solver-comparison
+    runs of Sec. 5.3 are 256 x 256 x 320 and its refinements, so h_z < h_x =
+    h_y).  One filament along z through (0.5, 0.5), the same profile and
+    noise as ``config_filament``, sampled at this mesh's cell centres;
+    ``constant_a`` keeps f and sets a = 1 (the constant-coefficient problem of
+    the explicit scheme, Table t2)."""
+    rng = _rng(seed_number)
+    cx, cy, cz = cell_centres(nx), cell_centres(ny), cell_centres(nz)
+    radial = np.exp(-((cx[None, :] - 0.5) ** 2 + (cy[:, None] - 0.5) ** 2) / (2.0 * sigma ** 2))
+    xi = np.exp(0.1 * rng.standard_normal((nz, ny, nx)))
+    n_e = smoothstep_window(cz)[:, None, None] * radial[None, :, :] * xi
+    n_p = 0.9 * smoothstep_window(cz - 0.02)[:, None, None] * radial[None, :, :] * xi
+    del xi
+    f = 50.0 * (n_p - n_e)
+    if constant_a:
+        a = np.ones((nz, ny, nx), dtype=np.float64)
+        kappa = 0.0
+        a_max = 1.0
+    else:
+        kappa = (a_max - 1.0) / n_e.max()
+        a = 1.0 + kappa * n_e
+    return Problem(name=f"streamer_mesh_{nx}x{ny}x{nz}_amax{a_max:g}", shape=(nx, ny, nz),
+                   h=(1.0 / nx, 1.0 / ny, 1.0 / nz), a=a, f=f, phi_bot=0.0, phi_top=1.0,
+                   meta={"seed": SEED_BASE + seed_number, "a_max": a_max, "kappa": kappa})
+
+
 def probe_box_mask(n: int, box=((0.4, 0.6), (0.4, 0.6), (0.45, 0.55))) -> np.ndarray:
     """Boolean (nz, ny, nx) mask of cells whose centre lies in the closed box
     [x0,x1] x [y0,y1] x [z0,z1]."""
