@@ -73,12 +73,28 @@ enum { GMG_SWEEP_AUTO = 0, GMG_SWEEP_HALF = 1, GMG_SWEEP_FUSED = 2 };
  * solution is the guess). */
 enum { GMG_CYCLE_V = 0, GMG_CYCLE_FMG = 1 };
 
+/* Smoother of every level but the coarsest (Sec. 3.2).  GMG_SMOOTH_RBGS:
+ * red-black symmetric Gauss-Seidel, nu_pre sweeps red-black before the coarse
+ * correction and nu_post black-red after it.  GMG_SMOOTH_CHEBYSHEV: the
+ * paper's own smoother, the degree-2 Chebyshev polynomial of eq. qntn in the
+ * SSOR-preconditioned level operator M^{-1} A_l (M: one symmetric red-black
+ * sweep from zero, red, black, red), nu_pre applications before and nu_post
+ * after the coarse correction, with bounds lambda* = 0.1 lambda and
+ * lambda_max = 1.1 lambda from lambda, the largest real part of the Ritz
+ * values of 10 Arnoldi steps on M^{-1} A_l (estimated when the coefficient
+ * is set; the start vector of level l is drawn by SplitMix64 seeded with l,
+ * cell c taking output c + 1 mapped to [-1, 1) as 2 (z >> 11) 2^-53 - 1).
+ * Chebyshev smoothing runs every level through per-level kernels (no
+ * one-workgroup bottom kernel) and needs cold_cycle = GMG_CYCLE_V. */
+enum { GMG_SMOOTH_RBGS = 0, GMG_SMOOTH_CHEBYSHEV = 1 };
+
 /* Solver options.  gmg_default_options fills the defaults given below. */
 typedef struct gmg_options {
   int restart;          /* Krylov dimension m of FGMRES(m), 1..32 (default 10)   */
   int max_iter;         /* cap on Arnoldi steps over all restarts (default 200)  */
-  int nu_pre;           /* red-black Gauss-Seidel pre-sweeps, 0..8 (default 2)   */
-  int nu_post;          /* post-sweeps, 0..8 (default 2)                         */
+  int nu_pre;           /* pre-smoothing sweeps (Chebyshev: applications), 0..8
+                           (default 2)                                           */
+  int nu_post;          /* post-smoothing sweeps (applications), 0..8 (default 2) */
   int precision;        /* GMG_FP64: whole solve in float64; GMG_MIXED: V-cycle
                            (coefficients, smoother, transfers, coarse solve) in
                            float32, FGMRES in float64 (default GMG_MIXED)       */
@@ -99,7 +115,7 @@ typedef struct gmg_options {
                            the same (the replays were not faster here: the
                            coarse-level kernels wait on the GPU's dispatch
                            latency, not on the host). */
-  int reserved[1];      /* must be zero */
+  int smoother;         /* GMG_SMOOTH_RBGS (default) or GMG_SMOOTH_CHEBYSHEV */
 } gmg_options;
 
 void gmg_default_options(gmg_options* opt);
@@ -240,6 +256,23 @@ int gmg_electric_field(gmg_ctx* ctx, const double* phi_dev, double phi_bot, doub
 /* Hierarchy description: number of levels and, for level l < cap, its
  * (nx, ny, nz) in shapes[3l..3l+2]. */
 int gmg_get_levels(gmg_ctx* ctx, int* nlevels, int* shapes, int cap);
+
+/* Chebyshev smoother (options.smoother = GMG_SMOOTH_CHEBYSHEV): the
+ * Arnoldi estimate lambda of each smoothed level (the coarsest is solved
+ * directly), from the coefficient last given to gmg_setup or
+ * gmg_update_coefficient; the bounds of eq. qntn are 0.1 and 1.1 lambda.
+ * Writes *nlevels (levels minus one) and the first min(cap, *nlevels)
+ * values to lam (host).  GMG_ERR_ARG for a context with the red-black
+ * smoother or null pointers. */
+int gmg_chebyshev_estimates(gmg_ctx* ctx, double* lam, int cap, int* nlevels);
+
+/* Host step of the estimate above (no GPU work): the largest real part of
+ * the eigenvalues of the m x m upper Hessenberg matrix H (row-major, row
+ * stride ldh >= m; entries below the subdiagonal are ignored), by the Francis
+ * double-shift QR iteration, into *out.  H is not modified.  GMG_ERR_ARG
+ * for null pointers, m < 1 or m > 64, ldh < m, or non-finite entries;
+ * GMG_NOT_CONVERGED if the iteration did not converge. */
+int gmg_ritz_max_real(const double* H, int m, int ldh, double* out);
 
 /* Per-kernel timing with HIP events on the context's stream.  While enabled,
  * every kernel launch is bracketed by events; gmg_profile_read sums the

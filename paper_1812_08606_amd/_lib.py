@@ -21,7 +21,7 @@ class Options(ctypes.Structure):
         ("fine_sweep", c_int),
         ("cold_cycle", c_int),
         ("graphs", c_int),
-        ("reserved", c_int * 1),
+        ("smoother", c_int),
     ]
 
 
@@ -56,6 +56,8 @@ SIGNATURES = {
     "gmg_electric_field": (c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p,
                                    c_void_p]),
     "gmg_get_levels": (c_int, [c_void_p, P_int, P_int, c_int]),
+    "gmg_chebyshev_estimates": (c_int, [c_void_p, P_double, c_int, P_int]),
+    "gmg_ritz_max_real": (c_int, [P_double, c_int, c_int, P_double]),
     "gmg_profile_enable": (c_int, [c_void_p, c_int]),
     "gmg_profile_reset": (c_int, [c_void_p]),
     "gmg_profile_read": (c_int, [c_void_p, ctypes.POINTER(ctypes.c_char_p), P_double,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <cmath>
 #include <cstdio>
@@ -19,6 +20,7 @@
 #include "gmg_fine.hpp"
 #include "gmg_step.hpp"
 #include "gmg_krylov.hpp"
+#include "gmg_cheb.hpp"
 
 using namespace gmg;
 
@@ -27,6 +29,8 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int MAX_RESTART = 32;
 constexpr double BREAKDOWN_TOL = 1e-14;
+constexpr int CHEB_ARNOLDI = 10;  // Arnoldi steps of the Chebyshev bound estimate
+constexpr int CHEB_DEGREE = 2;    // degree of the Chebyshev smoothing polynomial
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -55,12 +59,14 @@ struct LevelOffsets {
   size_t wx, wy, wz, tp;          // precision T faces (levels >= 1)
   size_t wx64, wy64, wz64, tp64;  // float64 faces (levels >= 1; == T faces in FP64)
   size_t b, x;                    // precision T right side and iterate
+  size_t cr, ce, cd;              // Chebyshev smoother: residual, SSOR output, direction (T)
 };
 
 struct Layout {
   std::vector<LevelShape> shapes;
   std::vector<LevelOffsets> lv;
   size_t V, Z, a32, b0, xs, partials, scal, cinv, bargs, total;
+  size_t cr0, cd0;  // Chebyshev smoother, finest level: float64 natural residual, T colour-split direction
   size_t tsize;  // bytes of the V-cycle precision
   size_t ldv;    // elements between consecutive Krylov vectors (v_i and z_i)
   size_t hn;     // elements of one colour array of a colour-split finest-level field
@@ -77,8 +83,8 @@ bool options_valid(const gmg_options* o) {
   if (o->fine_sweep < GMG_SWEEP_AUTO || o->fine_sweep > GMG_SWEEP_FUSED) return false;
   if (o->cold_cycle != GMG_CYCLE_V && o->cold_cycle != GMG_CYCLE_FMG) return false;
   if (o->graphs != 0 && o->graphs != 1) return false;
-  for (int r : o->reserved)
-    if (r) return false;
+  if (o->smoother != GMG_SMOOTH_RBGS && o->smoother != GMG_SMOOTH_CHEBYSHEV) return false;
+  if (o->smoother == GMG_SMOOTH_CHEBYSHEV && o->cold_cycle != GMG_CYCLE_V) return false;
   return true;
 }
 
@@ -105,7 +111,11 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   // 512-byte aligned
   L->hn = ((N + 1) / 2 + 63) / 64 * 64;
   L->ldv = 2 * L->hn;
-  L->V = take((size_t)(L->m + 1) * L->ldv * 8);
+  // the Chebyshev smoother's bound estimate keeps its Arnoldi basis in the
+  // Krylov slots
+  const bool cheb = o->smoother == GMG_SMOOTH_CHEBYSHEV;
+  const int nvslots = cheb ? std::max(L->m + 1, CHEB_ARNOLDI + 1) : L->m + 1;
+  L->V = take((size_t)nvslots * L->ldv * 8);
   L->Z = take((size_t)L->m * L->ldv * L->tsize);
   L->a32 = mixed ? take(N * 4) : 0;
   // finest-level right side in T (colour-split; natural when the finest
@@ -136,9 +146,16 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
     }
     lo.b = take(n * L->tsize);
     lo.x = take(n * L->tsize);
+    if (cheb && l < nl - 1) {
+      lo.cr = take(n * L->tsize);
+      lo.ce = take(n * L->tsize);
+      lo.cd = take(n * L->tsize);
+    }
   }
+  L->cr0 = cheb && nl > 1 ? take(N * 8) : 0;
+  L->cd0 = cheb && nl > 1 ? take(L->ldv * L->tsize) : 0;
   L->partials = take((size_t)MAXV * MAX_RED_BLOCKS * 8);
-  L->scal = take((size_t)(L->m * (L->m + 2) + (L->m + 2) + 16) * 8);
+  L->scal = take((size_t)(L->m * (L->m + 2) + (L->m + 2) + 32) * 8);
   const size_t nc = last.n();
   L->cinv = take(nc * nc * L->tsize);
   L->bargs = take(sizeof(BottomArgs<double>));
@@ -259,6 +276,10 @@ struct gmg_ctx {
   Profiler prof;
   // host Givens state
   std::vector<double> R, cs, sn, g, y;
+  // Chebyshev smoother: Arnoldi estimate and recurrence coefficients
+  // (c1, c2 of each of the CHEB_DEGREE steps) per smoothed level
+  std::vector<double> cheb_lam;
+  std::vector<std::array<double, 2 * CHEB_DEGREE>> cheb_coef;
 };
 
 namespace {
@@ -658,6 +679,45 @@ int write_bottom_args(gmg_ctx* c) {
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }
 
+// Chebyshev smoothing (Sec. 3.2, eq. qntn) on a coarse level l: nu
+// applications of the degree-CHEB_DEGREE recurrence, each step one SSOR
+// solve (red from zero, black, red) of the residual and the update of the
+// direction d and the iterate x.  From x = 0 unless from_x (the first
+// residual is then b itself).
+template <typename T>
+void cheb_smooth_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co, bool from_x, int nu) {
+  const LevelShape& s = c->L.shapes[l];
+  const LevelOffsets& o = c->L.lv[l];
+  T* R = wsp<T>(c, o.cr);
+  T* E = wsp<T>(c, o.ce);
+  T* D = wsp<T>(c, o.cd);
+  const Geom g = s.geom();
+  const size_t n = s.n();
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
+  const Launch cl = cell_launch(s.nx, s.ny, s.nz, 4096, 4);
+  const Launch ul = flat_launch(n);
+  const auto& cf = c->cheb_coef[l];
+  if (nu == 0 && !from_x) GMG_LAUNCH(c, kname("fill", l, sizeof(T)), k_fill<T>, ul, x, T(0), n);
+  bool zero = !from_x;
+  for (int it = 0; it < nu; ++it) {
+    for (int st = 0; st < CHEB_DEGREE; ++st) {
+      const bool first = zero && st == 0;
+      const T* rhs = b;
+      if (!first) {
+        GMG_LAUNCH(c, kname("cheb_resid", l, sizeof(T)), k_resid_face<T>, cl, (const T*)x, b, co, g, R, cl.kc);
+        rhs = R;
+      }
+      GMG_LAUNCH(c, kname("ssor_first", l, sizeof(T)), (k_gs_pair_face<T, true>), pl, E, rhs, co, g, pl.kc, 0);
+      GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, rhs, co, g, pl.kc, 1);
+      GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, rhs, co, g, pl.kc, 0);
+      const int mode = (st == 0 ? 1 : 0) | (first ? 2 : 0);
+      GMG_LAUNCH(c, kname("cheb_update", l, sizeof(T)), k_cheb_update<T>, ul, x, D, (const T*)E, cf[2 * st],
+                 cf[2 * st + 1], n, (size_t)0, mode);
+    }
+    zero = false;
+  }
+}
+
 // Levels >= 1 (face coefficients), right side in lv[l].b, result in lv[l].x:
 // a V-cycle from x = 0, or from the guess in lv[l].x when from_x (the
 // coarsest level is solved directly either way; a guess is never passed to
@@ -677,11 +737,18 @@ void vcycle_coarse(gmg_ctx* c, int l, bool from_x = false) {
     return;
   }
   const FaceCoef<T> co = face_coef<T>(c, l);
-  smooth_pre_face<T>(c, l, x, b, co, from_x);
+  const bool cheb = c->opt.smoother == GMG_SMOOTH_CHEBYSHEV;
+  if (cheb)
+    cheb_smooth_face<T>(c, l, x, b, co, from_x, c->opt.nu_pre);
+  else
+    smooth_pre_face<T>(c, l, x, b, co, from_x);
   resid_restrict_face<T>(c, l, x, b, co, wsp<T>(c, c->L.lv[l + 1].b));
   vcycle_coarse<T>(c, l + 1);
   prolong_add<T>(c, l, x, wsp<T>(c, c->L.lv[l + 1].x));
-  smooth_post_face<T>(c, l, x, b, co);
+  if (cheb)
+    cheb_smooth_face<T>(c, l, x, b, co, true, c->opt.nu_post);
+  else
+    smooth_post_face<T>(c, l, x, b, co);
 }
 
 // Full multigrid cycle on the levels >= l0 for the right side in lv[l0].b,
@@ -761,6 +828,69 @@ void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X, 
     gs_split<T, false>(c, X, B, nullptr, nullptr, a, 1);
     gs_split<T, false>(c, X, B, nullptr, nullptr, a, 0);
   }
+}
+
+// z = M (s * u) with the Chebyshev smoother on the finest level (at least
+// two levels).  X (colour-split) is the iterate; the SSOR solves write their
+// colour-split right side into the b0 scratch and their result into the xs
+// scratch; residuals are float64 in the natural layout, where the first
+// SSOR half-sweep reads them.  The first residual of the pre-smoothing is
+// s u itself.
+template <typename T>
+void vcycle_fine_cheb(gmg_ctx* c, const double* u, const double* bscale, T* X) {
+  const LevelShape& s = c->L.shapes[0];
+  const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
+  T* Bs = wsp<T>(c, c->L.b0);
+  T* E = wsp<T>(c, c->L.xs);
+  T* D = wsp<T>(c, c->L.cd0);
+  double* R = wsp<double>(c, c->L.cr0);
+  const size_t hn = c->L.hn, half = c->N / 2;
+  const Geom g = s.geom();
+  const Launch rl = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+  Launch ul = flat_launch(half);
+  ul.grid.y = 2;  // the two colour arrays
+  const auto& cf = c->cheb_coef[0];
+  auto resid = [&]() {
+    GMG_LAUNCH(c, kname("cheb_resid", 0, sizeof(T)), k_resid_split<T>, rl, (const T*)X, u, bscale, a, g, hn, R,
+               rl.kc);
+  };
+  auto smooth = [&](bool zero, int nu) {
+    if (nu == 0 && zero) {
+      const Launch fl = flat_launch(2 * hn);
+      GMG_LAUNCH(c, kname("fill", 0, sizeof(T)), k_fill<T>, fl, X, T(0), 2 * hn);
+    }
+    for (int it = 0; it < nu; ++it) {
+      for (int st = 0; st < CHEB_DEGREE; ++st) {
+        const bool first = zero && st == 0;
+        if (first) {
+          gs_split<T, true>(c, E, Bs, u, bscale, a, 0);
+        } else {
+          resid();
+          gs_split<T, true>(c, E, Bs, R, nullptr, a, 0);
+        }
+        gs_split<T, false>(c, E, Bs, nullptr, nullptr, a, 1);
+        gs_split<T, false>(c, E, Bs, nullptr, nullptr, a, 0);
+        const int mode = (st == 0 ? 1 : 0) | (first ? 2 : 0);
+        GMG_LAUNCH(c, kname("cheb_update", 0, sizeof(T)), k_cheb_update<T>, ul, X, D, (const T*)E, cf[2 * st],
+                   cf[2 * st + 1], half, hn, mode);
+      }
+      zero = false;
+    }
+  };
+  smooth(true, c->opt.nu_pre);
+  resid();
+  {
+    const Launch l{dim3((s.nx / 2 + BX - 1) / BX, (s.ny / 2 + BY - 1) / BY, s.nz / 2), dim3(BX, BY, 1), 0};
+    GMG_LAUNCH(c, kname("restrict_rhs", 0, sizeof(T)), k_restrict_split_rhs<T>, l, (const double*)R, nullptr, Bs,
+               wsp<T>(c, c->L.lv[1].b), g, hn);
+  }
+  vcycle_coarse<T>(c, 1);
+  {
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), (k_prolong_pair<T, true>), l, X,
+               (const T*)wsp<T>(c, c->L.lv[1].x), g, hn, 3, l.kc);
+  }
+  smooth(false, c->opt.nu_post);
 }
 
 // Launch of the fused symmetric sweep on the finest level: blocks of 64 x R
@@ -864,7 +994,9 @@ void vcycle_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
     coarse_solve<T>(c, b0, z);
     return;
   }
-  if (fused_sweeps<T>(c))
+  if (c->opt.smoother == GMG_SMOOTH_CHEBYSHEV)
+    vcycle_fine_cheb<T>(c, u, bscale, z);
+  else if (fused_sweeps<T>(c))
     vcycle_fine_sym<T>(c, u, bscale, z, false);
   else
     vcycle_fine_split<T>(c, u, bscale, z, false);
@@ -1151,6 +1283,224 @@ bool valid_ctx(gmg_ctx* c) { return c != nullptr; }
 double* kvec(gmg_ctx* c, int slot) { return wsp<double>(c, c->L.V) + (size_t)slot * c->L.ldv; }
 double* kscal(gmg_ctx* c) { return scal_misc(c) + 4; }
 
+// ---------------------------------------------------------------------------
+// Bounds of the Chebyshev smoother (Sec. 3.2, eq. qntn): per smoothed level,
+// 10 Arnoldi steps (modified Gram-Schmidt, Algorithm 1 without a
+// preconditioner) on M_l^{-1} A_l, the largest real part of the Ritz values
+// on the host.  Basis in the Krylov slots V[0..10] (natural float64, first
+// n_l entries), scalars in misc[16..31].
+// ---------------------------------------------------------------------------
+
+// Largest real part of the eigenvalues of the m x m upper Hessenberg matrix
+// H (row-major, row stride ldh) by the Francis double-shift QR iteration with
+// deflation at negligible subdiagonals (Golub and Van Loan, Sec. 7.5).  Only
+// the eigenvalues are wanted, so each similarity transform is applied to the
+// active diagonal block alone.
+int ritz_max_real(const double* Hin, int m, int ldh, double* out) {
+  std::vector<double> A((size_t)m * m, 0.0);
+  double fro = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = std::max(0, i - 1); j < m; ++j) {
+      const double v = Hin[(size_t)i * ldh + j];
+      if (!std::isfinite(v)) return GMG_ERR_ARG;
+      A[(size_t)i * m + j] = v;
+      fro += v * v;
+    }
+  fro = std::sqrt(fro);
+  auto h = [&](int i, int j) -> double& { return A[(size_t)i * m + j]; };
+  const double eps = 2.220446049250313e-16;
+  double best = -INFINITY;
+  int hi = m - 1, its = 0, total = 0;
+  while (hi >= 0) {
+    int lo = hi;
+    while (lo > 0) {
+      double sc = std::fabs(h(lo - 1, lo - 1)) + std::fabs(h(lo, lo));
+      if (sc == 0.0) sc = fro;
+      if (std::fabs(h(lo, lo - 1)) <= eps * sc) {
+        h(lo, lo - 1) = 0.0;
+        break;
+      }
+      --lo;
+    }
+    if (lo == hi) {  // 1 x 1 block
+      best = std::max(best, h(hi, hi));
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (lo == hi - 1) {  // 2 x 2 block: real pair or complex pair
+      const double p = 0.5 * (h(lo, lo) + h(hi, hi));
+      const double q = 0.5 * (h(lo, lo) - h(hi, hi));
+      const double disc = q * q + h(lo, hi) * h(hi, lo);
+      best = std::max(best, disc >= 0.0 ? p + std::sqrt(disc) : p);
+      hi -= 2;
+      its = 0;
+      continue;
+    }
+    if (++total > 100 * m) return GMG_NOT_CONVERGED;
+    ++its;
+    // shifts: eigenvalues of the trailing 2 x 2 block (sum s, product t);
+    // every 10th step of a block an exceptional pair to break cycles
+    double s, t;
+    if (its % 10 == 0) {
+      const double w = std::fabs(h(hi, hi - 1)) + std::fabs(h(hi - 1, hi - 2));
+      s = 1.5 * w + h(hi, hi);
+      t = w * w;
+    } else {
+      s = h(hi - 1, hi - 1) + h(hi, hi);
+      t = h(hi - 1, hi - 1) * h(hi, hi) - h(hi - 1, hi) * h(hi, hi - 1);
+    }
+    // first column of (H - s1)(H - s2), then chase the bulge down
+    double x = h(lo, lo) * h(lo, lo) + h(lo, lo + 1) * h(lo + 1, lo) - s * h(lo, lo) + t;
+    double y = h(lo + 1, lo) * (h(lo, lo) + h(lo + 1, lo + 1) - s);
+    double z = h(lo + 1, lo) * h(lo + 2, lo + 1);
+    for (int k = lo; k <= hi - 1; ++k) {
+      const int nr = k < hi - 1 ? 3 : 2;  // reflector length
+      double v[3] = {x, y, nr == 3 ? z : 0.0};
+      const double nrm = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      if (nrm > 0.0) {
+        const double alpha = v[0] >= 0.0 ? -nrm : nrm;
+        v[0] -= alpha;
+        const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        if (vv > 0.0) {
+          const double beta = 2.0 / vv;
+          for (int jc = std::max(lo, k - 1); jc <= hi; ++jc) {  // rows k.. from the left
+            double d = 0.0;
+            for (int r = 0; r < nr; ++r) d += v[r] * h(k + r, jc);
+            for (int r = 0; r < nr; ++r) h(k + r, jc) -= beta * d * v[r];
+          }
+          for (int ir = lo; ir <= std::min(k + 3, hi); ++ir) {  // columns k.. from the right
+            double d = 0.0;
+            for (int r = 0; r < nr; ++r) d += h(ir, k + r) * v[r];
+            for (int r = 0; r < nr; ++r) h(ir, k + r) -= beta * d * v[r];
+          }
+        }
+      }
+      if (k < hi - 1) {
+        x = h(k + 1, k);
+        y = h(k + 2, k);
+        z = k < hi - 2 ? h(k + 3, k) : 0.0;
+      }
+    }
+  }
+  *out = best;
+  return GMG_OK;
+}
+
+// out = M_l^{-1} A_l v for natural float64 vectors of level l: the
+// operator in float64 (the finest level's from the float64 coefficient,
+// the coarser levels' from their float64 faces), M_l the smoother's SSOR
+// solve in the V-cycle precision T.
+template <typename T>
+void cheb_minv_a(gmg_ctx* c, int l, const double* v, double* out) {
+  const LevelShape& s = c->L.shapes[l];
+  const Geom g = s.geom();
+  double* w = wsp<double>(c, c->L.cr0);
+  if (l == 0) {
+    const Launch rl = red_launch(c);
+    GMG_LAUNCH(c, "cheb_op_fine", k_op_natural<1>, rl, v, c->a, g, w, v, c->L.ldv, wsp<double>(c, c->L.partials),
+               rl.kc);
+    const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
+    T* E = wsp<T>(c, c->L.xs);
+    T* Bs = wsp<T>(c, c->L.b0);
+    gs_split<T, true>(c, E, Bs, w, nullptr, a, 0);
+    gs_split<T, false>(c, E, Bs, nullptr, nullptr, a, 1);
+    gs_split<T, false>(c, E, Bs, nullptr, nullptr, a, 0);
+    const Launch pl = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+    GMG_LAUNCH(c, "split_to_natural", k_split_to_natural<T>, pl, (const T*)E, c->L.hn, g, out, pl.kc);
+    return;
+  }
+  const LevelOffsets& o = c->L.lv[l];
+  const size_t n = s.n();
+  const FaceCoef<double> co64{wsp<double>(c, o.wx64), wsp<double>(c, o.wy64), wsp<double>(c, o.wz64),
+                              wsp<double>(c, o.tp64)};
+  const Launch cl = cell_launch(s.nx, s.ny, s.nz, 4096, 4);
+  GMG_LAUNCH(c, kname("cheb_op", l, 8), k_resid_face<double>, cl, (const double*)v, (const double*)nullptr, co64,
+             g, w, cl.kc);
+  T* R = wsp<T>(c, o.cr);
+  T* E = wsp<T>(c, o.ce);
+  const Launch fl = flat_launch(n);
+  GMG_LAUNCH(c, "convert", (k_convert<T, double>), fl, (const double*)w, R, n);
+  const FaceCoef<T> co = face_coef<T>(c, l);
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
+  GMG_LAUNCH(c, kname("ssor_first", l, sizeof(T)), (k_gs_pair_face<T, true>), pl, E, (const T*)R, co, g, pl.kc, 0);
+  GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, (const T*)R, co, g, pl.kc, 1);
+  GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, (const T*)R, co, g, pl.kc, 0);
+  GMG_LAUNCH(c, "convert", (k_convert<double, T>), fl, (const T*)E, out, n);
+}
+
+// Arnoldi estimates and recurrence coefficients of every smoothed level.
+template <typename T>
+int cheb_estimate(gmg_ctx* c) {
+  const int nl = (int)c->L.shapes.size();
+  c->cheb_lam.assign(std::max(nl - 1, 0), 0.0);
+  c->cheb_coef.assign(std::max(nl - 1, 0), {});
+  double* sd = scal_misc(c) + 16;  // dots 0..10, ||w||^2 at 11, the constant 1 at 12
+  double* part = wsp<double>(c, c->L.partials);
+  GMG_LAUNCH(c, "fill", k_fill<double>, flat_launch(1), sd + 12, 1.0, (size_t)1);
+  for (int l = 0; l < nl - 1; ++l) {
+    const size_t n = c->L.shapes[l].n();
+    const Launch fl = flat_launch(n);
+    Launch rf = fl;
+    rf.grid.x = std::min<unsigned>(fl.grid.x, MAX_RED_BLOCKS);
+    const int nb = rf.nblocks();
+    double* V0 = kvec(c, 0);
+    GMG_LAUNCH(c, "uniform_start", k_uniform_start, fl, V0, n, (unsigned long long)l);
+    GMG_LAUNCH(c, "multidot", k_multidot<1>, rf, (const double*)V0, n, (const double*)V0, c->L.ldv, part);
+    finalize(c, nb, 1, 0, sd + 11, nullptr, nullptr);
+    if (read_back(c, sd + 11, 1) != GMG_OK) return GMG_ERR_HIP;
+    const double n0 = std::sqrt(c->pinned[0]);
+    if (!(n0 > 0.0) || !std::isfinite(n0)) return GMG_ERR_NONFINITE;
+    GMG_LAUNCH(c, "lincomb", k_lincomb3, fl, V0, (const double*)V0, (const double*)nullptr, (const double*)nullptr,
+               1.0 / n0, 0.0, 0.0, n, 0, part);
+    double H[(CHEB_ARNOLDI + 1) * CHEB_ARNOLDI] = {};
+    int m = CHEB_ARNOLDI;
+    for (int j = 0; j < CHEB_ARNOLDI; ++j) {
+      double* w = kvec(c, j + 1);
+      cheb_minv_a<T>(c, l, kvec(c, j), w);
+      for (int i = 0; i <= j; ++i) {
+        GMG_LAUNCH(c, "multidot", k_multidot<1>, rf, (const double*)w, n, (const double*)kvec(c, i), c->L.ldv,
+                   part);
+        finalize(c, nb, 1, 0, sd + i, nullptr, nullptr);
+        GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<1>, rf, w, n, (const double*)kvec(c, i), c->L.ldv,
+                   (const double*)(sd + i), (const double*)(sd + 12), i == j ? 1 : 0, part);
+      }
+      finalize(c, nb, 1, 0, sd + 11, nullptr, nullptr);
+      if (read_back(c, sd, 12) != GMG_OK) return GMG_ERR_HIP;
+      for (int i = 0; i <= j; ++i) H[i * CHEB_ARNOLDI + j] = c->pinned[i];
+      const double hn = std::sqrt(c->pinned[11]);
+      if (!std::isfinite(hn)) return GMG_ERR_NONFINITE;
+      if (hn == 0.0) {
+        m = j + 1;
+        break;
+      }
+      H[(j + 1) * CHEB_ARNOLDI + j] = hn;
+      if (j + 1 < CHEB_ARNOLDI)
+        GMG_LAUNCH(c, "lincomb", k_lincomb3, fl, w, (const double*)w, (const double*)nullptr, (const double*)nullptr,
+                   1.0 / hn, 0.0, 0.0, n, 0, part);
+    }
+    double lam = 0.0;
+    const int st = ritz_max_real(H, m, CHEB_ARNOLDI, &lam);
+    if (st != GMG_OK) return st == GMG_NOT_CONVERGED ? GMG_ERR_NONFINITE : st;
+    if (!(lam > 0.0)) return GMG_ERR_NONFINITE;
+    c->cheb_lam[l] = lam;
+    // eq. qntn on [0.1 lam, 1.1 lam]: theta, delta the centre and half-width
+    const double lmin = 0.1 * lam, lmax = 1.1 * lam;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    auto& cf = c->cheb_coef[l];
+    cf[0] = 0.0;
+    cf[1] = 1.0 / theta;  // d = e / theta
+    double rho_prev = 1.0 / sigma;
+    for (int st2 = 1; st2 < CHEB_DEGREE; ++st2) {
+      const double rho = 1.0 / (2.0 * sigma - rho_prev);
+      cf[2 * st2] = rho * rho_prev;
+      cf[2 * st2 + 1] = 2.0 * rho / delta;
+      rho_prev = rho;
+    }
+  }
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
 // out = M u (one V-cycle from zero) in the natural layout, float64.
 void precond_natural(gmg_ctx* c, const double* u, double* out) {
   char* Zb = c->ws + c->L.Z;
@@ -1436,6 +1786,7 @@ void gmg_default_options(gmg_options* opt) {
   opt->fine_sweep = GMG_SWEEP_AUTO;
   opt->cold_cycle = GMG_CYCLE_FMG;
   opt->graphs = 0;
+  opt->smoother = GMG_SMOOTH_RBGS;
 }
 
 size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt) {
@@ -1473,7 +1824,8 @@ int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const dou
   c->N = L.shapes[0].n();
   c->mixed = opt->precision == GMG_MIXED;
   c->nc = (int)L.shapes.back().n();
-  c->bottom_from = bottom_level(L);
+  // the Chebyshev smoother runs every level through the per-level kernels
+  c->bottom_from = opt->smoother == GMG_SMOOTH_CHEBYSHEV ? -1 : bottom_level(L);
   c->err = hipSuccess;
   c->pinned = nullptr;
   const int m = opt->restart;
@@ -1488,6 +1840,7 @@ int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const dou
   }
   int r = c->mixed ? write_bottom_args<float>(c) : write_bottom_args<double>(c);
   if (r == GMG_OK) r = build_hierarchy(c);
+  if (r == GMG_OK && opt->smoother == GMG_SMOOTH_CHEBYSHEV) r = c->mixed ? cheb_estimate<float>(c) : cheb_estimate<double>(c);
   if (r != GMG_OK) {
     gmg_destroy(c);
     return r;
@@ -1498,9 +1851,26 @@ int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const dou
 
 int gmg_update_coefficient(gmg_ctx* c, const double* a_dev) {
   if (!valid_ctx(c) || !a_dev) return GMG_ERR_ARG;
-  if (a_dev != c->a) drop_graphs(c);  // the float64 cycle reads the coefficient itself
+  const bool cheb = c->opt.smoother == GMG_SMOOTH_CHEBYSHEV;
+  // the float64 cycle reads the coefficient itself; the Chebyshev
+  // coefficients are launch arguments
+  if (a_dev != c->a || cheb) drop_graphs(c);
   c->a = a_dev;
-  return build_hierarchy(c);
+  int r = build_hierarchy(c);
+  if (r == GMG_OK && cheb) r = c->mixed ? cheb_estimate<float>(c) : cheb_estimate<double>(c);
+  return r;
+}
+
+int gmg_chebyshev_estimates(gmg_ctx* c, double* lam, int cap, int* nlevels) {
+  if (!valid_ctx(c) || !lam || !nlevels || cap < 0 || c->opt.smoother != GMG_SMOOTH_CHEBYSHEV) return GMG_ERR_ARG;
+  *nlevels = (int)c->cheb_lam.size();
+  for (int l = 0; l < std::min(cap, *nlevels); ++l) lam[l] = c->cheb_lam[l];
+  return GMG_OK;
+}
+
+int gmg_ritz_max_real(const double* H, int m, int ldh, double* out) {
+  if (!H || !out || m < 1 || m > 64 || ldh < m) return GMG_ERR_ARG;
+  return ritz_max_real(H, m, ldh, out);
 }
 
 int gmg_set_stream(gmg_ctx* c, void* hip_stream) {
@@ -1713,7 +2083,10 @@ int cycle_api(gmg_ctx* c, const double* v_dev, double* z_dev, bool fmg) {
 
 int gmg_vcycle(gmg_ctx* c, const double* v_dev, double* z_dev) { return cycle_api(c, v_dev, z_dev, false); }
 
-int gmg_fmg(gmg_ctx* c, const double* v_dev, double* z_dev) { return cycle_api(c, v_dev, z_dev, true); }
+int gmg_fmg(gmg_ctx* c, const double* v_dev, double* z_dev) {
+  if (valid_ctx(c) && c->opt.smoother == GMG_SMOOTH_CHEBYSHEV) return GMG_ERR_ARG;  // V-cycles only
+  return cycle_api(c, v_dev, z_dev, true);
+}
 
 int gmg_face_flux_grad(gmg_ctx* c, const double* phi_dev, const double* lam_dev, double phi_bot, double phi_top,
                        double* dLda_dev) {

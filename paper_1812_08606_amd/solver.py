@@ -16,6 +16,7 @@ FP64, MIXED = 0, 1
 _PRECISION = {"fp64": FP64, "mixed": MIXED}
 _FINE_SWEEP = {"auto": 0, "half": 1, "fused": 2}
 _COLD_CYCLE = {"vcycle": 0, "fmg": 1}
+_SMOOTHER = {"rbgs": 0, "chebyshev": 1}
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -68,12 +69,17 @@ class GMGPoisson:
     per symmetric sweep, float32 only) or "auto".  cold_cycle: preconditioner
     of a solve without an initial guess, "fmg" (full multigrid, the default)
     or "vcycle"; warm-started solves use V-cycles.  graphs: replay each
-    preconditioner application from a captured HIP graph (same results)."""
+    preconditioner application from a captured HIP graph (same results).
+    smoother: "rbgs" (red-black symmetric Gauss-Seidel, nu_pre / nu_post
+    sweeps) or "chebyshev" (the degree-2 Chebyshev polynomial in the
+    SSOR-preconditioned level operator, Sec. 3.2 eq. qntn, nu_pre / nu_post
+    applications, default 1 each; V-cycles only, so cold_cycle defaults to
+    "vcycle")."""
 
     def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
-                 max_iter: int = 200, nu_pre: int = 2, nu_post: int = 2,
-                 coarse_max_cells: int = 4096, fine_sweep: str = "auto", cold_cycle: str = "fmg",
-                 graphs: bool = False):
+                 max_iter: int = 200, nu_pre: int | None = None, nu_post: int | None = None,
+                 coarse_max_cells: int = 4096, fine_sweep: str = "auto", cold_cycle: str | None = None,
+                 graphs: bool = False, smoother: str = "rbgs"):
         self._lib = _lib.load()
         if a.dim() != 3:
             raise ValueError("a must be 3-D (nz, ny, nx)")
@@ -87,6 +93,16 @@ class GMGPoisson:
         self.precision = precision
         if fine_sweep not in _FINE_SWEEP:
             raise ValueError(f"fine_sweep must be one of {sorted(_FINE_SWEEP)}")
+        if smoother not in _SMOOTHER:
+            raise ValueError(f"smoother must be one of {sorted(_SMOOTHER)}")
+        cheb = smoother == "chebyshev"
+        if cold_cycle is None:
+            cold_cycle = "vcycle" if cheb else "fmg"
+        if nu_pre is None:
+            nu_pre = 1 if cheb else 2
+        if nu_post is None:
+            nu_post = 1 if cheb else 2
+        self.smoother = smoother
         if cold_cycle not in _COLD_CYCLE:
             raise ValueError(f"cold_cycle must be one of {sorted(_COLD_CYCLE)}")
         opt = _lib.Options()
@@ -98,6 +114,7 @@ class GMGPoisson:
         opt.fine_sweep = _FINE_SWEEP[fine_sweep]
         opt.cold_cycle = _COLD_CYCLE[cold_cycle]
         opt.graphs = int(bool(graphs))
+        opt.smoother = _SMOOTHER[smoother]
         self.options = opt
         nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
         if nbytes == 0:
@@ -134,6 +151,16 @@ class GMGPoisson:
             self._ctx = ctypes.c_void_p()
 
     close = __del__
+
+    def chebyshev_estimates(self):
+        """Arnoldi estimate lambda of each smoothed level (Chebyshev smoother;
+        the bounds of eq. qntn are 0.1 and 1.1 lambda)."""
+        n = ctypes.c_int()
+        out = (ctypes.c_double * 64)()
+        st = self._lib.gmg_chebyshev_estimates(self._ctx, out, 64, ctypes.byref(n))
+        if st != OK:
+            raise GMGError(st, "gmg_chebyshev_estimates")
+        return [out[i] for i in range(min(n.value, 64))]
 
     @property
     def levels(self):

@@ -36,7 +36,7 @@ def test_default_options_and_workspace(lib):
     opt = Options()
     lib.gmg_default_options(ctypes.byref(opt))
     assert (opt.restart, opt.max_iter, opt.nu_pre, opt.nu_post, opt.precision, opt.coarse_max_cells,
-            opt.fine_sweep, opt.cold_cycle, opt.graphs) == (10, 200, 2, 2, 1, 4096, 0, 1, 0)
+            opt.fine_sweep, opt.cold_cycle, opt.graphs, opt.smoother) == (10, 200, 2, 2, 1, 4096, 0, 1, 0, 0)
     n64 = lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt))
     N = 64 ** 3
     # 11 float64 Krylov vectors + 10 float32 preconditioned vectors dominate
@@ -51,6 +51,19 @@ def test_default_options_and_workspace(lib):
     opt.fine_sweep = 2
     assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == n64
     opt.fine_sweep = 0
+    # Chebyshev smoother: V-cycles only; extra per-level buffers
+    opt.smoother = 1
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == 0  # with the FMG cold cycle
+    opt.cold_cycle = 0
+    n_cheb = lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt))
+    assert n64 + N * 8 < n_cheb < n64 + 3 * N * 8
+    opt.restart = 4  # the bound estimate still gets its 11 basis slots
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) > 11 * N * 8
+    opt.restart = 10
+    opt.smoother = 2
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == 0
+    opt.smoother = 0
+    opt.cold_cycle = 1
     opt.precision = 0
     assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) > n64
 
@@ -72,3 +85,61 @@ def test_null_arguments_rejected(lib):
     assert lib.gmg_assemble_elliptic(None, None, None, None, None, None) == -1
     assert lib.gmg_electric_field(None, None, 0.0, 1.0, None, None, None, None) == -1
     assert lib.gmg_fmg(None, None, None) == -1
+    n = ctypes.c_int()
+    lam = (ctypes.c_double * 4)()
+    assert lib.gmg_chebyshev_estimates(None, lam, 4, ctypes.byref(n)) == -1
+    v = ctypes.c_double()
+    assert lib.gmg_ritz_max_real(None, 3, 3, ctypes.byref(v)) == -1
+
+
+def _ritz(lib, H):
+    import numpy as np
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    m = H.shape[0]
+    out = ctypes.c_double()
+    st = lib.gmg_ritz_max_real(H.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m, H.shape[1],
+                               ctypes.byref(out))
+    return st, out.value
+
+
+def test_ritz_max_real_matches_dense_eigenvalues(lib):
+    """The host step of the Chebyshev bound estimate: the largest real part
+    of the eigenvalues of an upper Hessenberg matrix (Francis QR) against
+    numpy's dense eigenvalue routine, on random Hessenberg matrices of every
+    size 1..12 (real and complex spectra), Arnoldi matrices of a symmetric
+    positive definite operator, and matrices with an exactly zero
+    subdiagonal entry; entries below the subdiagonal are ignored and the row
+    stride may exceed m."""
+    import numpy as np
+    rng = np.random.default_rng(71)
+    for trial in range(300):
+        m = 1 + trial % 12
+        H = np.triu(rng.standard_normal((m, m)), -1)
+        if trial % 5 == 0 and m > 2:
+            H[m // 2, m // 2 - 1] = 0.0
+        want = np.linalg.eigvals(H).real.max()
+        junk = np.tril(rng.standard_normal((m, m)), -2)
+        wide = np.zeros((m, m + 3))
+        wide[:, :m] = H + junk
+        st, got = _ritz(lib, wide)
+        assert st == 0 and abs(got - want) <= 1e-10 * max(1.0, np.abs(H).max()), (trial, got, want)
+    # Arnoldi on a symmetric positive definite matrix: real Ritz values
+    for m in (1, 2, 5, 10):
+        B = rng.standard_normal((40, 40))
+        S = B @ B.T + 40 * np.eye(40)
+        V = np.zeros((40, m + 1))
+        Hh = np.zeros((m + 1, m))
+        v = rng.standard_normal(40)
+        V[:, 0] = v / np.linalg.norm(v)
+        for j in range(m):
+            w = S @ V[:, j]
+            for i in range(j + 1):
+                Hh[i, j] = w @ V[:, i]
+                w = w - Hh[i, j] * V[:, i]
+            Hh[j + 1, j] = np.linalg.norm(w)
+            V[:, j + 1] = w / Hh[j + 1, j]
+        st, got = _ritz(lib, Hh[:m, :m])
+        assert st == 0 and abs(got - np.linalg.eigvals(Hh[:m, :m]).real.max()) <= 1e-10 * got
+    st, _ = _ritz(lib, np.array([[1.0, np.nan], [1.0, 2.0]]))
+    assert st == -1
+

@@ -724,3 +724,116 @@ def test_graph_replays_equal_eager_launches(precision):
     rg = sg.solve(f, p.phi_bot, p.phi_top, tol=1e-8)
     re_ = se.solve(f, p.phi_bot, p.phi_top, tol=1e-8)
     assert torch.equal(rg.phi, re_.phi)
+
+
+# ---------------------------------------------------------------- Chebyshev smoother
+CHEB_SHAPES = [(48, 40, 36), (70, 12, 8), (64, 64, 64), (6, 4, 10), (130, 8, 4), (32, 32, 40)]
+
+
+def _oracle_cheb(a, h):
+    from oracle.chebyshev import lambda_max_estimate, start_vector
+    hier = build_hierarchy(a, h)
+    lams = []
+    for li, lev in enumerate(hier.levels[:-1]):
+        nx, ny, nz = lev.shape
+        lams.append(lambda_max_estimate(lev, start_vector((nz, ny, nx), li)))
+    return hier, lams
+
+
+@pytest.mark.parametrize("shape", CHEB_SHAPES)
+def test_chebyshev_estimates_and_vcycle_match_oracle(shape):
+    """Chebyshev(2)+SSOR smoother (Sec. 3.2, eq. qntn), float64: the Arnoldi
+    estimate of every smoothed level (SplitMix64 start vectors drawn on each
+    side) and one V-cycle from zero against the oracle's."""
+    from oracle.chebyshev import vcycle_chebyshev
+    print(f"chebyshev fp64 {shape}", flush=True)
+    a, f, h = _rand_problem(shape, 8)
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64", smoother="chebyshev")
+    hier, lams = _oracle_cheb(a, h)
+    assert [tuple(l.shape) for l in hier.levels] == s.levels
+    got = s.chebyshev_estimates()
+    assert len(got) == len(lams)
+    np.testing.assert_allclose(got, lams, rtol=1e-11)
+    bounds = [(0.1 * lam, 1.1 * lam) for lam in lams]
+    z = npy(s.vcycle(T(f)))
+    ref = vcycle_chebyshev(hier, bounds, f)
+    assert rel(z, ref) < 1e-11
+    np.testing.assert_allclose(z, ref, rtol=1e-8, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("nu", [(2, 1), (1, 2), (0, 1)])
+def test_chebyshev_vcycle_applications(nu):
+    """nu_pre / nu_post applications of the smoother (0: none before the
+    coarse correction) against the oracle's V-cycle with the same counts."""
+    from oracle.chebyshev import chebyshev_smooth
+    from oracle.multigrid import coarse_solve, prolong, restrict
+    from oracle.operator import apply_faces
+    a, f, h = _rand_problem((32, 24, 16), 9)
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64", smoother="chebyshev", nu_pre=nu[0], nu_post=nu[1])
+    hier, lams = _oracle_cheb(a, h)
+
+    def cyc(b, level):
+        lev = hier.levels[level]
+        if level == len(hier.levels) - 1:
+            return coarse_solve(hier, b)
+        lmax, lstar = 1.1 * lams[level], 0.1 * lams[level]
+        x = np.zeros_like(b)
+        for _ in range(nu[0]):
+            x = chebyshev_smooth(x, b, lev, lmax, lstar)
+        x = x + prolong(cyc(restrict(b - apply_faces(x, lev.faces, lev.h)), level + 1))
+        for _ in range(nu[1]):
+            x = chebyshev_smooth(x, b, lev, lmax, lstar)
+        return x
+    assert rel(npy(s.vcycle(T(f))), cyc(f, 0)) < 1e-11
+
+
+@pytest.mark.parametrize("case", [(3, 32, 6, 10), (2, 32, 8, 5)])
+def test_chebyshev_fgmres_fixed_steps_match_oracle(case):
+    """FGMRES(m) with the Chebyshev V-cycle, fixed step count, float64."""
+    from oracle.chebyshev import vcycle_chebyshev
+    from oracle.fgmres import fgmres
+    cfg, n, k, m = case
+    print(f"chebyshev fgmres workload {cfg} n={n} k={k} m={m}", flush=True)
+    p = make_config(cfg, n=n)
+    s = gm.GMGPoisson(T(p.a), precision="fp64", smoother="chebyshev", restart=m, max_iter=k)
+    res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=0.0)
+    hier, lams = _oracle_cheb(p.a, p.h)
+    bounds = [(0.1 * lam, 1.1 * lam) for lam in lams]
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    ref = fgmres(lambda x: apply_operator(x, p.a, p.h), b, lambda v: vcycle_chebyshev(hier, bounds, v),
+                 tol=0.0, restart=m, max_iter=k)
+    assert res.iterations == ref.iterations == k
+    assert rel(npy(res.phi), ref.x) < 1e-10
+
+
+def test_chebyshev_mixed_converges_and_renews_bounds():
+    """Mixed precision (float32 smoother and estimate's SSOR), filament 64^3,
+    max(a) = 1e4: the estimates agree with float64's to float32 rounding; the
+    solve converges (checked with the oracle's operator) in at most one step
+    more than the float64 oracle's Chebyshev solve; a new coefficient
+    re-estimates the bounds exactly as a fresh context does; the full
+    multigrid entry point is refused (V-cycles only)."""
+    from oracle.chebyshev import vcycle_chebyshev
+    from oracle.fgmres import fgmres
+    p = make_config(3, n=64)
+    s = gm.GMGPoisson(T(p.a), precision="mixed", smoother="chebyshev")
+    s64 = gm.GMGPoisson(T(p.a), precision="fp64", smoother="chebyshev")
+    np.testing.assert_allclose(s.chebyshev_estimates(), s64.chebyshev_estimates(), rtol=1e-4)
+    res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8)
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    r = np.linalg.norm(b - apply_operator(npy(res.phi), p.a, p.h)) / np.linalg.norm(b)
+    hier, lams = _oracle_cheb(p.a, p.h)
+    bounds = [(0.1 * lam, 1.1 * lam) for lam in lams]
+    ref = fgmres(lambda x: apply_operator(x, p.a, p.h), b, lambda v: vcycle_chebyshev(hier, bounds, v), tol=1e-8)
+    print(f"chebyshev mixed 64^3: {res.iterations} steps (fp64 oracle {ref.iterations}), relres {r:.2e}",
+          flush=True)
+    assert res.converged and r < 1e-8 and res.iterations <= ref.iterations + 1
+    a2 = T(p.a) * 1.5 + 0.25
+    s.update_coefficient(a2)
+    fresh = gm.GMGPoisson(a2, precision="mixed", smoother="chebyshev")
+    assert s.chebyshev_estimates() == fresh.chebyshev_estimates()
+    r2 = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8)
+    r3 = fresh.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8)
+    assert r2.converged and torch.equal(r2.phi, r3.phi)
+    with pytest.raises(gm.solver.GMGError):
+        s.fmg(T(p.f))
