@@ -23,7 +23,9 @@ Besides the step, the other Krylov methods of Sec. 5.3 (Table t1) are timed
 on the workload's forward problem, and again on the streamer channel meshed
 256 x 256 x 320 and 512 x 512 x 640 on the unit cube (the comparison's
 meshes, h_z < h_x = h_y), with its variable coefficient and with a = 1
-(Table t2's constant-coefficient problem).
+(Table t2's constant-coefficient problem).  The red-black Gauss-Seidel
+smoother is also compared with the paper's Chebyshev(2)+SSOR smoother on the
+workload's forward problem (solve time, iterations, renewal time).
 
 Prints one JSON line on stdout; progress goes to stderr.
 
@@ -69,7 +71,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=160, help="edge of the CPU-oracle sample grid")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
-    ap.add_argument("--no-krylov", action="store_true", help="skip the comparison of Krylov methods")
+    ap.add_argument("--no-krylov", action="store_true",
+                    help="skip the comparison runs (Krylov methods, meshes, smoothers)")
+    ap.add_argument("--no-smoothers", action="store_true",
+                    help="skip the comparison of the Gauss-Seidel and Chebyshev smoothers")
     ap.add_argument("--krylov-meshes", default="256x256x320,512x512x640",
                     help="comma-separated nx x ny x nz meshes of the unit cube for the Krylov comparison "
                          "('' skips it)")
@@ -131,6 +136,29 @@ def bytes_per_cell(base, level, s, nu_post=2):
         if base == "prolong_set":  # coarse x read, x written
             return s + s / 8
     return None
+
+
+def cheb_bytes_per_cell(base, level, s):
+    """Kernels of a V-cycle with the Chebyshev(2)+SSOR smoother (the SSOR
+    half-sweeps are the Gauss-Seidel kernels and keep their models)."""
+    if base == "cheb_update":  # d, x written; e, d, x read, except d in the first step of an
+        # application and x in the first from zero: mean of 3s, 5s, 4s, 5s over a V-cycle's 4 steps
+        return 4.25 * s
+    if level == 0:
+        if base == "cheb_resid":  # X (both colours), u (float64), a read; r (float64, natural) written
+            return 2 * s + 16
+        if base == "restrict_rhs":  # r (float64) read; B scratch and the coarse right side written
+            return 8 + s + s / 8
+        if base == "prolong_add":  # both colours of X read and written, coarse x read
+            return 2 * s + s / 8
+    elif level is not None and level > 0:
+        if base == "cheb_resid":  # x, b, faces read; r written
+            return 6 * s
+        if base == "ssor_first":
+            return bytes_per_cell("gs_first", level, s)
+        if base == "ssor":
+            return bytes_per_cell("gs", level, s)
+    return bytes_per_cell(base, level, s)
 
 
 def outer_bytes(name, nv, s_z):
@@ -406,6 +434,56 @@ def main():
             del aq, fq
             torch.cuda.empty_cache()
 
+    # -- smoothers (Sec. 3.2): red-black symmetric Gauss-Seidel (the default,
+    # full multigrid cycles on a cold solve; and with V-cycles) against the
+    # paper's Chebyshev(2)+SSOR smoother (V-cycles), forward solve from zero;
+    # renewal = hierarchy rebuild (+ the Chebyshev bound estimate) ----------
+    smoothers = None
+    if not c5 and not args.no_krylov and not args.no_smoothers:
+        log("smoother comparison (mixed, forward solve from zero) ...")
+        smoothers = {}
+        phi = torch.empty_like(a0)
+        for label, kw in (("rbgs_fmg", {}), ("rbgs_vcycle", {"cold_cycle": "vcycle"}),
+                          ("chebyshev_vcycle", {"smoother": "chebyshev"})):
+            solver = gm.GMGPoisson(a0, precision="mixed", **kw)
+            res = solver.solve(f0, p.phi_bot, p.phi_top, args.tol, out=phi)
+            times, renew = [], []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                res = solver.solve(f0, p.phi_bot, p.phi_top, args.tol, out=phi)
+                e1.record()
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+                e0.record()
+                solver.update_coefficient(a0)
+                e1.record()
+                e1.synchronize()
+                renew.append(e0.elapsed_time(e1))
+            solver.profile(True)
+            solver.profile_reset()
+            solver.solve(f0, p.phi_bot, p.phi_top, args.tol, out=phi)
+            prof = solver.profile_read()
+            solver.profile(False)
+            kernels = []
+            for name, (tot, cnt) in sorted(prof.items(), key=lambda kv: -kv[1][0])[:8]:
+                base, level = split_name(name)
+                bpc = cheb_bytes_per_cell(base, level, 4) if level is not None and level >= 0 else None
+                gbs = bpc * N / 8 ** level * cnt / (tot * 1e-3) / 1e9 if bpc else None
+                kernels.append({"kernel": name, "ms": round(tot, 3), "launches": cnt,
+                                "GBps": round(gbs) if gbs else None})
+            smoothers[label] = dict(solve_ms=statistics.median(times), renewal_ms=statistics.median(renew),
+                                    iterations=res.iterations, converged=res.converged,
+                                    final_relres=res.final_relres, top_kernels=kernels)
+            if label.startswith("chebyshev"):
+                smoothers[label]["lambda_per_level"] = solver.chebyshev_estimates()
+            log(f"  {label:17s} solve {smoothers[label]['solve_ms']:8.2f} ms  {res.iterations:3d} it  "
+                f"renewal {smoothers[label]['renewal_ms']:7.2f} ms  top {kernels[0]['kernel']} "
+                f"{kernels[0]['GBps']} GB/s")
+            del solver
+        del phi
+        torch.cuda.empty_cache()
+
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -533,6 +611,7 @@ def main():
         "cpu_baseline": cpu,
         "krylov_methods": krylov,
         "krylov_meshes": krylov_meshes,
+        "smoothers": smoothers,
     }
     if fp64 is not None:
         line["fp64"] = {
