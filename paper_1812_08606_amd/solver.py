@@ -105,6 +105,8 @@ class GMGPoisson:
         self.smoother = smoother
         if cold_cycle not in _COLD_CYCLE:
             raise ValueError(f"cold_cycle must be one of {sorted(_COLD_CYCLE)}")
+        if cheb and cold_cycle == "fmg":
+            raise ValueError("the Chebyshev smoother runs V-cycles only (cold_cycle='vcycle')")
         opt = _lib.Options()
         self._lib.gmg_default_options(ctypes.byref(opt))
         opt.restart, opt.max_iter = int(restart), int(max_iter)
