@@ -3,9 +3,10 @@
 
 Default workload (c3): the 512^3 single-filament problem (max(a) = 1e4,
 f = 50 (n_p - n_e)), unit cube, phi = 0 / 1 on the plates, tolerance 1e-8,
-FGMRES(10) with one multigrid cycle per step (V(2,2) smoothing): full
-multigrid cycles in a solve from no initial guess, V-cycles in a
-warm-started one (the library defaults).  One benchmark step is one pass of
+FGMRES(10) with one multigrid cycle per step: full multigrid cycles in a
+solve from no initial guess, V-cycles in a warm-started one (the library's
+default), with 2 pre- and 3 post-smoothing sweeps (the library's default is
+2 and 2; one more post-sweep saves a FGMRES step of the cold solves here).  One benchmark step is one pass of
 the whole hot path: coefficient renewal (hierarchy rebuild), the forward
 solve from a zero guess, the adjoint solve for a fixed dL/dphi and the dL/da
 face-flux kernel.  Each step therefore holds two converged 1e-8 solves;
@@ -17,7 +18,8 @@ max(a) = 1e3, 256^3 gradient workload) run the same step on their fields.
 Workload c5: the 768^3 two-filament time loop.  Step t advects both
 filaments t cells in +z (the step-0 fields rolled along z on the device),
 renews the coefficient and solves warm-started from the previous phi; one
-solve per step.
+solve per step, with the library's V(2,2) (the warm solves take as many
+steps with a third post-sweep, which then only costs time).
 
 Besides the step, the other Krylov methods of Sec. 5.3 (Table t1) are timed
 on the workload's forward problem, and again on the streamer channel meshed
@@ -73,6 +75,10 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-krylov", action="store_true",
                     help="skip the comparison runs (Krylov methods, meshes, smoothers)")
+    ap.add_argument("--nu-pre", type=int, default=None,
+                    help="pre-smoothing sweeps of the step (default 2)")
+    ap.add_argument("--nu-post", type=int, default=None,
+                    help="post-smoothing sweeps of the step (default 3 for c1-c4, 2 for c5)")
     ap.add_argument("--no-smoothers", action="store_true",
                     help="skip the comparison of the Gauss-Seidel and Chebyshev smoothers")
     ap.add_argument("--krylov-meshes", default="256x256x320,512x512x640",
@@ -85,6 +91,11 @@ def parse():
         args.steps = 19 if args.workload == "c5" else 3
     if args.n is None:
         args.n = {"c1": 64, "c2": 256, "c3": 512, "c4": 256, "c5": 768}[args.workload]
+    # smoothing of the benchmark step: V(2,3) for the cold-start workloads
+    # (fewest FGMRES steps per unit time with full multigrid cycles at 256^3
+    # and 512^3), the library's V(2,2) for the warm-started time loop
+    if args.nu_pre is None and args.nu_post is None:
+        args.nu_pre, args.nu_post = (2, 2) if args.workload == "c5" else (2, 3)
     return args
 
 
@@ -247,6 +258,8 @@ def main():
     from workloads import make_config, probe_box_mask
 
     dev = torch.device("cuda:0")
+    # smoothing sweeps of the benchmark step (None: the library default)
+    nu_kw = {"nu_pre": args.nu_pre, "nu_post": args.nu_post}
     n = args.n
     N = n ** 3
     h = 1.0 / n
@@ -269,7 +282,7 @@ def main():
         return ((gx ** 2 + gy ** 2 + gz ** 2) * h ** 3).sum()
 
     def run_c3(precision):
-        solver = gm.GMGPoisson(a0, precision=precision)
+        solver = gm.GMGPoisson(a0, precision=precision, **nu_kw)
         phi = torch.empty_like(a0)
         lam = torch.empty_like(a0)
         grad = torch.empty_like(a0)
@@ -341,7 +354,7 @@ def main():
         # 0.59 at 768^3)
         step_prm = dict(eps0_over_e=1.0 / 50.0, tau_eff=1.0, mu_e=kappa / 50.0, mu_p=kappa / 5000.0,
                         De=(1e-6, 1e-6, 1e-6))
-        solver = gm.GMGPoisson(a0, precision=precision)
+        solver = gm.GMGPoisson(a0, precision=precision, **nu_kw)
         phi = torch.zeros_like(a0)
         a_t = torch.empty_like(a0)
         f_t = torch.empty_like(f0)
@@ -443,7 +456,7 @@ def main():
         log("smoother comparison (mixed, forward solve from zero) ...")
         smoothers = {}
         phi = torch.empty_like(a0)
-        for label, kw in (("rbgs_fmg", {}), ("rbgs_vcycle", {"cold_cycle": "vcycle"}),
+        for label, kw in (("rbgs_fmg", dict(nu_kw)), ("rbgs_vcycle", dict(nu_kw, cold_cycle="vcycle")),
                           ("chebyshev_vcycle", {"smoother": "chebyshev"})):
             solver = gm.GMGPoisson(a0, precision="mixed", **kw)
             res = solver.solve(f0, p.phi_bot, p.phi_top, args.tol, out=phi)
@@ -573,11 +586,11 @@ def main():
     desc = {1: "constant a = 1, Gaussian source", 2: "filament, max(a)=1e3", 3: "filament, max(a)=1e4",
             4: "filament, max(a)=1e3, probe-box loss", 5: "two filaments, max(a)=1e4"}[cfg]
     if c5:
-        workload = (f"{desc} {n}^3 time loop, tol {args.tol:g}, FGMRES(10) + V(2,2)-cycle mixed "
+        workload = (f"{desc} {n}^3 time loop, tol {args.tol:g}, FGMRES(10) + V({args.nu_pre},{args.nu_post})-cycle mixed "
                     "(float32 cycle, float64 outer); step = advect the densities (roll) + coefficient "
                     "and right side of e18 from them + renewal + warm-started solve + E = -grad phi")
     else:
-        workload = (f"{desc} {n}^3, tol {args.tol:g}, FGMRES(10) + full multigrid cycle (V(2,2) "
+        workload = (f"{desc} {n}^3, tol {args.tol:g}, FGMRES(10) + full multigrid cycle (V({args.nu_pre},{args.nu_post}) "
                     "smoothing) mixed (float32 cycle, float64 outer); step = renewal + forward solve + "
                     "adjoint solve + dL/da, both from no initial guess")
     line = {
