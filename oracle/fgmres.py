@@ -114,26 +114,28 @@ def fgmres(A, b, M, x0=None, tol=1e-8, restart=10, max_iter=200,
 
 def solve_poisson(a, f, h, phi_bot=0.0, phi_top=1.0, tol=1e-8, restart=10,
                   max_iter=200, nu_pre=2, nu_post=2, precision="fp64",
-                  x0=None, coarse_max_cells=4096, cold="fmg"):
+                  x0=None, coarse_max_cells=4096, cold="fmg", warm="vcycle"):
     """FGMRES(restart) with one multigrid cycle per step on A phi = f +
     lifting.
 
-    The cycle is a V-cycle, except in a solve without an initial guess
-    (x0 None) with cold = "fmg": there every step applies the full multigrid
-    cycle (Sec. 3.2: FMG on the first time step, which starts from zero,
-    V-cycles on the later, warm-started ones).
+    The cycle of a solve without an initial guess (x0 None) is the full
+    multigrid cycle when cold = "fmg", of a warm-started one when warm =
+    "fmg", and a V-cycle otherwise (Sec. 3.2: FMG on the first time step,
+    which starts from zero, V-cycles on the later, warm-started ones; the
+    defaults).  The preconditioner acts on the Krylov vectors, so either
+    cycle serves a warm start: it only changes M.
 
     precision "fp64": the whole cycle in float64;
     precision "mixed": the cycle (coefficients, smoother, transfers, coarse
     solve) in float32, its input v_j rounded to float32 and its output
     promoted exactly to float64; everything else in float64."""
     dtype = {"fp64": np.float64, "mixed": np.float32}[precision]
-    if cold not in ("vcycle", "fmg"):
-        raise ValueError("cold must be 'vcycle' or 'fmg'")
+    if cold not in ("vcycle", "fmg") or warm not in ("vcycle", "fmg"):
+        raise ValueError("cold and warm must be 'vcycle' or 'fmg'")
     hier = build_hierarchy(a, h, nu_pre=nu_pre, nu_post=nu_post,
                            coarse_max_cells=coarse_max_cells, dtype=dtype)
     b = rhs(f, a, h, phi_bot, phi_top)
-    cycle = fmg if (cold == "fmg" and x0 is None) else vcycle
+    cycle = fmg if (cold if x0 is None else warm) == "fmg" else vcycle
 
     def A(x):
         return apply_operator(x, a, h)

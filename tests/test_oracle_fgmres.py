@@ -164,3 +164,27 @@ def test_cold_start_fmg_preconditioner():
     w1 = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=x0, cold="vcycle")
     w2 = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=x0, cold="fmg")
     assert w1.iterations == w2.iterations and np.array_equal(w1.x, w2.x)
+
+
+def test_warm_start_with_fmg_preconditioner_is_the_residual_equation_solve():
+    """With warm = "fmg" a warm-started solve preconditions with the full
+    multigrid cycle.  FGMRES from x0 builds its Krylov space from r0 = b -
+    A x0, so it equals x0 plus FGMRES from zero on A e = r0 with the same
+    preconditioner and the tolerance rescaled to ||b|| (same iterations, same
+    iterate to rounding); on the two-filament time loop (max(a) = 1e4) it
+    needs fewer steps than the V-cycle."""
+    from oracle.fgmres import fgmres
+    from oracle.multigrid import build_hierarchy, fmg
+    p0 = config_two_filaments(32, step=0)
+    x0 = solve_poisson(p0.a, p0.f, p0.h, p0.phi_bot, p0.phi_top, tol=1e-8).x
+    p = config_two_filaments(32, step=1)
+    wf = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=x0, warm="fmg")
+    wv = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=x0)
+    assert wf.converged and wv.converged and wf.iterations < wv.iterations
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    r0 = b - apply_operator(x0, p.a, p.h)
+    hier = build_hierarchy(p.a, p.h)
+    e = fgmres(lambda x: apply_operator(x, p.a, p.h), r0, lambda v: fmg(hier, v),
+               tol=1e-8 * np.linalg.norm(b) / np.linalg.norm(r0))
+    assert e.iterations == wf.iterations
+    np.testing.assert_allclose(x0 + e.x, wf.x, rtol=0, atol=1e-10 * np.abs(wf.x).max())
