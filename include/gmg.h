@@ -68,9 +68,9 @@ enum { GMG_FP64 = 0, GMG_MIXED = 1 };
  * float32 rounding). */
 enum { GMG_SWEEP_AUTO = 0, GMG_SWEEP_HALF = 1, GMG_SWEEP_FUSED = 2 };
 
-/* Preconditioner of a solve started without an initial guess (Sec. 3.2: FMG
- * on the first time step, which starts from zero; V-cycles once the previous
- * solution is the guess). */
+/* Multigrid cycle applied by the preconditioner (Sec. 3.2: FMG on the first
+ * time step, which starts from zero; V-cycles once the previous solution is
+ * the guess). */
 enum { GMG_CYCLE_V = 0, GMG_CYCLE_FMG = 1 };
 
 /* Smoother of every level but the coarsest (Sec. 3.2).  GMG_SMOOTH_RBGS:
@@ -85,7 +85,8 @@ enum { GMG_CYCLE_V = 0, GMG_CYCLE_FMG = 1 };
  * is set; the start vector of level l is drawn by SplitMix64 seeded with l,
  * cell c taking output c + 1 mapped to [-1, 1) as 2 (z >> 11) 2^-53 - 1).
  * Chebyshev smoothing runs every level through per-level kernels (no
- * one-workgroup bottom kernel) and needs cold_cycle = GMG_CYCLE_V. */
+ * one-workgroup bottom kernel) and needs cold_cycle = warm_cycle =
+ * GMG_CYCLE_V. */
 enum { GMG_SMOOTH_RBGS = 0, GMG_SMOOTH_CHEBYSHEV = 1 };
 
 /* Solver options.  gmg_default_options fills the defaults given below. */
@@ -107,8 +108,7 @@ typedef struct gmg_options {
                            measured faster (float32, long z-chunks) */
   int cold_cycle;       /* preconditioner of a solve with use_x0 = 0: GMG_CYCLE_FMG
                            (default) one full multigrid cycle per step,
-                           GMG_CYCLE_V one V-cycle per step.  Warm-started
-                           solves always use V-cycles. */
+                           GMG_CYCLE_V one V-cycle per step. */
   int graphs;           /* 1: each preconditioner application is captured
                            once into a HIP graph and replayed; 0 (default):
                            its kernels are launched one by one.  Results are
@@ -116,6 +116,11 @@ typedef struct gmg_options {
                            coarse-level kernels wait on the GPU's dispatch
                            latency, not on the host). */
   int smoother;         /* GMG_SMOOTH_RBGS (default) or GMG_SMOOTH_CHEBYSHEV */
+  int warm_cycle;       /* preconditioner of a solve with use_x0 = 1:
+                           GMG_CYCLE_V (default, the paper's choice) or
+                           GMG_CYCLE_FMG (full multigrid cycles: fewer steps
+                           on the time loops measured; the cycle acts on the
+                           Krylov vectors, so either serves a warm start) */
 } gmg_options;
 
 void gmg_default_options(gmg_options* opt);
@@ -142,8 +147,9 @@ int gmg_update_coefficient(gmg_ctx* ctx, const double* a_dev);
 /* Change the stream later calls enqueue on. */
 int gmg_set_stream(gmg_ctx* ctx, void* hip_stream);
 
-/* FGMRES(m) (Algorithm 1), right-preconditioned by one V-cycle per step
- * from a zero guess (Sec. 3.2), on A phi = b.  Stops when the relative
+/* FGMRES(m) (Algorithm 1), right-preconditioned by one multigrid cycle per
+ * step (Sec. 3.2; opt->cold_cycle or opt->warm_cycle picks the full
+ * multigrid cycle or the V-cycle from a zero guess), on A phi = b.  Stops when the relative
  * residual ||b - A phi|| / ||b|| < tol (eq. criterion; the in-cycle least-
  * squares estimate triggers the check, the true residual decides it) or after
  * opt->max_iter Arnoldi steps.

@@ -22,6 +22,7 @@ class Options(ctypes.Structure):
         ("cold_cycle", c_int),
         ("graphs", c_int),
         ("smoother", c_int),
+        ("warm_cycle", c_int),
     ]
 
 

@@ -84,7 +84,9 @@ bool options_valid(const gmg_options* o) {
   if (o->cold_cycle != GMG_CYCLE_V && o->cold_cycle != GMG_CYCLE_FMG) return false;
   if (o->graphs != 0 && o->graphs != 1) return false;
   if (o->smoother != GMG_SMOOTH_RBGS && o->smoother != GMG_SMOOTH_CHEBYSHEV) return false;
-  if (o->smoother == GMG_SMOOTH_CHEBYSHEV && o->cold_cycle != GMG_CYCLE_V) return false;
+  if (o->warm_cycle != GMG_CYCLE_V && o->warm_cycle != GMG_CYCLE_FMG) return false;
+  if (o->smoother == GMG_SMOOTH_CHEBYSHEV && (o->cold_cycle != GMG_CYCLE_V || o->warm_cycle != GMG_CYCLE_V))
+    return false;
   return true;
 }
 
@@ -1787,6 +1789,7 @@ void gmg_default_options(gmg_options* opt) {
   opt->cold_cycle = GMG_CYCLE_FMG;
   opt->graphs = 0;
   opt->smoother = GMG_SMOOTH_RBGS;
+  opt->warm_cycle = GMG_CYCLE_V;
 }
 
 size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt) {
@@ -1909,7 +1912,7 @@ int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top,
     const Launch fl = flat_launch(c->N);
     GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
   }
-  c->fmg_now = allow_fmg && !use_x0 && c->opt.cold_cycle == GMG_CYCLE_FMG;
+  c->fmg_now = allow_fmg && (use_x0 ? c->opt.warm_cycle : c->opt.cold_cycle) == GMG_CYCLE_FMG;
   c->gmres_mode = gmres;
   c->nprec = 0;
   double* misc = scal_misc(c);

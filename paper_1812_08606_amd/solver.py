@@ -68,7 +68,8 @@ class GMGPoisson:
     finest-level smoother kernels, "half" (one per half-sweep), "fused" (one
     per symmetric sweep, float32 only) or "auto".  cold_cycle: preconditioner
     of a solve without an initial guess, "fmg" (full multigrid, the default)
-    or "vcycle"; warm-started solves use V-cycles.  graphs: replay each
+    or "vcycle"; warm_cycle: the same for a warm-started solve, "vcycle"
+    (the paper's choice, the default) or "fmg".  graphs: replay each
     preconditioner application from a captured HIP graph (same results).
     smoother: "rbgs" (red-black symmetric Gauss-Seidel, nu_pre / nu_post
     sweeps) or "chebyshev" (the degree-2 Chebyshev polynomial in the
@@ -79,7 +80,7 @@ class GMGPoisson:
     def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
                  max_iter: int = 200, nu_pre: int | None = None, nu_post: int | None = None,
                  coarse_max_cells: int = 4096, fine_sweep: str = "auto", cold_cycle: str | None = None,
-                 graphs: bool = False, smoother: str = "rbgs"):
+                 graphs: bool = False, smoother: str = "rbgs", warm_cycle: str = "vcycle"):
         self._lib = _lib.load()
         if a.dim() != 3:
             raise ValueError("a must be 3-D (nz, ny, nx)")
@@ -105,8 +106,10 @@ class GMGPoisson:
         self.smoother = smoother
         if cold_cycle not in _COLD_CYCLE:
             raise ValueError(f"cold_cycle must be one of {sorted(_COLD_CYCLE)}")
-        if cheb and cold_cycle == "fmg":
-            raise ValueError("the Chebyshev smoother runs V-cycles only (cold_cycle='vcycle')")
+        if warm_cycle not in _COLD_CYCLE:
+            raise ValueError(f"warm_cycle must be one of {sorted(_COLD_CYCLE)}")
+        if cheb and (cold_cycle == "fmg" or warm_cycle == "fmg"):
+            raise ValueError("the Chebyshev smoother runs V-cycles only (cold_cycle = warm_cycle = 'vcycle')")
         opt = _lib.Options()
         self._lib.gmg_default_options(ctypes.byref(opt))
         opt.restart, opt.max_iter = int(restart), int(max_iter)
@@ -117,6 +120,7 @@ class GMGPoisson:
         opt.cold_cycle = _COLD_CYCLE[cold_cycle]
         opt.graphs = int(bool(graphs))
         opt.smoother = _SMOOTHER[smoother]
+        opt.warm_cycle = _COLD_CYCLE[warm_cycle]
         self.options = opt
         nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
         if nbytes == 0:

@@ -36,7 +36,8 @@ def test_default_options_and_workspace(lib):
     opt = Options()
     lib.gmg_default_options(ctypes.byref(opt))
     assert (opt.restart, opt.max_iter, opt.nu_pre, opt.nu_post, opt.precision, opt.coarse_max_cells,
-            opt.fine_sweep, opt.cold_cycle, opt.graphs, opt.smoother) == (10, 200, 2, 2, 1, 4096, 0, 1, 0, 0)
+            opt.fine_sweep, opt.cold_cycle, opt.graphs, opt.smoother, opt.warm_cycle) == \
+        (10, 200, 2, 2, 1, 4096, 0, 1, 0, 0, 0)
     n64 = lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt))
     N = 64 ** 3
     # 11 float64 Krylov vectors + 10 float32 preconditioned vectors dominate
@@ -60,6 +61,13 @@ def test_default_options_and_workspace(lib):
     opt.restart = 4  # the bound estimate still gets its 11 basis slots
     assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) > 11 * N * 8
     opt.restart = 10
+    opt.warm_cycle = 1  # the Chebyshev smoother takes V-cycles only
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == 0
+    opt.smoother = 0
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) > 0
+    opt.warm_cycle = 2
+    assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == 0
+    opt.warm_cycle = 0
     opt.smoother = 2
     assert lib.gmg_workspace_bytes(64, 64, 64, ctypes.byref(opt)) == 0
     opt.smoother = 0

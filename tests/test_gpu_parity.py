@@ -271,9 +271,12 @@ def test_operator_full_size_sampled():
         assert abs(y[k, j, i] - acc) <= 1e-12 * (abs(acc) + a[k, j, i] / h2)
 
 
-def test_warm_start_time_loop_matches_oracle():
+@pytest.mark.parametrize("warm", ["vcycle", "fmg"])
+def test_warm_start_time_loop_matches_oracle(warm):
     """Per-step coefficient renewal and warm start (Sec. 2.1; Sec. 3.2): the
-    two-filament workload advected one cell per step, 64^3, FP64."""
+    two-filament workload advected one cell per step, 64^3, FP64; the
+    warm-started solves preconditioned by V-cycles (the paper's choice) or by
+    full multigrid cycles (option warm_cycle)."""
     n = 64
     prev_g = prev_o = None
     s = None
@@ -281,18 +284,19 @@ def test_warm_start_time_loop_matches_oracle():
         p = make_config(5, n=n, step=step)
         a = T(p.a)
         if s is None:
-            s = gm.GMGPoisson(a, precision="fp64")
+            s = gm.GMGPoisson(a, precision="fp64", warm_cycle=warm)
         else:
             s.update_coefficient(a)
         res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8, x0=prev_g)
-        ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=prev_o)
-        print(f"time step {step}: gpu {res.iterations}, oracle {ref.iterations}", flush=True)
+        ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=prev_o, warm=warm)
+        print(f"time step {step} ({warm}): gpu {res.iterations}, oracle {ref.iterations}", flush=True)
         assert res.converged and res.iterations == ref.iterations
         assert rel(npy(res.phi), ref.x) < 1e-10
         prev_g, prev_o = res.phi.clone(), ref.x
 
 
-def test_mixed_time_loop_two_filaments_within_residual_bound():
+@pytest.mark.parametrize("warm", ["vcycle", "fmg"])
+def test_mixed_time_loop_two_filaments_within_residual_bound(warm):
     """The two-filament time loop in mixed precision on a 96^3 copy (the
     768^3 hierarchy's shape: 96 -> 3, coarsest 27 cells): every warm-started
     step converges, and its phi differs from the float64 oracle's by no more
@@ -306,17 +310,17 @@ def test_mixed_time_loop_two_filaments_within_residual_bound():
         p = make_config(5, n=n, step=step)
         a = T(p.a)
         if s is None:
-            s = gm.GMGPoisson(a, precision="mixed")
+            s = gm.GMGPoisson(a, precision="mixed", warm_cycle=warm)
         else:
             s.update_coefficient(a)
         res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8, x0=prev_g)
-        ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=prev_o)
+        ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=prev_o, warm=warm)
         b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
         phi = npy(res.phi)
         r_gpu = np.linalg.norm(b - apply_operator(phi, p.a, p.h))
         r_ref = np.linalg.norm(b - apply_operator(ref.x, p.a, p.h))
         err = np.linalg.norm(phi - ref.x)
-        print(f"mixed time step {step}: gpu {res.iterations} steps, oracle {ref.iterations}, "
+        print(f"mixed time step {step} ({warm}): gpu {res.iterations} steps, oracle {ref.iterations}, "
               f"|dphi|/|phi| = {err / np.linalg.norm(ref.x):.2e}", flush=True)
         assert res.converged and r_gpu < 1e-8 * np.linalg.norm(b)
         assert err <= (r_gpu + r_ref) / lam_min
