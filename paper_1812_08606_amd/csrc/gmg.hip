@@ -1843,7 +1843,8 @@ int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const dou
   }
   int r = c->mixed ? write_bottom_args<float>(c) : write_bottom_args<double>(c);
   if (r == GMG_OK) r = build_hierarchy(c);
-  if (r == GMG_OK && opt->smoother == GMG_SMOOTH_CHEBYSHEV) r = c->mixed ? cheb_estimate<float>(c) : cheb_estimate<double>(c);
+  if (r == GMG_OK && opt->smoother == GMG_SMOOTH_CHEBYSHEV)
+    r = c->mixed ? cheb_estimate<float>(c) : cheb_estimate<double>(c);
   if (r != GMG_OK) {
     gmg_destroy(c);
     return r;
