@@ -722,18 +722,19 @@ _MESH_PROBLEM = None
 
 
 # ---------------------------------------------------------------- HIP graphs
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_graph_replays_equal_eager_launches(precision):
+@pytest.mark.parametrize("precision, warm", [("mixed", "vcycle"), ("fp64", "vcycle"), ("mixed", "fmg")])
+def test_graph_replays_equal_eager_launches(precision, warm):
     """Preconditioner applications replayed from captured HIP graphs give
     bit-identical solves to eager launches, over repeated replays with the
     program's own eager work and synchronisations in between: cold solves
-    (full multigrid), warm solves (V-cycles), BiCGSTAB, and after a change of
-    the coefficient buffer."""
+    (full multigrid), warm solves (V-cycles, or full multigrid cycles with
+    the warm_cycle option), BiCGSTAB, and after a change of the coefficient
+    buffer."""
     p = make_config(2, n=64)
     a = T(p.a)
     f = T(p.f)
-    sg = gm.GMGPoisson(a, precision=precision, graphs=True)
-    se = gm.GMGPoisson(a, precision=precision, graphs=False)
+    sg = gm.GMGPoisson(a, precision=precision, graphs=True, warm_cycle=warm)
+    se = gm.GMGPoisson(a, precision=precision, graphs=False, warm_cycle=warm)
     for rep in range(3):
         rg = sg.solve(f, p.phi_bot, p.phi_top, tol=1e-8)
         re_ = se.solve(f, p.phi_bot, p.phi_top, tol=1e-8)
