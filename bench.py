@@ -447,6 +447,27 @@ def main():
                 log(f"  {label} (max a = {float(coef.max()):g}, levels {len(solver.levels)})")
                 entry[label] = time_krylov_methods(torch, solver, fq, q.phi_bot, q.phi_top, args.tol)
                 del solver
+                torch.cuda.empty_cache()
+                # the solver as the benchmark step runs it: full multigrid
+                # cycles from zero with the step's smoothing
+                solver = gm.GMGPoisson(coef, precision="mixed", **step_kw)
+                phi_m = torch.empty_like(fq)
+                res = solver.solve(fq, q.phi_bot, q.phi_top, args.tol, out=phi_m)
+                times = []
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    res = solver.solve(fq, q.phi_bot, q.phi_top, args.tol, out=phi_m)
+                    e1.record()
+                    e1.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                entry[label]["fgmres_fmg_step_smoothing"] = dict(
+                    solve_ms=statistics.median(times), iterations=res.iterations, converged=res.converged,
+                    final_relres=res.final_relres, smoothing=[args.nu_pre, args.nu_post])
+                log(f"  fgmres + FMG V({args.nu_pre},{args.nu_post}) {statistics.median(times):8.2f} ms "
+                    f"{res.iterations:3d} it")
+                del solver, phi_m
+                torch.cuda.empty_cache()
             krylov_meshes[spec] = entry
             del aq, fq
             torch.cuda.empty_cache()
