@@ -18,6 +18,10 @@ paper:
 * ``adjoint``   -- gradient of a loss through the solve (derived from e18);
 * ``semi_implicit`` -- coefficient and right side of the elliptic problem of
   a semi-implicit step, and E = -grad phi (Sec. 2.1-2.2);
+* ``krylov``    -- the other Krylov methods of the comparison in Sec. 5.3
+  (GMRES, CG, FCG, CGS, BiCGSTAB) with any preconditioner;
+* ``chebyshev`` -- the paper's Chebyshev(2)+SSOR smoother (Sec. 3.2, eq.
+  qntn), its Arnoldi bound estimate and the V-cycle that uses it;
 * ``exact``     -- independent exact references (spectral DCT/DST solve for
   constant a, sparse direct solve, manufactured solution) used to pin the
   pieces above.
