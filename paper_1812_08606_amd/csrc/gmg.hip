@@ -1460,13 +1460,17 @@ int cheb_estimate(gmg_ctx* c) {
     for (int j = 0; j < CHEB_ARNOLDI; ++j) {
       double* w = kvec(c, j + 1);
       cheb_minv_a<T>(c, l, kvec(c, j), w);
-      for (int i = 0; i <= j; ++i) {
-        GMG_LAUNCH(c, "multidot", k_multidot<1>, rf, (const double*)w, n, (const double*)kvec(c, i), c->L.ldv,
-                   part);
-        finalize(c, nb, 1, 0, sd + i, nullptr, nullptr);
-        GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<1>, rf, w, n, (const double*)kvec(c, i), c->L.ldv,
-                   (const double*)(sd + i), (const double*)(sd + 12), i == j ? 1 : 0, part);
+      // modified Gram-Schmidt: h_i = (w, v_i), w -= h_i v_i in turn, each
+      // update fused with the next dot
+      GMG_LAUNCH(c, "multidot", k_multidot<1>, rf, (const double*)w, n, (const double*)kvec(c, 0), c->L.ldv, part);
+      finalize(c, nb, 1, 0, sd, nullptr, nullptr);
+      for (int i = 0; i < j; ++i) {
+        GMG_LAUNCH(c, "mgs_axpy_dot", k_mgs_axpy_dot, rf, w, n, (const double*)kvec(c, i),
+                   (const double*)kvec(c, i + 1), (const double*)(sd + i), part);
+        finalize(c, nb, 1, 0, sd + i + 1, nullptr, nullptr);
       }
+      GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<1>, rf, w, n, (const double*)kvec(c, j), c->L.ldv,
+                 (const double*)(sd + j), (const double*)(sd + 12), 1, part);
       finalize(c, nb, 1, 0, sd + 11, nullptr, nullptr);
       if (read_back(c, sd, 12) != GMG_OK) return GMG_ERR_HIP;
       for (int i = 0; i <= j; ++i) H[i * CHEB_ARNOLDI + j] = c->pinned[i];

@@ -143,4 +143,24 @@ __global__ __launch_bounds__(NTHREADS) void k_cheb_update(T* __restrict__ x, T* 
   }
 }
 
+// One modified Gram-Schmidt step of the bound estimate fused with the dot of
+// the next: w -= h u (h = *hcol), then the per-block partial sums of
+// (w, u2) (flat launch).  Each thread does exactly what the update and the
+// dot kernels would do in turn, so the result is the same to the bit.
+__global__ __launch_bounds__(NTHREADS) void k_mgs_axpy_dot(double* __restrict__ w, size_t n,
+                                                           const double* __restrict__ u,
+                                                           const double* __restrict__ u2,
+                                                           const double* __restrict__ hcol,
+                                                           double* __restrict__ partials) {
+  const double cf = *hcol;
+  double acc[1] = {0.0};
+  GMG_FLAT_LOOP(c, n) {
+    double wv = w[c];
+    wv -= cf * u[c];
+    w[c] = wv;
+    acc[0] += wv * u2[c];
+  }
+  block_store_partials<1>(acc, 1, partials, gridDim.x);
+}
+
 }  // namespace gmg
