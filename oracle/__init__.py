@@ -44,6 +44,7 @@ from .multigrid import (  # noqa: F401
     coarsen_faces,
     rbgs_half_sweep,
     restrict,
+    restrict_transpose,
     prolong,
     vcycle,
     Hierarchy,

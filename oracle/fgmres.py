@@ -114,7 +114,8 @@ def fgmres(A, b, M, x0=None, tol=1e-8, restart=10, max_iter=200,
 
 def solve_poisson(a, f, h, phi_bot=0.0, phi_top=1.0, tol=1e-8, restart=10,
                   max_iter=200, nu_pre=2, nu_post=2, precision="fp64",
-                  x0=None, coarse_max_cells=4096, cold="fmg", warm="vcycle"):
+                  x0=None, coarse_max_cells=4096, cold="fmg", warm="vcycle",
+                  restriction="mean"):
     """FGMRES(restart) with one multigrid cycle per step on A phi = f +
     lifting.
 
@@ -133,7 +134,8 @@ def solve_poisson(a, f, h, phi_bot=0.0, phi_top=1.0, tol=1e-8, restart=10,
     if cold not in ("vcycle", "fmg") or warm not in ("vcycle", "fmg"):
         raise ValueError("cold and warm must be 'vcycle' or 'fmg'")
     hier = build_hierarchy(a, h, nu_pre=nu_pre, nu_post=nu_post,
-                           coarse_max_cells=coarse_max_cells, dtype=dtype)
+                           coarse_max_cells=coarse_max_cells, dtype=dtype,
+                           restriction=restriction)
     b = rhs(f, a, h, phi_bot, phi_top)
     cycle = fmg if (cold if x0 is None else warm) == "fmg" else vcycle
 

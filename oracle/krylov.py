@@ -10,7 +10,12 @@ their steps; these are the textbook forms:
   x = x0 + M (V_m y_m) with y_m the least-squares solution (the same
   recurrences as Algorithm 1 with one fixed M; only the update differs).
 * CG, preconditioned: the standard preconditioned conjugate gradient
-  recurrence (M symmetric positive definite; the symmetric V-cycle is).
+  recurrence.  Its optimality assumes a fixed symmetric positive definite
+  M.  The default V-cycle is not symmetric (its mean-of-8 restriction is not
+  a multiple of the transpose of its trilinear prolongation; a test shows
+  M != M^T), so with it CG is only a heuristic; the V-cycle built with the
+  option ``restriction="transpose"`` (R = P^T / 8, equal pre- and
+  post-smoothing counts) is symmetric.
 * FCG: flexible CG with truncation to one previous direction (Notay's
   flexible CG): the new direction is z made A-orthogonal to the last one,
   p = z - ((z, A p_old) / (p_old, A p_old)) p_old.  With a fixed symmetric

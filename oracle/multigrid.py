@@ -23,7 +23,14 @@ operators is not available, and its smoother is replaced, see below):
   degree-2 Chebyshev polynomial wrapped around one local SSOR step
   (Sec. 3.2); red-black symmetric Gauss-Seidel is the data-parallel form of
   that SSOR step.
-* Restriction: mean of the residual over the 8 children.
+* Restriction: mean of the residual over the 8 children (default).  That is
+  not a multiple of the transpose of the trilinear prolongation, so the
+  V-cycle is not a symmetric operator; CG (Sec. 5.3) assumes one.  Option
+  ``restriction="transpose"``: R = P^T / 8, the transpose of the trilinear
+  prolongation with its ghost rules folded back (full weighting over the 64
+  fine cells around a coarse cell), which with nu_pre = nu_post makes the
+  V-cycle symmetric (the pre-smoother red-black, the post-smoother its
+  adjoint black-red, and P A_c^{-1} R = P A_c^{-1} P^T / 8).
 * Prolongation: cell-centred trilinear interpolation (per dimension 3/4 of
   the parent, 1/4 of the nearer coarse neighbour).  Coarse ghosts outside the
   domain: mirror on the x/y sides (Neumann), negated mirror through the plates
@@ -95,11 +102,13 @@ class Hierarchy:
     nu_pre: int
     nu_post: int
     dtype: type
+    restriction: str = "mean"  # "mean" (of the 8 children) or "transpose" (P^T / 8)
 
 
 def build_hierarchy(a, h, nu_pre=2, nu_post=2, coarse_max_cells=4096,
-                    dtype=np.float64):
-    """Level data for the V-cycle.
+                    dtype=np.float64, restriction="mean"):
+    """Level data for the V-cycle.  ``restriction``: "mean" (of the 8
+    children) or "transpose" (P^T / 8).
 
     The finest level's faces are formed from the coefficient rounded to
     ``dtype`` (float32 for the mixed-precision preconditioner), in ``dtype``
@@ -121,8 +130,10 @@ def build_hierarchy(a, h, nu_pre=2, nu_post=2, coarse_max_cells=4096,
         levels.append(Level(shape=shp, h=h_l, faces=F, diag=diagonal(F, h_l)))
     A_c = assemble_dense(levels[-1].faces, levels[-1].h)
     factor = sla.cho_factor(A_c, lower=True)
+    if restriction not in ("mean", "transpose"):
+        raise ValueError("restriction must be 'mean' or 'transpose'")
     return Hierarchy(levels=levels, coarse_factor=factor, nu_pre=nu_pre,
-                     nu_post=nu_post, dtype=dtype)
+                     nu_post=nu_post, dtype=dtype, restriction=restriction)
 
 
 def colour_mask(shape_zyx, colour):
@@ -147,6 +158,35 @@ def restrict(r):
     """Coarse value = mean of the 8 children."""
     nz, ny, nx = r.shape
     return r.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(1, 3, 5))
+
+
+def _interp_axis_transpose(f, axis, dirichlet):
+    """Transpose of ``_interp_axis``: coarse[I] = 3/4 (f[2I] + f[2I+1]) +
+    1/4 (f[2I-1] + f[2I+2]); the ghost terms of the first and last fine
+    cells fold back onto coarse cells 0 and N-1 with the ghost's sign."""
+    f = np.moveaxis(f, axis, 0)
+    sign = -1.0 if dirichlet else 1.0
+    even, odd = f[0::2], f[1::2]
+    c = 0.75 * (even + odd)
+    c[1:] += 0.25 * odd[:-1]  # f[2I-1] weights c[I] by 1/4
+    c[:-1] += 0.25 * even[1:]  # f[2I+2] weights c[I] by 1/4
+    c[0] += 0.25 * sign * even[0]  # ghost below cell 0 is sign * c[0]
+    c[-1] += 0.25 * sign * odd[-1]  # ghost above cell N-1 is sign * c[N-1]
+    return np.moveaxis(c, 0, axis)
+
+
+def restrict_transpose(r):
+    """R = P^T / 8: the transpose of ``prolong`` (one 1-D transpose per
+    axis), scaled so that R keeps a constant interior field."""
+    c = _interp_axis_transpose(r, 0, dirichlet=True)
+    c = _interp_axis_transpose(c, 1, dirichlet=False)
+    c = _interp_axis_transpose(c, 2, dirichlet=False)
+    return c / 8.0
+
+
+def restriction_of(hier):
+    """The hierarchy's restriction operator."""
+    return restrict_transpose if hier.restriction == "transpose" else restrict
 
 
 def _interp_axis(c, axis, dirichlet):
@@ -190,7 +230,7 @@ def vcycle(hier: Hierarchy, b, level=0, x0=None):
         rbgs_half_sweep(x, b, lev, 0)
         rbgs_half_sweep(x, b, lev, 1)
     r = b - apply_faces(x, lev.faces, lev.h)
-    e = vcycle(hier, restrict(r), level + 1)
+    e = vcycle(hier, restriction_of(hier)(r), level + 1)
     x += prolong(e)
     for _ in range(hier.nu_post):
         rbgs_half_sweep(x, b, lev, 1)
@@ -204,8 +244,8 @@ def fmg(hier: Hierarchy, b):
     first time step).  The paper names the method without its steps; this is
     the textbook cycle:
 
-    1. right sides of every level: b_0 = b, b_{l+1} = R b_l (mean of the 8
-       children, the V-cycle's restriction);
+    1. right sides of every level: b_0 = b, b_{l+1} = R b_l (the V-cycle's
+       restriction);
     2. the coarsest level solved directly;
     3. level by level towards the finest, the coarser solution interpolated
        (the V-cycle's trilinear prolongation) is the initial guess of one
@@ -213,7 +253,7 @@ def fmg(hier: Hierarchy, b):
     nl = len(hier.levels)
     bs = [np.asarray(b, dtype=hier.dtype)]
     for _ in range(nl - 1):
-        bs.append(restrict(bs[-1]))
+        bs.append(restriction_of(hier)(bs[-1]))
     x = coarse_solve(hier, bs[-1])
     for level in range(nl - 2, -1, -1):
         x = vcycle(hier, bs[level], level, x0=prolong(x))

@@ -91,6 +91,42 @@ def test_vcycle_preconditioner_is_not_symmetric():
     assert np.linalg.norm(Mm - Mm.T) > 1e-3 * np.linalg.norm(Mm)
 
 
+def _symmetric_vcycle(n=8, seed=51):
+    """The _problem of size n with the V-cycle of R = P^T / 8, nu = 2 / 2."""
+    rng = np.random.default_rng(seed)
+    a = np.exp(rng.uniform(-1.5, 1.5, (n, n, n)))
+    hier = build_hierarchy(a, (1 / n,) * 3, restriction="transpose")
+
+    def M(v):
+        return vcycle(hier, v.reshape(a.shape)).ravel()
+    return M
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_cg_with_the_symmetric_vcycle_minimises_the_energy_error(k):
+    """With the symmetric V-cycle (R = P^T / 8) CG is CG again: x_k
+    minimises ||x - x*||_A over the Krylov space of M A from M r0 (dense
+    Galerkin solve on an explicit basis), and FCG gives the same iterates."""
+    A, _, b, Ad = _problem()
+    M = _symmetric_vcycle()
+    Q = _krylov_basis(lambda v: M(A(v)), M(b), k)
+    c = np.linalg.solve(Q.T @ Ad @ Q, Q.T @ b)
+    res = cg(A, b, M, tol=0.0, max_iter=k)
+    np.testing.assert_allclose(res.x, Q @ c, rtol=1e-8, atol=1e-10 * np.abs(Q @ c).max())
+    res_f = cg(A, b, M, tol=0.0, max_iter=k, flexible=True)
+    np.testing.assert_allclose(res_f.x, res.x, rtol=1e-8, atol=1e-10 * np.abs(res.x).max())
+
+
+def test_symmetric_vcycle_preconditioner_is_symmetric():
+    """The counterpart of the test above: with R = P^T / 8 the V-cycle's
+    matrix is symmetric (to rounding)."""
+    A, _, b, Ad = _problem(n=4)
+    M = _symmetric_vcycle(n=4)
+    n = Ad.shape[0]
+    Mm = np.stack([M(e) for e in np.eye(n)], axis=1)
+    assert np.linalg.norm(Mm - Mm.T) <= 1e-13 * np.linalg.norm(Mm)
+
+
 @pytest.mark.parametrize("k", [2, 5])
 def test_gmres_minimises_the_residual_and_equals_fgmres(k):
     """Right-preconditioned GMRES: x_k = M u with u minimising ||b - A M u||
