@@ -51,11 +51,17 @@ if ROOT not in sys.path:
 
 METRIC = "converged cells/s per 1e-8 Poisson solve + HBM GB/s, FP64 vs mixed, 512^3"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-# what the counted kernel (the finest-level fused sweep) is built from: its
-# device code and the host function that sets its launch shape
+# what the counted kernels (the finest-level sweeps) are built from: their
+# device code and the host functions that set their launch shapes
 KERNEL_SOURCES = ["gmg_common.hpp", "gmg_kernels.hpp", "gmg_fine.hpp"]
-LAUNCH_SOURCE = ("gmg.hip", r"Launch sym_launch\(.*?\n}\n")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sym_fine_f32_filament512.md")
+LAUNCH_SOURCES = {
+    "sym_fine_f32": ("gmg.hip", r"Launch sym_launch\(.*?\n}\n"),
+    "gs_fine_f64": ("gmg.hip", r"void gs_split\(.*?\n}\n"),
+}
+TRAFFIC_FILES = {
+    "sym_fine_f32": os.path.join(ROOT, "profiles", "traffic_sym_fine_f32_filament512.md"),
+    "gs_fine_f64": os.path.join(ROOT, "profiles", "traffic_gs_fine_f64_filament512.md"),
+}
 
 
 def log(*a):
@@ -198,29 +204,100 @@ def nv_sequence(iterations, restart):
     return [it % restart + 1 for it in range(iterations)]
 
 
-def kernel_source_hash():
+def kernel_source_hash(kernel="sym_fine_f32"):
+    """Hash of the device sources and of the kernel's launch function."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1812_08606_amd", "csrc")
     for f in KERNEL_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    text = open(os.path.join(csrc, LAUNCH_SOURCE[0])).read()
-    m = re.search(LAUNCH_SOURCE[1], text, flags=re.S)
+    fname, pattern = LAUNCH_SOURCES[kernel]
+    text = open(os.path.join(csrc, fname)).read()
+    m = re.search(pattern, text, flags=re.S)
     h.update((m.group(0) if m else text).encode())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the finest-level symmetric sweep from the
+def measured_traffic(kernel="sym_fine_f32"):
+    """HBM bytes per launch of a finest-level sweep kernel at 512^3 from the
     committed counter summary, if it was taken on the current kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(kernel)
+    if path is None or not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     m_h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    if not (m_b and m_h) or m_h.group(1) != kernel_source_hash():
+    if not (m_b and m_h) or m_h.group(1) != kernel_source_hash(kernel):
         return None
     return float(m_b.group(1))
+
+
+def kernel_table(prof, prof_steps, its_prof, s, N, restart=10):
+    """Per-kernel rows (name, ms per step, launches per step, average ms per
+    launch, algorithmic GB/s, algorithmic bytes per launch) from an event
+    pass, sorted by time, and the algorithmic bytes of the whole pass.  s:
+    bytes of the V-cycle precision (also of the stored z_j)."""
+    nvs = [nv for its in its_prof for nv in nv_sequence(its, restart)]
+    table = []
+    total_bytes = 0.0
+    for name, (tot_ms, cnt) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        base, level = split_name(name)
+        tb = None
+        bpl = None
+        if level is not None and level >= 0:
+            bpc = bytes_per_cell(base, level, s)
+            if bpc is not None:
+                bpl = bpc * N / 8 ** level
+                tb = bpl * cnt
+        elif name.startswith("op_multidot") or name == "axpy_norm":
+            tb = sum(outer_bytes(name, nv, s) for nv in nvs) * N
+        elif name.startswith("update"):
+            b_upd = 0.0
+            for its in its_prof:
+                left = its
+                while left > 0:
+                    k = min(left, restart)
+                    b_upd += outer_bytes(name, k, s)
+                    left -= k
+            tb = b_upd * N
+        elif outer_bytes(name, 0, s) is not None:
+            tb = outer_bytes(name, 0, s) * N * cnt
+        gbs = tb / (tot_ms * 1e-3) / 1e9 if tb else None
+        if tb:
+            total_bytes += tb
+        table.append((name, tot_ms / prof_steps, cnt / prof_steps, tot_ms / cnt, gbs, bpl))
+    return table, total_bytes
+
+
+def roofline_of(table, ms_per_step, traffic_ok):
+    """Roofline entry of the dominant kernel with a per-launch byte model
+    (the first such row of the time-sorted table): algorithmic bytes per
+    launch over the event-timed average launch; measured traffic from the
+    committed counter summary when traffic_ok and the sources match."""
+    dom = next((t for t in table if t[5] is not None), None)
+    if dom is None:
+        return None
+    name, ms_s, cnt, avg_ms, gbs, bpl = dom
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    return {
+        "bound": "hbm",
+        "kernel": name,
+        "achieved": round(achieved, 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "traffic": measured_traffic(name) if traffic_ok else None,
+        "avg_launch_ms": round(avg_ms, 5),
+        "bytes_per_launch": bpl,
+        "share_of_step": round(ms_s / ms_per_step, 3),
+    }
+
+
+def kernel_rows(table, limit=12):
+    """The table's first rows for the JSON line."""
+    return [{"kernel": name, "ms_per_step": round(ms_s, 4), "launches_per_step": round(cnt, 2),
+             "avg_ms": round(avg, 5), "GBps": round(gbs) if gbs else None}
+            for name, ms_s, cnt, avg, gbs, _ in table[:limit]]
 
 
 def time_krylov_methods(torch, solver, f, pb, pt, tol):
@@ -531,63 +608,26 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written by one device copy")
         del src, dst
 
-    # -- per-kernel table and roofline from the event pass ------------------
-    s = 4
-    restart = 10
-    ps = mixed["prof_steps"]
-    # iterations of the solves inside the profiled pass (c3: the same every step)
-    its_prof = [r.iterations for r in mixed["prof_solves"]] if c5 else its_mixed * ps
-    nvs = [nv for its in its_prof for nv in nv_sequence(its, restart)]
-    table = []
-    total_bytes = 0.0
-    for name, (tot_ms, cnt) in sorted(mixed["prof"].items(), key=lambda kv: -kv[1][0]):
-        base, level = split_name(name)
-        tb = None
-        bpl = None
-        if level is not None and level >= 0:
-            bpc = bytes_per_cell(base, level, s)
-            if bpc is not None:
-                bpl = bpc * N / 8 ** level
-                tb = bpl * cnt
-        elif name.startswith("op_multidot") or name == "axpy_norm":
-            tb = sum(outer_bytes(name, nv, s) for nv in nvs) * N
-        elif name.startswith("update"):
-            b_upd = 0.0
-            for its in its_prof:
-                left = its
-                while left > 0:
-                    k = min(left, restart)
-                    b_upd += outer_bytes(name, k, s)
-                    left -= k
-            tb = b_upd * N
-        elif outer_bytes(name, 0, s) is not None:
-            tb = outer_bytes(name, 0, s) * N * cnt
-        gbs = tb / (tot_ms * 1e-3) / 1e9 if tb else None
-        if tb:
-            total_bytes += tb
-        table.append((name, tot_ms / ps, cnt / ps, tot_ms / cnt, gbs, bpl))
-    if table:
-        log(f"{'kernel':34s} {'ms/step':>9s} {'launch':>7s} {'avg ms':>9s} {'GB/s':>8s}")
-        for name, ms_s, cnt, avg, gbs, _ in table:
-            log(f"{name:34s} {ms_s:9.3f} {cnt:7.1f} {avg:9.4f} {gbs if gbs else float('nan'):8.0f}")
-    roofline = None
-    dom = next((t for t in table if t[5] is not None), None)
-    if dom is not None:
-        name, ms_s, cnt, avg_ms, gbs, bpl = dom
-        achieved = bpl / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic() if (name == "sym_fine_f32" and n == 512 and args.workload == "c3") else None
-        roofline = {
-            "bound": "hbm",
-            "kernel": name,
-            "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic,
-            "avg_launch_ms": round(avg_ms, 5),
-            "bytes_per_launch": bpl,
-            "share_of_step": round(ms_s / mixed["ms_per_step"], 3),
-        }
+    # -- per-kernel tables and rooflines from the event passes -------------
+    def tables(run_out, s_bytes, its):
+        ps = run_out["prof_steps"]
+        # iterations of the solves inside the profiled pass (c3: the same every step)
+        its_prof = [r.iterations for r in run_out["prof_solves"]] if c5 else its * ps
+        table, total = kernel_table(run_out["prof"], ps, its_prof, s_bytes, N)
+        if table:
+            log(f"{'kernel':34s} {'ms/step':>9s} {'launch':>7s} {'avg ms':>9s} {'GB/s':>8s}")
+            for name, ms_s, cnt, avg, gbs, _ in table:
+                log(f"{name:34s} {ms_s:9.3f} {cnt:7.1f} {avg:9.4f} {gbs if gbs else float('nan'):8.0f}")
+        traffic_ok = n == 512 and args.workload == "c3"
+        roof = roofline_of(table, run_out["ms_per_step"], traffic_ok)
+        model = (total / ps) / (run_out["ms_per_step"] * 1e-3) / 1e9 if total else None
+        return table, roof, model
+
+    table, roofline, model_gbs = tables(mixed, 4, its_mixed)
+    fp64_table = fp64_roofline = fp64_model_gbs = None
+    if fp64 is not None:
+        log("fp64 kernels:")
+        fp64_table, fp64_roofline, fp64_model_gbs = tables(fp64, 8, [r.iterations for r in fp64["solves"]])
 
     # -- CPU oracle baseline ------------------------------------------------
     cpu = None
@@ -646,8 +686,9 @@ def main():
         "setup_ms": mixed.get("setup_ms"),
         "setup_and_solve_cells_per_s": (N / ((mixed["setup_ms"] + mixed["solve_ms"]) * 1e-3)
                                         if mixed.get("setup_ms") and mixed["solve_ms"] else None),
-        "model_gbs": (total_bytes / ps) / (mixed["ms_per_step"] * 1e-3) / 1e9 if total_bytes else None,
+        "model_gbs": model_gbs,
         "roofline": roofline,
+        "kernels": kernel_rows(table),
         "cpu_baseline": cpu,
         "krylov_methods": krylov,
         "krylov_meshes": krylov_meshes,
@@ -662,6 +703,9 @@ def main():
             "solve_cells_per_s": N / (fp64["solve_ms"] * 1e-3) if fp64["solve_ms"] else None,
             "iterations": [r.iterations for r in fp64["solves"]],
             "final_relres": [r.final_relres for r in fp64["solves"]],
+            "model_gbs": fp64_model_gbs,
+            "roofline": fp64_roofline,
+            "kernels": kernel_rows(fp64_table) if fp64_table else None,
         }
         line["mixed_speedup_vs_fp64"] = fp64["ms_per_step"] / mixed["ms_per_step"]
         if "phi" in mixed and "phi" in fp64:  # forward solutions of the two precisions

@@ -89,6 +89,19 @@ enum { GMG_CYCLE_V = 0, GMG_CYCLE_FMG = 1 };
  * GMG_CYCLE_V. */
 enum { GMG_SMOOTH_RBGS = 0, GMG_SMOOTH_CHEBYSHEV = 1 };
 
+/* Restriction of the V-cycle (Sec. 3.2; the paper's figure of the transfer
+ * operators is missing, so both are readings).  GMG_RESTRICT_MEAN: the
+ * residual averaged over the 8 children of a coarse cell (default).
+ * GMG_RESTRICT_TRANSPOSE: R = P^T / 8, the transpose of the trilinear
+ * prolongation with its ghost rules folded back (full weighting over the
+ * 4 x 4 x 4 fine cells around a coarse cell); with nu_pre = nu_post the
+ * V-cycle is then a symmetric positive definite operator, which the
+ * conjugate gradient method of the comparison in Sec. 5.3 assumes.  The
+ * transpose restriction runs as a residual pass and a restriction pass on
+ * every level (no one-workgroup bottom kernel) and needs cold_cycle =
+ * warm_cycle = GMG_CYCLE_V and the red-black smoother. */
+enum { GMG_RESTRICT_MEAN = 0, GMG_RESTRICT_TRANSPOSE = 1 };
+
 /* Solver options.  gmg_default_options fills the defaults given below. */
 typedef struct gmg_options {
   int restart;          /* Krylov dimension m of FGMRES(m), 1..32 (default 10)   */
@@ -121,6 +134,7 @@ typedef struct gmg_options {
                            GMG_CYCLE_FMG (full multigrid cycles: fewer steps
                            on the time loops measured; the cycle acts on the
                            Krylov vectors, so either serves a warm start) */
+  int restriction;      /* GMG_RESTRICT_MEAN (default) or GMG_RESTRICT_TRANSPOSE */
 } gmg_options;
 
 void gmg_default_options(gmg_options* opt);

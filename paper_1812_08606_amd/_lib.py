@@ -23,6 +23,7 @@ class Options(ctypes.Structure):
         ("graphs", c_int),
         ("smoother", c_int),
         ("warm_cycle", c_int),
+        ("restriction", c_int),
     ]
 
 

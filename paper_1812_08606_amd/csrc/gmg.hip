@@ -67,6 +67,7 @@ struct Layout {
   std::vector<LevelOffsets> lv;
   size_t V, Z, a32, b0, xs, partials, scal, cinv, bargs, total;
   size_t cr0, cd0;  // Chebyshev smoother, finest level: float64 natural residual, T colour-split direction
+  size_t rr;        // transpose restriction: residual of the level being restricted (finest: float64)
   size_t tsize;  // bytes of the V-cycle precision
   size_t ldv;    // elements between consecutive Krylov vectors (v_i and z_i)
   size_t hn;     // elements of one colour array of a colour-split finest-level field
@@ -86,6 +87,10 @@ bool options_valid(const gmg_options* o) {
   if (o->smoother != GMG_SMOOTH_RBGS && o->smoother != GMG_SMOOTH_CHEBYSHEV) return false;
   if (o->warm_cycle != GMG_CYCLE_V && o->warm_cycle != GMG_CYCLE_FMG) return false;
   if (o->smoother == GMG_SMOOTH_CHEBYSHEV && (o->cold_cycle != GMG_CYCLE_V || o->warm_cycle != GMG_CYCLE_V))
+    return false;
+  if (o->restriction != GMG_RESTRICT_MEAN && o->restriction != GMG_RESTRICT_TRANSPOSE) return false;
+  if (o->restriction == GMG_RESTRICT_TRANSPOSE &&
+      (o->smoother != GMG_SMOOTH_RBGS || o->cold_cycle != GMG_CYCLE_V || o->warm_cycle != GMG_CYCLE_V))
     return false;
   return true;
 }
@@ -154,6 +159,7 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
       lo.cd = take(n * L->tsize);
     }
   }
+  L->rr = o->restriction == GMG_RESTRICT_TRANSPOSE && nl > 1 ? take(N * 8) : 0;
   L->cr0 = cheb && nl > 1 ? take(N * 8) : 0;
   L->cd0 = cheb && nl > 1 ? take(L->ldv * L->tsize) : 0;
   L->partials = take((size_t)MAXV * MAX_RED_BLOCKS * 8);
@@ -595,12 +601,47 @@ void smooth_post_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co
   }
 }
 
+// Launch of k_restrict_fw: one thread per coarse cell of fine level s.
+Launch fw_launch(const LevelShape& s) {
+  return Launch{dim3((s.nx / 2 + BX - 1) / BX, (s.ny / 2 + BY - 1) / BY, s.nz / 2), dim3(BX, BY, 1), 0};
+}
+
 template <typename T>
 void resid_restrict_face(gmg_ctx* c, int l, const T* x, const T* b, const FaceCoef<T>& co, T* bc) {
   const LevelShape& s = c->L.shapes[l];
+  if (c->opt.restriction == GMG_RESTRICT_TRANSPOSE) {
+    // r = b - A x into the residual scratch, then bc = P^T r / 8
+    T* r = wsp<T>(c, c->L.rr);
+    const Launch cl = cell_launch(s.nx, s.ny, s.nz, 4096, 4);
+    GMG_LAUNCH(c, kname("resid", l, sizeof(T)), k_resid_face<T>, cl, x, b, co, s.geom(), r, cl.kc);
+    GMG_LAUNCH(c, kname("restrict_fw", l, sizeof(T)), (k_restrict_fw<T, T>), fw_launch(s), (const T*)r, bc,
+               s.geom());
+    return;
+  }
   const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2);
   GMG_LAUNCH(c, kname("resid_restrict", l, sizeof(T)), k_resid_restrict_face<T>, pl, x, b, co, s.geom(), bc,
              pl.kc);
+}
+
+// Finest level (colour-split X and B, right side s u): residual and
+// restriction into the level-1 right side.  Transpose restriction: r = s u -
+// A x in float64 (natural layout), then P^T r / 8.
+template <typename T>
+void resid_restrict_fine(gmg_ctx* c, const T* X, const T* B, const double* u, const double* bscale, const T* a) {
+  const LevelShape& s = c->L.shapes[0];
+  T* bc = wsp<T>(c, c->L.lv[1].b);
+  if (c->opt.restriction == GMG_RESTRICT_TRANSPOSE) {
+    double* r = wsp<double>(c, c->L.rr);
+    const Launch rl = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
+    GMG_LAUNCH(c, kname("resid", 0, sizeof(T)), k_resid_split<T>, rl, X, u, bscale, a, s.geom(), c->L.hn, r,
+               rl.kc);
+    GMG_LAUNCH(c, kname("restrict_fw", 0, sizeof(T)), (k_restrict_fw<double, T>), fw_launch(s), (const double*)r,
+               bc, s.geom());
+    return;
+  }
+  const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+  GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), k_resid_restrict_split<T>, l, X, B, a, s.geom(), c->L.hn,
+             bc, l.kc);
 }
 
 // Levels >= 1 that are not the coarsest (every dimension even): x += P xc.
@@ -815,11 +856,7 @@ void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X, 
     if (it > 0 || from_x) gs_split<T, false>(c, X, B, nullptr, nullptr, a, 0);
     gs_split<T, false>(c, X, B, nullptr, nullptr, a, 1);
   }
-  {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
-    GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), k_resid_restrict_split<T>, l, (const T*)X, (const T*)B, a,
-               s.geom(), hn, wsp<T>(c, c->L.lv[1].b), l.kc);
-  }
+  resid_restrict_fine<T>(c, X, B, u, bscale, a);
   vcycle_coarse<T>(c, 1);
   {
     const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
@@ -947,11 +984,7 @@ void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z, bo
     sym_split<T, true>(c, nullptr, buf(1), B, u, bscale, a, 0);
   for (int p = 2; p <= npre; ++p) sym_split<T, false>(c, buf(p - 1), buf(p), B, nullptr, nullptr, a, 0);
   T* X = buf(npre);
-  {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
-    GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), k_resid_restrict_split<T>, l, (const T*)X, (const T*)B, a,
-               s.geom(), hn, wsp<T>(c, c->L.lv[1].b), l.kc);
-  }
+  resid_restrict_fine<T>(c, X, B, u, bscale, a);
   vcycle_coarse<T>(c, 1);
   {
     const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
@@ -1613,6 +1646,15 @@ int true_residual(gmg_ctx* c, const double* f, const double* x, double pb, doubl
   return GMG_OK;
 }
 
+// b = 0: phi = 0 (whatever the initial guess), relative residual 0, as in
+// fgmres_solve.
+int zero_solution(gmg_ctx* c, double* x, KrylovOut& out) {
+  GMG_LAUNCH(c, "fill", k_fill<double>, flat_launch(c->N), x, 0.0, c->N);
+  note(c, hipStreamSynchronize(c->stream));
+  out.relres = 0.0;
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
 // Preconditioned CG, or FCG (new direction A-orthogonalised against the last
 // one) when flexible.  Slots: r 0, q 1, z 2, p 3.
 int krylov_cg(gmg_ctx* c, const double* f, double pb, double pt, double tol, double* x, int max_iter, bool flexible,
@@ -1626,10 +1668,7 @@ int krylov_cg(gmg_ctx* c, const double* f, double pb, double pt, double tol, dou
     double bnorm, rn;
     int st = true_residual(c, f, x, pb, pt, bnorm, rn);
     if (st != GMG_OK) return st;
-    if (bnorm == 0.0) {
-      out.relres = 0.0;
-      return GMG_OK;
-    }
+    if (bnorm == 0.0) return zero_solution(c, x, out);
     out.relres = rn / bnorm;
     if (rn < tol * bnorm) return GMG_OK;
     if (out.it >= max_iter) return GMG_NOT_CONVERGED;
@@ -1673,10 +1712,7 @@ int krylov_cgs(gmg_ctx* c, const double* f, double pb, double pt, double tol, do
     double bnorm, rn;
     int st = true_residual(c, f, x, pb, pt, bnorm, rn);
     if (st != GMG_OK) return st;
-    if (bnorm == 0.0) {
-      out.relres = 0.0;
-      return GMG_OK;
-    }
+    if (bnorm == 0.0) return zero_solution(c, x, out);
     out.relres = rn / bnorm;
     if (rn < tol * bnorm) return GMG_OK;
     if (out.it >= max_iter) return GMG_NOT_CONVERGED;
@@ -1722,10 +1758,7 @@ int krylov_bicgstab(gmg_ctx* c, const double* f, double pb, double pt, double to
     double bnorm, rn;
     int st = true_residual(c, f, x, pb, pt, bnorm, rn);
     if (st != GMG_OK) return st;
-    if (bnorm == 0.0) {
-      out.relres = 0.0;
-      return GMG_OK;
-    }
+    if (bnorm == 0.0) return zero_solution(c, x, out);
     out.relres = rn / bnorm;
     if (rn < tol * bnorm) return GMG_OK;
     if (out.it >= max_iter) return GMG_NOT_CONVERGED;
@@ -1794,6 +1827,7 @@ void gmg_default_options(gmg_options* opt) {
   opt->graphs = 0;
   opt->smoother = GMG_SMOOTH_RBGS;
   opt->warm_cycle = GMG_CYCLE_V;
+  opt->restriction = GMG_RESTRICT_MEAN;
 }
 
 size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt) {
@@ -1802,20 +1836,14 @@ size_t gmg_workspace_bytes(int nx, int ny, int nz, const gmg_options* opt) {
   return L.total;
 }
 
-int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const double* a_dev,
-              const gmg_options* opt, void* workspace_dev, size_t workspace_bytes, void* hip_stream,
-              gmg_ctx** out) {
-  if (!out || !a_dev || !opt) return GMG_ERR_ARG;
-  *out = nullptr;
-  if (!(hx > 0) || !(hy > 0) || !(hz > 0) || !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz))
-    return GMG_ERR_ARG;
-  Layout L;
-  const int st = make_layout(nx, ny, nz, hx, hy, hz, opt, &L);
-  if (st != GMG_OK) return st;
-  if (!workspace_dev || workspace_bytes < L.total || ((uintptr_t)workspace_dev % ALIGN) != 0)
-    return GMG_ERR_WORKSPACE;
-  gmg_ctx* c = new (std::nothrow) gmg_ctx();
-  if (!c) return GMG_ERR_ARG;
+namespace {
+
+// Context c (constructed by the caller) for the grid, coefficient and
+// layout L, on the workspace ws (checked by the caller) and the host buffer
+// host_buf of MAX_RESTART + 8 doubles for read-backs; builds the hierarchy.
+int init_ctx(gmg_ctx* c, int nx, int ny, int nz, double hx, double hy, double hz, const double* a_dev,
+             const gmg_options* opt, void* ws, size_t ws_bytes, void* hip_stream, const Layout& L,
+             double* host_buf) {
   c->nx = nx;
   c->ny = ny;
   c->nz = nz;
@@ -1825,30 +1853,61 @@ int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const dou
   c->opt = *opt;
   c->a = a_dev;
   c->stream = (hipStream_t)hip_stream;
-  c->ws = (char*)workspace_dev;
-  c->ws_bytes = workspace_bytes;
+  c->ws = (char*)ws;
+  c->ws_bytes = ws_bytes;
   c->L = L;
   c->N = L.shapes[0].n();
   c->mixed = opt->precision == GMG_MIXED;
   c->nc = (int)L.shapes.back().n();
-  // the Chebyshev smoother runs every level through the per-level kernels
-  c->bottom_from = opt->smoother == GMG_SMOOTH_CHEBYSHEV ? -1 : bottom_level(L);
+  // the Chebyshev smoother and the transpose restriction run every level
+  // through the per-level kernels
+  c->bottom_from =
+      (opt->smoother == GMG_SMOOTH_CHEBYSHEV || opt->restriction == GMG_RESTRICT_TRANSPOSE) ? -1 : bottom_level(L);
   c->err = hipSuccess;
-  c->pinned = nullptr;
+  c->pinned = host_buf;
   const int m = opt->restart;
   c->R.assign((size_t)m * m, 0.0);
   c->cs.assign(m, 0.0);
   c->sn.assign(m, 0.0);
   c->g.assign(m + 1, 0.0);
   c->y.assign(m, 0.0);
-  if (hipHostMalloc((void**)&c->pinned, (size_t)(MAX_RESTART + 8) * 8, hipHostMallocDefault) != hipSuccess) {
-    delete c;
-    return GMG_ERR_HIP;
-  }
   int r = c->mixed ? write_bottom_args<float>(c) : write_bottom_args<double>(c);
   if (r == GMG_OK) r = build_hierarchy(c);
   if (r == GMG_OK && opt->smoother == GMG_SMOOTH_CHEBYSHEV)
     r = c->mixed ? cheb_estimate<float>(c) : cheb_estimate<double>(c);
+  return r;
+}
+
+int check_setup_args(double hx, double hy, double hz, const double* a_dev, const gmg_options* opt) {
+  if (!a_dev || !opt) return GMG_ERR_ARG;
+  if (!(hx > 0) || !(hy > 0) || !(hz > 0) || !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz))
+    return GMG_ERR_ARG;
+  return GMG_OK;
+}
+
+}  // namespace
+
+int gmg_setup(int nx, int ny, int nz, double hx, double hy, double hz, const double* a_dev,
+              const gmg_options* opt, void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+              gmg_ctx** out) {
+  if (!out) return GMG_ERR_ARG;
+  *out = nullptr;
+  int st = check_setup_args(hx, hy, hz, a_dev, opt);
+  if (st != GMG_OK) return st;
+  Layout L;
+  st = make_layout(nx, ny, nz, hx, hy, hz, opt, &L);
+  if (st != GMG_OK) return st;
+  if (!workspace_dev || workspace_bytes < L.total || ((uintptr_t)workspace_dev % ALIGN) != 0)
+    return GMG_ERR_WORKSPACE;
+  gmg_ctx* c = new (std::nothrow) gmg_ctx();
+  if (!c) return GMG_ERR_ARG;
+  double* pinned = nullptr;
+  if (hipHostMalloc((void**)&pinned, (size_t)(MAX_RESTART + 8) * 8, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return GMG_ERR_HIP;
+  }
+  const int r = init_ctx(c, nx, ny, nz, hx, hy, hz, a_dev, opt, workspace_dev, workspace_bytes, hip_stream, L,
+                         pinned);
   if (r != GMG_OK) {
     gmg_destroy(c);
     return r;

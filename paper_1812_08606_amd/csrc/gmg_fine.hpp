@@ -649,6 +649,63 @@ __global__ __launch_bounds__(NTHREADS) void k_restrict_mean(const T* __restrict_
   bc[((size_t)K * NY + J) * NX + I] = sum * T(0.125);
 }
 
+// Weights of the 1-D transpose of the cell-centred linear interpolation for
+// coarse index I of n: fine cells 2I-1 .. 2I+2 weigh 1/4, 3/4, 3/4, 1/4; a
+// fine cell outside the grid gets weight 0 (its address is clamped) and the
+// ghost it stands for folds onto the end cell with sign sg (+1 mirror, -1
+// negated mirror).
+__device__ __forceinline__ void fw_weights(int I, int n, double sg, int idx[4], double w[4]) {
+  const int nf = 2 * n;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int f = 2 * I - 1 + t;
+    idx[t] = min(max(f, 0), nf - 1);
+    w[t] = (t == 0 || t == 3) ? 0.25 : 0.75;
+  }
+  if (I == 0) {
+    w[0] = 0.0;
+    w[1] += 0.25 * sg;
+  }
+  if (I == n - 1) {
+    w[3] = 0.0;
+    w[2] += 0.25 * sg;
+  }
+}
+
+// bc = P^T r / 8: the transpose of the trilinear prolongation (negated
+// mirror through the plates, mirror on the sides) applied to the fine
+// residual r (natural layout, fine geometry g, every dimension even),
+// i.e. full weighting over the 4 x 4 x 4 fine cells around each coarse cell.
+// One thread per coarse cell; sums in float64.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(NTHREADS) void k_restrict_fw(const TI* __restrict__ r, TO* __restrict__ bc, Geom g) {
+  const int NX = g.nx >> 1, NY = g.ny >> 1, NZ = g.nz >> 1;
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int J = blockIdx.y * BY + threadIdx.y;
+  const int K = blockIdx.z;
+  if (I >= NX || J >= NY) return;
+  int ix[4], iy[4], iz[4];
+  double wx[4], wy[4], wz[4];
+  fw_weights(I, NX, 1.0, ix, wx);
+  fw_weights(J, NY, 1.0, iy, wy);
+  fw_weights(K, NZ, -1.0, iz, wz);
+  double sum = 0.0;
+#pragma unroll
+  for (int tk = 0; tk < 4; ++tk) {
+    double sy = 0.0;
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      const size_t row = ((size_t)iz[tk] * g.ny + iy[tj]) * g.nx;
+      double sx = 0.0;
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) sx += wx[ti] * (double)r[row + ix[ti]];
+      sy += wy[tj] * sx;
+    }
+    sum += wz[tk] * sy;
+  }
+  bc[((size_t)K * NY + J) * NX + I] = (TO)(0.125 * sum);
+}
+
 // w = A z (z colour-split, promoted to float64) and the dots (w, u_v),
 // v < NV.  Lane tx owns pair m of row j (rows strided by the grid's y extent)
 // and marches its z-chunk keeping z and a of the pair on planes k-1, k, k+1

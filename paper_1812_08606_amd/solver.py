@@ -17,6 +17,7 @@ _PRECISION = {"fp64": FP64, "mixed": MIXED}
 _FINE_SWEEP = {"auto": 0, "half": 1, "fused": 2}
 _COLD_CYCLE = {"vcycle": 0, "fmg": 1}
 _SMOOTHER = {"rbgs": 0, "chebyshev": 1}
+_RESTRICTION = {"mean": 0, "transpose": 1}
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -75,12 +76,16 @@ class GMGPoisson:
     sweeps) or "chebyshev" (the degree-2 Chebyshev polynomial in the
     SSOR-preconditioned level operator, Sec. 3.2 eq. qntn, nu_pre / nu_post
     applications, default 1 each; V-cycles only, so cold_cycle defaults to
+    "vcycle").  restriction: "mean" (of the 8 children, the default) or
+    "transpose" (R = P^T / 8: with nu_pre = nu_post a symmetric V-cycle, for
+    the conjugate gradient method; V-cycles only, so cold_cycle defaults to
     "vcycle")."""
 
     def __init__(self, a: torch.Tensor, h=None, precision: str = "mixed", restart: int = 10,
                  max_iter: int = 200, nu_pre: int | None = None, nu_post: int | None = None,
                  coarse_max_cells: int = 4096, fine_sweep: str = "auto", cold_cycle: str | None = None,
-                 graphs: bool = False, smoother: str = "rbgs", warm_cycle: str = "vcycle"):
+                 graphs: bool = False, smoother: str = "rbgs", warm_cycle: str = "vcycle",
+                 restriction: str = "mean"):
         self._lib = _lib.load()
         if a.dim() != 3:
             raise ValueError("a must be 3-D (nz, ny, nx)")
@@ -97,8 +102,11 @@ class GMGPoisson:
         if smoother not in _SMOOTHER:
             raise ValueError(f"smoother must be one of {sorted(_SMOOTHER)}")
         cheb = smoother == "chebyshev"
+        if restriction not in _RESTRICTION:
+            raise ValueError(f"restriction must be one of {sorted(_RESTRICTION)}")
+        vonly = cheb or restriction == "transpose"
         if cold_cycle is None:
-            cold_cycle = "vcycle" if cheb else "fmg"
+            cold_cycle = "vcycle" if vonly else "fmg"
         if nu_pre is None:
             nu_pre = 1 if cheb else 2
         if nu_post is None:
@@ -110,6 +118,9 @@ class GMGPoisson:
             raise ValueError(f"warm_cycle must be one of {sorted(_COLD_CYCLE)}")
         if cheb and (cold_cycle == "fmg" or warm_cycle == "fmg"):
             raise ValueError("the Chebyshev smoother runs V-cycles only (cold_cycle = warm_cycle = 'vcycle')")
+        if restriction == "transpose" and (cheb or cold_cycle == "fmg" or warm_cycle == "fmg"):
+            raise ValueError("the transpose restriction runs red-black V-cycles only "
+                             "(smoother = 'rbgs', cold_cycle = warm_cycle = 'vcycle')")
         opt = _lib.Options()
         self._lib.gmg_default_options(ctypes.byref(opt))
         opt.restart, opt.max_iter = int(restart), int(max_iter)
@@ -121,6 +132,7 @@ class GMGPoisson:
         opt.graphs = int(bool(graphs))
         opt.smoother = _SMOOTHER[smoother]
         opt.warm_cycle = _COLD_CYCLE[warm_cycle]
+        opt.restriction = _RESTRICTION[restriction]
         self.options = opt
         nbytes = self._lib.gmg_workspace_bytes(nx, ny, nz, ctypes.byref(opt))
         if nbytes == 0:

@@ -58,16 +58,40 @@ def test_nv_sequence_restarts():
     assert bench.nv_sequence(12, 5) == [1, 2, 3, 4, 5, 1, 2, 3, 4, 5, 1, 2]
 
 
-def test_traffic_only_for_matching_sources(monkeypatch, tmp_path):
+@pytest.mark.parametrize("kernel", ["sym_fine_f32", "gs_fine_f64"])
+def test_traffic_only_for_matching_sources(monkeypatch, tmp_path, kernel):
     f = tmp_path / "traffic.md"
     f.write_text("traffic_bytes_per_launch: 2141258775\nkernel_source_sha256_16: 0123456789abcdef\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0123456789abcdef")
-    assert bench.measured_traffic() == 2141258775.0
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "fedcba9876543210")
-    assert bench.measured_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
-    assert bench.measured_traffic() is None
+    monkeypatch.setitem(bench.TRAFFIC_FILES, kernel, str(f))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda k: "0123456789abcdef")
+    assert bench.measured_traffic(kernel) == 2141258775.0
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda k: "fedcba9876543210")
+    assert bench.measured_traffic(kernel) is None
+    monkeypatch.setitem(bench.TRAFFIC_FILES, kernel, str(tmp_path / "missing.md"))
+    assert bench.measured_traffic(kernel) is None
+    assert bench.measured_traffic("resid_restrict_fine_f32") is None
+
+
+def test_kernel_sources_hash_per_kernel():
+    """Each counted kernel hashes the device sources plus its own launch
+    function, so a change to one launch shape voids only that summary."""
+    h32, h64 = bench.kernel_source_hash("sym_fine_f32"), bench.kernel_source_hash("gs_fine_f64")
+    assert len(h32) == len(h64) == 16 and h32 != h64
+
+
+def test_kernel_table_and_roofline():
+    """Byte models per kernel from an event pass: the fused sweep's 14 B/cell
+    per launch at 512^3 (mixed) over its average launch, and the float64
+    half-sweep's 20 B/cell."""
+    N = 512 ** 3
+    prof = {"sym_fine_f32": (6.9, 10), "op_multidot_zf32": (1.0, 5), "gs_fine_f64": (3.6, 5)}
+    table, total = bench.kernel_table(prof, 1, [5], 4, N)
+    roof = bench.roofline_of(table, 100.0, False)
+    assert roof["kernel"] == "sym_fine_f32" and roof["bytes_per_launch"] == 14 * N
+    assert abs(roof["achieved"] - 14 * N / 0.69e-3 / 1e9) < 0.1 and roof["traffic"] is None
+    table64, _ = bench.kernel_table({"gs_fine_f64": (3.6, 5)}, 1, [5], 8, N)
+    assert bench.roofline_of(table64, 100.0, False)["bytes_per_launch"] == 20 * N
+    assert total > 0
 
 
 def test_more_than_one_gpu_is_refused(monkeypatch):

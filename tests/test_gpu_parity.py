@@ -344,6 +344,18 @@ def test_zero_right_side_gives_zero():
     assert res.status == 0 and res.iterations == 0 and not res.phi.abs().max().item()
 
 
+@pytest.mark.parametrize("method", ["fgmres", "gmres", "cg", "fcg", "cgs", "bicgstab"])
+def test_zero_right_side_gives_zero_every_krylov_method(method):
+    """b = 0 with a nonzero initial guess: every method of the comparison
+    returns phi = 0 and relative residual 0, as fgmres_solve does."""
+    p = make_config(1, n=16)
+    s = gm.GMGPoisson(T(p.a), precision="fp64")
+    x0 = torch.ones(p.a.shape, dtype=torch.float64, device=DEV)
+    res, napp = s.krylov_solve(torch.zeros_like(x0), 0.0, 0.0, method=method, x0=x0)
+    assert res.status == 0 and res.iterations == 0 and napp == 0
+    assert res.final_relres == 0.0 and not res.phi.abs().max().item()
+
+
 def test_max_iter_exhausted():
     p = make_config(3, n=16)
     s = gm.GMGPoisson(T(p.a), precision="fp64", max_iter=2)
@@ -719,6 +731,90 @@ def test_cg_stagnates_on_table_mesh_and_says_so():
 
 
 _MESH_PROBLEM = None
+
+
+# ---------------------------------------------------------------- symmetric V-cycle
+SYM_SHAPES = [(48, 40, 36), (70, 12, 8), (64, 64, 64), (6, 4, 10), (130, 8, 4), (64, 32, 48)]
+
+
+@pytest.mark.parametrize("shape", SYM_SHAPES)
+def test_transpose_restriction_vcycle_matches_oracle(shape):
+    """The V-cycle with R = P^T / 8 (restriction "transpose": residual pass,
+    full-weighting pass, every level through per-level kernels) against the
+    oracle's, float64 and float32, with half-sweep and fused finest-level
+    sweeps."""
+    print(f"vcycle transpose restriction {shape}", flush=True)
+    a, f, h = _rand_problem(shape, 41)
+    hier = build_hierarchy(a, h, restriction="transpose")
+    s64 = gm.GMGPoisson(T(a), h=h, precision="fp64", restriction="transpose")
+    assert s64.levels == [tuple(l.shape) for l in hier.levels]
+    z = npy(s64.vcycle(T(f)))
+    ref = vcycle(hier, f)
+    assert rel(z, ref) < 1e-12
+    np.testing.assert_allclose(z, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+    ref32 = vcycle(build_hierarchy(a, h, dtype=np.float32, restriction="transpose"),
+                   f.astype(np.float32)).astype(np.float64)
+    for sweep in ("half", "fused"):
+        s32 = gm.GMGPoisson(T(a), h=h, precision="mixed", restriction="transpose", fine_sweep=sweep)
+        assert rel(npy(s32.vcycle(T(f))), ref32) < 2e-5
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_transpose_restriction_vcycle_is_symmetric(n):
+    """(u, M v) = (M u, v) for the float64 V-cycle with R = P^T / 8 and
+    nu_pre = nu_post, on the filament workload (max(a) = 1e4); with the mean
+    restriction the two differ."""
+    p = make_config(3, n=n)
+    rng = np.random.default_rng(42)
+    u, v = T(rng.standard_normal(p.a.shape)), T(rng.standard_normal(p.a.shape))
+    for restriction, symmetric in (("transpose", True), ("mean", False)):
+        s = gm.GMGPoisson(T(p.a), precision="fp64", restriction=restriction, cold_cycle="vcycle")
+        uMv = float((u * s.vcycle(v)).sum())
+        Muv = float((s.vcycle(u) * v).sum())
+        d = abs(uMv - Muv) / abs(uMv)
+        print(f"{restriction} {n}^3: |(u,Mv) - (Mu,v)| / |(u,Mv)| = {d:.2e}", flush=True)
+        assert (d < 1e-12) if symmetric else (d > 1e-6)
+
+
+@pytest.mark.parametrize("method", ["cg", "fcg"])
+@pytest.mark.parametrize("case", [("cfg", 3, 32, 6), ("mesh", 32, 32, 40, False, 6)])
+def test_cg_with_symmetric_vcycle_fixed_steps_match_oracle(method, case):
+    """CG and FCG preconditioned by the symmetric V-cycle, float64, after a
+    fixed number of iterations, against the oracle."""
+    from oracle.krylov import cg
+    k = case[-1]
+    p = _krylov_case(case[:-1])
+    s = gm.GMGPoisson(T(p.a), precision="fp64", max_iter=k, restriction="transpose")
+    res, napp = s.krylov_solve(T(p.f), p.phi_bot, p.phi_top, method=method, tol=0.0)
+    hier = build_hierarchy(p.a, p.h, restriction="transpose")
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    ref = cg(lambda x: apply_operator(x, p.a, p.h), b, lambda v: vcycle(hier, v), tol=0.0, max_iter=k,
+             flexible=method == "fcg")
+    assert res.iterations == ref.iterations == k and napp == ref.precond
+    assert rel(npy(res.phi), ref.x) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_cg_converges_on_table_mesh_with_symmetric_vcycle(precision):
+    """The 256 x 256 x 320 comparison mesh with max(a) = 1e4 (Sec. 5.3, Table
+    t1): preconditioned by the symmetric V-cycle, CG reaches the 1e-8
+    relative residual (checked with the oracle's operator), in at most 1.5
+    times the iterations FGMRES takes with the same V-cycle."""
+    global _MESH_PROBLEM
+    if _MESH_PROBLEM is None:
+        _MESH_PROBLEM = config_streamer_mesh(256, 256, 320)
+    p = _MESH_PROBLEM
+    s = gm.GMGPoisson(T(p.a), precision=precision, restriction="transpose")
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    its = {}
+    for method in ("fgmres", "cg"):
+        res, napp = s.krylov_solve(T(p.f), p.phi_bot, p.phi_top, method=method, tol=1e-8)
+        r = np.linalg.norm(b - apply_operator(npy(res.phi), p.a, p.h)) / np.linalg.norm(b)
+        print(f"symmetric V-cycle, {precision}, {method}: {res.iterations} iterations, true relres {r:.2e}",
+              flush=True)
+        assert res.converged and r < 1e-8 and abs(r - res.final_relres) <= 1e-3 * r
+        its[method] = res.iterations
+    assert its["cg"] <= 1.5 * its["fgmres"]
 
 
 # ---------------------------------------------------------------- HIP graphs
