@@ -1,5 +1,6 @@
-"""Elliptic side of one semi-implicit step.  Test infrastructure only: the
-product path never imports or calls this module.
+"""Elliptic side of one semi-implicit step, and the time step around it.
+Test infrastructure only: the product path never imports or calls this
+module.
 
 The coefficient and right side of the variable-coefficient elliptic problem
 that each time step solves (Sec. 2.1, eq. semi2 for the predictor of the
@@ -22,8 +23,30 @@ Readings of points the paper leaves open:
 * Ghost cells of phi for E: the same as the operator's (``oracle.operator``):
   mirrored through the plates, ``2 phi_b - phi_c``, equal to the boundary
   cell on the sides.
+
+``time_step`` sequences one step of either scheme around the elliptic solve
+(Sec. 2.1).  The transport operator -- drift, diffusion and source of the
+density equations, discretised in the paper by MUSCL fluxes with the Koren
+limiter -- is not part of the solver: the caller passes it as a function
+``transport(n_e, n_p, E) -> (L_e, L_p)`` giving the time derivatives of the
+two densities for a frozen field E = (E_x, E_y, E_z, |E|), so that each
+density equation of eqs. e1, e2 and semi-implicit reads
+``(n_new - n_base) / dt = L(n_eval, E)``.
+
+* Second order (eqs. e1, e2, semi2): the elliptic problem with
+  tau_eff = tau/2 from the densities at t_n gives phi^{n+1/2} and E^{n+1/2};
+  the predictor n^{n+1/2} = n^n + tau/2 L(n^n, E^{n+1/2}) (eq. e1); the
+  corrector n^{n+1} = n^n + tau L(n^{n+1/2}, E^{n+1/2}) (eq. e2), reusing
+  E^{n+1/2}: one elliptic solve per step.
+* First order (eqs. semi-implicit, e15): tau_eff = tau gives phi^{n+1},
+  E^{n+1}; n^{n+1} = n^n + tau L(n^n, E^{n+1}).
+
+The solve is warm-started from the previous step's phi when one is given
+(Sec. 3.2), cold (full multigrid cycles) otherwise.
 """
 from __future__ import annotations
+
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -71,3 +94,44 @@ def electric_field(phi, h, phi_bot, phi_top):
     ey = -(py[:, 2:, :] - py[:, :-2, :]) / (2.0 * hy)
     ez = -(pz[2:] - pz[:-2]) / (2.0 * hz)
     return ex, ey, ez, np.sqrt(ex * ex + ey * ey + ez * ez)
+
+
+@dataclass
+class StepParams:
+    eps0_over_e: float
+    mu_e: float
+    mu_p: float
+    De: tuple  # (D_x, D_y, D_z)
+
+
+@dataclass
+class StepResult:
+    n_e: np.ndarray
+    n_p: np.ndarray
+    phi: np.ndarray  # phi^{n+1/2} (second order) or phi^{n+1} (first order)
+    E: tuple  # the field of phi: (E_x, E_y, E_z, |E|)
+    iterations: int
+
+
+def time_step(n_e, n_p, h, prm: StepParams, tau, transport, phi_bot, phi_top, phi_prev=None,
+              scheme="second", tol=1e-8, **solve_kw):
+    """One time step of the second-order scheme (eqs. e1, e2 with the
+    elliptic problem semi2) or of the first-order one (eqs. semi-implicit,
+    e15).  solve_kw go to ``oracle.fgmres.solve_poisson``."""
+    from .fgmres import solve_poisson
+
+    if scheme not in ("second", "first"):
+        raise ValueError("scheme must be 'second' or 'first'")
+    n_e = np.asarray(n_e, dtype=np.float64)
+    n_p = np.asarray(n_p, dtype=np.float64)
+    tau_eff = 0.5 * tau if scheme == "second" else tau
+    a = coefficient(n_e, n_p, prm.eps0_over_e, tau_eff, prm.mu_e, prm.mu_p)
+    f = right_side(n_e, n_p, h, tau_eff, prm.De)
+    sol = solve_poisson(a, f, h, phi_bot, phi_top, tol=tol, x0=phi_prev, **solve_kw)
+    E = electric_field(sol.x, h, phi_bot, phi_top)
+    le, lp = transport(n_e, n_p, E)
+    if scheme == "first":
+        return StepResult(n_e + tau * le, n_p + tau * lp, sol.x, E, sol.iterations)
+    ne_h, np_h = n_e + 0.5 * tau * le, n_p + 0.5 * tau * lp  # predictor (eq. e1)
+    le, lp = transport(ne_h, np_h, E)
+    return StepResult(n_e + tau * le, n_p + tau * lp, sol.x, E, sol.iterations)  # corrector (eq. e2)
