@@ -300,30 +300,44 @@ def kernel_rows(table, limit=12):
             for name, ms_s, cnt, avg, gbs, _ in table[:limit]]
 
 
-def time_krylov_methods(torch, solver, f, pb, pt, tol):
+KRYLOV_METHODS = ("fgmres", "gmres", "cg", "fcg", "cgs", "bicgstab")
+
+
+def time_krylov_methods(torch, make_solver, f, pb, pt, tol):
     """Each Krylov method of the comparison from no initial guess, one
     V-cycle per preconditioner application: one untimed solve, then the
-    median of 3 event-timed solves."""
+    median of 3 event-timed solves; then FGMRES and CG preconditioned by the
+    symmetric V-cycle (restriction R = P^T / 8; "_symmetric").
+    make_solver(restriction) builds the solver (one at a time on the GPU)."""
     phi = torch.empty_like(f)
     out = {}
-    for method in ("fgmres", "gmres", "cg", "fcg", "cgs", "bicgstab"):
-        res, napp = solver.krylov_solve(f, pb, pt, method=method, tol=tol, out=phi)
-        times = []
-        for _ in range(3):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            res, napp = solver.krylov_solve(f, pb, pt, method=method, tol=tol, out=phi)
-            e1.record()
-            e1.synchronize()
-            times.append(e0.elapsed_time(e1))
-        out[method] = dict(solve_ms=statistics.median(times), iterations=res.iterations,
-                           preconditioner_applications=napp, converged=res.converged,
-                           final_relres=res.final_relres)
+    for restriction, methods, suffix in (("mean", KRYLOV_METHODS, ""),
+                                         ("transpose", ("fgmres", "cg"), "_symmetric")):
+        slv = make_solver(restriction)
+        for method in methods:
+            out[method + suffix] = _time_method(torch, slv, method, f, pb, pt, tol, phi)
+        del slv
+        torch.cuda.empty_cache()
     for method, d in out.items():
         d["ratio_to_fgmres"] = d["solve_ms"] / out["fgmres"]["solve_ms"]
-        log(f"  {method:9s} {d['solve_ms']:8.2f} ms  {d['iterations']:3d} it  "
+        log(f"  {method:18s} {d['solve_ms']:8.2f} ms  {d['iterations']:3d} it  "
             f"{d['preconditioner_applications']:3d} M  ratio {d['ratio_to_fgmres']:.3f}")
     return out
+
+
+def _time_method(torch, slv, method, f, pb, pt, tol, phi):
+    """One untimed solve, then the median of 3 event-timed solves."""
+    res, napp = slv.krylov_solve(f, pb, pt, method=method, tol=tol, out=phi)
+    times = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        res, napp = slv.krylov_solve(f, pb, pt, method=method, tol=tol, out=phi)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return dict(solve_ms=statistics.median(times), iterations=res.iterations, preconditioner_applications=napp,
+                converged=res.converged, final_relres=res.final_relres)
 
 
 def main():
@@ -498,9 +512,8 @@ def main():
     krylov = None
     if not c5 and not args.no_krylov:
         log("Krylov method comparison (mixed, V-cycle preconditioner) ...")
-        solver = gm.GMGPoisson(a0, precision="mixed")
-        krylov = time_krylov_methods(torch, solver, f0, p.phi_bot, p.phi_top, args.tol)
-        del solver
+        krylov = time_krylov_methods(torch, lambda r: gm.GMGPoisson(a0, precision="mixed", restriction=r), f0,
+                                     p.phi_bot, p.phi_top, args.tol)
         torch.cuda.empty_cache()
 
     # -- the same comparison on the meshes of Table t1 / t2 (unit cube,
@@ -520,10 +533,10 @@ def main():
             log(f"Krylov comparison on the {spec} mesh (inputs in {time.perf_counter() - t_gen:.1f}s) ...")
             entry = {"cells": mx * my * mz, "h": list(q.h)}
             for label, coef in (("variable_a", aq), ("constant_a", torch.ones_like(aq))):
-                solver = gm.GMGPoisson(coef, precision="mixed")
-                log(f"  {label} (max a = {float(coef.max()):g}, levels {len(solver.levels)})")
-                entry[label] = time_krylov_methods(torch, solver, fq, q.phi_bot, q.phi_top, args.tol)
-                del solver
+                log(f"  {label} (max a = {float(coef.max()):g})")
+                entry[label] = time_krylov_methods(
+                    torch, lambda r, coef=coef: gm.GMGPoisson(coef, precision="mixed", restriction=r), fq,
+                    q.phi_bot, q.phi_top, args.tol)
                 torch.cuda.empty_cache()
                 # the solver as the benchmark step runs it: full multigrid
                 # cycles from zero with the step's smoothing

@@ -273,6 +273,36 @@ int gmg_assemble_elliptic(gmg_ctx* ctx, const double* ne_dev, const double* np_d
 int gmg_electric_field(gmg_ctx* ctx, const double* phi_dev, double phi_bot, double phi_top, double* ex_dev,
                        double* ey_dev, double* ez_dev, double* emag_dev);
 
+/* The elliptic half of one time step of the semi-implicit schemes (Sec.
+ * 2.1): from the densities at t_n, the coefficient and right side
+ * (gmg_assemble_elliptic, into the caller's a_dev and f_dev: prm->tau_eff =
+ * tau/2 for eq. semi2 of the second-order scheme, tau for eq. e15 of the
+ * first-order one), the coefficient renewal (gmg_update_coefficient with
+ * a_dev, which the context keeps), the solve (fgmres_solve, warm-started
+ * from phi_dev when use_x0 != 0, Sec. 3.2) and the field E = -grad phi and
+ * |E| of the solution (gmg_electric_field), in one call with one wait at
+ * the end.  ne, np, a, f, phi, ex, ey, ez, emag: nz*ny*nx float64 on the
+ * context's grid, a and f distinct from ne, np; phi_dev holds phi^{n+1/2}
+ * (second order) or phi^{n+1} (first order) on return.  iterations and
+ * final_true_relres (may be NULL) as in fgmres_solve.  Returns the solve's
+ * status (GMG_OK or GMG_NOT_CONVERGED) or an error of any of the steps. */
+int gmg_elliptic_step(gmg_ctx* ctx, const double* ne_dev, const double* np_dev, const gmg_step_params* prm,
+                      double phi_bot, double phi_top, double tol, double* a_dev, double* f_dev, double* phi_dev,
+                      int use_x0, double* ex_dev, double* ey_dev, double* ez_dev, double* emag_dev, int* iterations,
+                      double* final_true_relres);
+
+/* The density half of the time step (Sec. 2.1): n_out = n + dt L for both
+ * species, L the time derivatives the caller's transport operator (drift,
+ * diffusion and source of the density equations, which this library does not
+ * discretise) gives for the field of gmg_elliptic_step: dt = tau/2 with L at
+ * t_n for the predictor of eq. e1, dt = tau with L at t_n + tau/2 for the
+ * corrector of eq. e2 (both from n at t_n), dt = tau with L at t_n for the
+ * first-order scheme.  All arrays nz*ny*nx float64; the outputs may be the
+ * inputs ne_dev, np_dev.  Errors: GMG_ERR_ARG for null pointers or a
+ * non-finite dt. */
+int gmg_density_update(gmg_ctx* ctx, const double* ne_dev, const double* np_dev, const double* le_dev,
+                       const double* lp_dev, double dt, double* ne_out, double* np_out);
+
 /* Hierarchy description: number of levels and, for level l < cap, its
  * (nx, ny, nz) in shapes[3l..3l+2]. */
 int gmg_get_levels(gmg_ctx* ctx, int* nlevels, int* shapes, int cap);

@@ -15,6 +15,8 @@ from .solver import (  # noqa: E402,F401
     MIXED,
     GMGError,
     GMGPoisson,
+    SemiImplicitStepper,
     SolveResult,
+    StepInfo,
     poisson_solve,
 )

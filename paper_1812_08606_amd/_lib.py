@@ -57,6 +57,11 @@ SIGNATURES = {
                                       c_void_p]),
     "gmg_electric_field": (c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p,
                                    c_void_p]),
+    "gmg_elliptic_step": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(StepParams), c_double, c_double,
+                                  c_double, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, P_int, P_double]),
+    "gmg_density_update": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                                   c_void_p]),
     "gmg_get_levels": (c_int, [c_void_p, P_int, P_int, c_int]),
     "gmg_chebyshev_estimates": (c_int, [c_void_p, P_double, c_int, P_int]),
     "gmg_ritz_max_real": (c_int, [P_double, c_int, c_int, P_double]),

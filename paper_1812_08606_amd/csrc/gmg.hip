@@ -2165,9 +2165,12 @@ int gmg_face_flux_grad(gmg_ctx* c, const double* phi_dev, const double* lam_dev,
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }
 
-int gmg_assemble_elliptic(gmg_ctx* c, const double* ne_dev, const double* np_dev, const gmg_step_params* prm,
-                          double* a_dev, double* f_dev) {
-  if (!valid_ctx(c) || !ne_dev || !np_dev || !prm || !a_dev || !f_dev) return GMG_ERR_ARG;
+namespace {
+
+// The assembly and field kernels of a time step, enqueued without waiting.
+int launch_assemble(gmg_ctx* c, const double* ne_dev, const double* np_dev, const gmg_step_params* prm,
+                    double* a_dev, double* f_dev) {
+  if (!ne_dev || !np_dev || !prm || !a_dev || !f_dev) return GMG_ERR_ARG;
   const double vals[] = {prm->eps0_over_e, prm->tau_eff, prm->mu_e, prm->mu_p, prm->De[0], prm->De[1], prm->De[2]};
   for (double v : vals)
     if (!std::isfinite(v)) return GMG_ERR_ARG;
@@ -2176,20 +2179,67 @@ int gmg_assemble_elliptic(gmg_ctx* c, const double* ne_dev, const double* np_dev
                    prm->De[0] / (c->hx * c->hx), prm->De[1] / (c->hy * c->hy), prm->De[2] / (c->hz * c->hz)};
   const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
   GMG_LAUNCH(c, "assemble_step", k_assemble_step, l, ne_dev, np_dev, c->L.shapes[0].geom(), p, a_dev, f_dev, l.kc);
-  note(c, hipStreamSynchronize(c->stream));
-  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+  return GMG_OK;
 }
 
-int gmg_electric_field(gmg_ctx* c, const double* phi_dev, double phi_bot, double phi_top, double* ex_dev,
-                       double* ey_dev, double* ez_dev, double* emag_dev) {
-  if (!valid_ctx(c) || !phi_dev || !ex_dev || !ey_dev || !ez_dev || !emag_dev) return GMG_ERR_ARG;
+int launch_field(gmg_ctx* c, const double* phi_dev, double phi_bot, double phi_top, double* ex_dev, double* ey_dev,
+                 double* ez_dev, double* emag_dev) {
+  if (!phi_dev || !ex_dev || !ey_dev || !ez_dev || !emag_dev) return GMG_ERR_ARG;
   if (!std::isfinite(phi_bot) || !std::isfinite(phi_top)) return GMG_ERR_ARG;
   if (c->ny > 65535 * BY) return GMG_ERR_SHAPE;
   const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
   GMG_LAUNCH(c, "electric_field", k_electric_field, l, phi_dev, c->L.shapes[0].geom(), c->hx, c->hy, c->hz,
              phi_bot, phi_top, ex_dev, ey_dev, ez_dev, emag_dev, l.kc);
+  return GMG_OK;
+}
+
+int wait_stream(gmg_ctx* c) {
   note(c, hipStreamSynchronize(c->stream));
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
+}  // namespace
+
+int gmg_assemble_elliptic(gmg_ctx* c, const double* ne_dev, const double* np_dev, const gmg_step_params* prm,
+                          double* a_dev, double* f_dev) {
+  if (!valid_ctx(c)) return GMG_ERR_ARG;
+  const int st = launch_assemble(c, ne_dev, np_dev, prm, a_dev, f_dev);
+  return st != GMG_OK ? st : wait_stream(c);
+}
+
+int gmg_electric_field(gmg_ctx* c, const double* phi_dev, double phi_bot, double phi_top, double* ex_dev,
+                       double* ey_dev, double* ez_dev, double* emag_dev) {
+  if (!valid_ctx(c)) return GMG_ERR_ARG;
+  const int st = launch_field(c, phi_dev, phi_bot, phi_top, ex_dev, ey_dev, ez_dev, emag_dev);
+  return st != GMG_OK ? st : wait_stream(c);
+}
+
+int gmg_elliptic_step(gmg_ctx* c, const double* ne_dev, const double* np_dev, const gmg_step_params* prm,
+                      double phi_bot, double phi_top, double tol, double* a_dev, double* f_dev, double* phi_dev,
+                      int use_x0, double* ex_dev, double* ey_dev, double* ez_dev, double* emag_dev, int* iterations,
+                      double* final_true_relres) {
+  if (!valid_ctx(c) || !phi_dev || !ex_dev || !ey_dev || !ez_dev || !emag_dev) return GMG_ERR_ARG;
+  if (!std::isfinite(phi_bot) || !std::isfinite(phi_top) || !(tol >= 0.0)) return GMG_ERR_ARG;
+  int st = launch_assemble(c, ne_dev, np_dev, prm, a_dev, f_dev);
+  if (st != GMG_OK) return st;
+  st = gmg_update_coefficient(c, a_dev);
+  if (st != GMG_OK) return st;
+  const int solved = fgmres_solve(c, f_dev, phi_bot, phi_top, tol, phi_dev, use_x0, iterations, nullptr, 0, nullptr,
+                                  final_true_relres);
+  if (solved < 0) return solved;
+  st = launch_field(c, phi_dev, phi_bot, phi_top, ex_dev, ey_dev, ez_dev, emag_dev);
+  if (st != GMG_OK) return st;
+  st = wait_stream(c);
+  return st != GMG_OK ? st : solved;
+}
+
+int gmg_density_update(gmg_ctx* c, const double* ne_dev, const double* np_dev, const double* le_dev,
+                       const double* lp_dev, double dt, double* ne_out, double* np_out) {
+  if (!valid_ctx(c) || !ne_dev || !np_dev || !le_dev || !lp_dev || !ne_out || !np_out) return GMG_ERR_ARG;
+  if (!std::isfinite(dt)) return GMG_ERR_ARG;
+  GMG_LAUNCH(c, "density_update", k_density_update, flat_launch(c->N), ne_dev, np_dev, le_dev, lp_dev, dt, ne_out,
+             np_out, c->N);
+  return wait_stream(c);
 }
 
 int gmg_get_levels(gmg_ctx* c, int* nlevels, int* shapes, int cap) {

@@ -77,4 +77,19 @@ __global__ __launch_bounds__(NTHREADS) void k_electric_field(const double* __res
   }
 }
 
+// Density update of the time step: n_out = n + dt L for both species (the
+// predictor of eq. e1 with dt = tau/2, the corrector of eq. e2 and the
+// first-order step with dt = tau).  Outputs may be the inputs n (same index
+// read, then written), so no restrict qualifiers.
+__global__ __launch_bounds__(NTHREADS) void k_density_update(const double* ne, const double* np, const double* le,
+                                                             const double* lp, double dt, double* oe, double* op,
+                                                             size_t n) {
+  GMG_FLAT_LOOP(c, n) {
+    const double e = ne[c] + dt * le[c];
+    const double p = np[c] + dt * lp[c];
+    oe[c] = e;
+    op[c] = p;
+  }
+}
+
 }  // namespace gmg

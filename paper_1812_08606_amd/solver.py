@@ -349,6 +349,102 @@ class GMGPoisson:
         return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(n.value, cap))}
 
 
+@dataclass
+class StepInfo:
+    """Result of SemiImplicitStepper.step: the new densities, the potential
+    and field of the step's elliptic solve (phi^{n+1/2}, E^{n+1/2} in the
+    second-order scheme; phi^{n+1}, E^{n+1} in the first-order one), and the
+    solve's status, iterations and final relative residual."""
+    n_e: torch.Tensor
+    n_p: torch.Tensor
+    phi: torch.Tensor
+    E: tuple
+    status: int
+    iterations: int
+    final_relres: float
+
+
+class SemiImplicitStepper:
+    """Time steps of the paper's semi-implicit schemes around the GPU solve
+    (Sec. 2.1).  scheme "second" (eqs. e1, e2, semi2): the elliptic problem
+    with tau/2 from the densities at t_n gives phi^{n+1/2}, E^{n+1/2} (one
+    solve per step, warm-started from the previous step's phi); the
+    predictor n^{n+1/2} = n^n + tau/2 L(n^n) and the corrector n^{n+1} = n^n
+    + tau L(n^{n+1/2}), both with E^{n+1/2}.  scheme "first" (eqs.
+    semi-implicit, e15): tau in the elliptic problem, n^{n+1} = n^n + tau
+    L(n^n) with E^{n+1}.
+
+    ``transport(n_e, n_p, E) -> (L_e, L_p)`` is the caller's: the time
+    derivatives of the densities (drift, diffusion, source; the paper's MUSCL
+    fluxes are not part of this library) for the frozen field E = (E_x, E_y,
+    E_z, |E|), as float64 tensors of the grid's shape.  The assembly, solve,
+    field and density updates run in the HIP library (gmg_elliptic_step,
+    gmg_density_update).
+
+    a: a template float64 (nz, ny, nx) tensor (only its shape and device are
+    used); h, precision and the other keyword arguments go to GMGPoisson."""
+
+    def __init__(self, a: torch.Tensor, phi_bot: float, phi_top: float, eps0_over_e: float, mu_e: float,
+                 mu_p: float, De=(0.0, 0.0, 0.0), scheme: str = "second", tol: float = 1e-8, h=None, **solver_kw):
+        if scheme not in ("second", "first"):
+            raise ValueError("scheme must be 'second' or 'first'")
+        self.solver = GMGPoisson(torch.ones_like(a), h=h, **solver_kw)
+        self._lib = self.solver._lib
+        self.shape, self.device = self.solver.shape, self.solver.device
+        self.scheme, self.tol = scheme, float(tol)
+        self.bc = (float(phi_bot), float(phi_top))
+        self.coef = (float(eps0_over_e), float(mu_e), float(mu_p), tuple(float(v) for v in De))
+        self.a = torch.empty_like(a)
+        self.f = torch.empty_like(a)
+        self.phi = torch.zeros_like(a)
+        self.E = tuple(torch.empty_like(a) for _ in range(4))
+        self._warm = False
+
+    def _update(self, n_e, n_p, l_e, l_p, dt, out_e, out_p):
+        for t, nm in ((n_e, "n_e"), (n_p, "n_p"), (l_e, "L_e"), (l_p, "L_p"), (out_e, "out n_e"),
+                      (out_p, "out n_p")):
+            _check_field(t, self.shape, nm, self.device)
+        with torch.cuda.device(self.device):
+            self.solver._sync_stream()
+            st = self._lib.gmg_density_update(self.solver._ctx, _ptr(n_e), _ptr(n_p), _ptr(l_e), _ptr(l_p),
+                                              float(dt), _ptr(out_e), _ptr(out_p))
+        if st != OK:
+            raise GMGError(st, "gmg_density_update")
+
+    def step(self, n_e: torch.Tensor, n_p: torch.Tensor, tau: float, transport, out=None) -> StepInfo:
+        """One time step from (n_e, n_p) at t_n; the new densities go to
+        ``out`` = (n_e, n_p) when given (may be the inputs), else to new
+        tensors.  phi and E of the result are the stepper's buffers,
+        overwritten by the next step."""
+        _check_field(n_e, self.shape, "n_e", self.device)
+        _check_field(n_p, self.shape, "n_p", self.device)
+        eps, mu_e, mu_p, De = self.coef
+        tau_eff = 0.5 * tau if self.scheme == "second" else tau
+        prm = _lib.StepParams(eps, float(tau_eff), mu_e, mu_p, (ctypes.c_double * 3)(*De))
+        its = ctypes.c_int(0)
+        rel = ctypes.c_double(float("nan"))
+        with torch.cuda.device(self.device):
+            self.solver._sync_stream()
+            st = self._lib.gmg_elliptic_step(self.solver._ctx, _ptr(n_e), _ptr(n_p), ctypes.byref(prm), *self.bc,
+                                             self.tol, _ptr(self.a), _ptr(self.f), _ptr(self.phi),
+                                             int(self._warm), *[_ptr(e) for e in self.E], ctypes.byref(its),
+                                             ctypes.byref(rel))
+        if st < 0:
+            raise GMGError(st, "gmg_elliptic_step")
+        self.solver._a = self.a  # the context keeps the coefficient's pointer
+        self._warm = True
+        oe, op = out if out is not None else (torch.empty_like(n_e), torch.empty_like(n_p))
+        l_e, l_p = transport(n_e, n_p, self.E)
+        if self.scheme == "first":
+            self._update(n_e, n_p, l_e, l_p, tau, oe, op)
+        else:
+            he, hp = torch.empty_like(n_e), torch.empty_like(n_p)
+            self._update(n_e, n_p, l_e, l_p, 0.5 * tau, he, hp)  # predictor (eq. e1)
+            l_e, l_p = transport(he, hp, self.E)
+            self._update(n_e, n_p, l_e, l_p, tau, oe, op)  # corrector (eq. e2)
+        return StepInfo(oe, op, self.phi, self.E, st, its.value, rel.value)
+
+
 class _PoissonSolve(torch.autograd.Function):
     """phi = A(a)^{-1} (f + lifting(a)); the backward solves the adjoint with
     the same (self-adjoint) operator and hierarchy: lambda = A^{-1} dL/dphi,

@@ -295,6 +295,34 @@ def test_warm_start_time_loop_matches_oracle(warm):
         prev_g, prev_o = res.phi.clone(), ref.x
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_warm_started_steps_take_two_to_four_iterations(precision):
+    """The paper's iteration claim (Sec. 5.3, Fig. fstep): after the first
+    time step, warm-started solves with V-cycles need 2 to 4 FGMRES
+    iterations to 1e-8 at its mild coefficient contrast.  Two-filament
+    workload advected one cell per step at 64^3 with max(a) = 2, one cold
+    and four warm-started solves, each taking as many iterations as the
+    float64 oracle's."""
+    from workloads import config_two_filaments
+    prev_g = prev_o = None
+    s = None
+    its = []
+    for step in range(5):
+        p = config_two_filaments(64, a_max=2.0, step=step)
+        a = T(p.a)
+        if s is None:
+            s = gm.GMGPoisson(a, precision=precision)
+        else:
+            s.update_coefficient(a)
+        res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-8, x0=prev_g)
+        ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-8, x0=prev_o)
+        print(f"max(a) = 2, step {step} ({precision}): gpu {res.iterations}, oracle {ref.iterations}", flush=True)
+        assert res.converged and res.iterations == ref.iterations
+        its.append(res.iterations)
+        prev_g, prev_o = res.phi.clone(), ref.x
+    assert all(2 <= k <= 4 for k in its[1:]), its
+
+
 @pytest.mark.parametrize("warm", ["vcycle", "fmg"])
 def test_mixed_time_loop_two_filaments_within_residual_bound(warm):
     """The two-filament time loop in mixed precision on a 96^3 copy (the
@@ -609,6 +637,84 @@ def test_semi_implicit_step_full_size():
     E_ref = electric_field(npy(res.phi), h, 0.0, 1.0)
     for g_, r_ in zip(E, E_ref):
         assert rel(npy(g_), r_) < 1e-14
+
+
+def _step_case(n):
+    """Densities behind the two-filament workload (n_e = (a - 1) / kappa,
+    n_p = f / 50 + n_e) and step parameters for which P = a / 50 plus an ion
+    term at tau_eff = 1."""
+    from oracle.semi_implicit import StepParams
+    from workloads import config_two_filaments
+    p = config_two_filaments(n, step=0)
+    kappa = p.meta["kappa"]
+    ne = (p.a - 1.0) / kappa
+    npp = p.f / 50.0 + ne
+    prm = StepParams(eps0_over_e=1.0 / 50.0, mu_e=kappa / 50.0, mu_p=kappa / 5000.0, De=(1e-4, 1e-4, 1e-4))
+    return p, ne, npp, prm
+
+
+def _ionisation_and_recombination(n_e, n_p, E):
+    """The caller's transport of these tests: an ionisation source 0.1 |E|
+    n_e and a recombination loss 0.01 n_e n_p for both species (cell-local;
+    the same code runs on NumPy arrays and torch tensors)."""
+    s = 0.1 * E[3] * n_e - 0.01 * n_e * n_p
+    return s, s
+
+
+@pytest.mark.parametrize("scheme", ["second", "first"])
+def test_semi_implicit_time_steps_match_oracle(scheme):
+    """Three time steps of the second-order scheme (eqs. e1, e2, semi2) or
+    of the first-order one (eqs. semi-implicit, e15) on the two-filament
+    densities at 64^3, float64: gmg_elliptic_step (assembly, renewal,
+    warm-started solve, field) and gmg_density_update around the caller's
+    transport give the oracle's phi, E and densities within 1e-10, with the
+    same iteration counts."""
+    from oracle.semi_implicit import time_step
+    p, ne, npp, prm = _step_case(64)
+    tau = 1.0
+    st = gm.SemiImplicitStepper(T(ne), p.phi_bot, p.phi_top, prm.eps0_over_e, prm.mu_e, prm.mu_p, prm.De,
+                                scheme=scheme, precision="fp64")
+    ge, gp = T(ne), T(npp)
+    oe, op, ophi = ne, npp, None
+    for k in range(3):
+        info = st.step(ge, gp, tau, _ionisation_and_recombination)
+        r = time_step(oe, op, p.h, prm, tau, _ionisation_and_recombination, p.phi_bot, p.phi_top, phi_prev=ophi,
+                      scheme=scheme)
+        print(f"{scheme}-order step {k}: gpu {info.iterations} it, oracle {r.iterations} it, "
+              f"|dn_e| {rel(npy(info.n_e), r.n_e):.1e}", flush=True)
+        assert info.status == 0 and info.iterations == r.iterations
+        assert rel(npy(info.phi), r.phi) < 1e-10
+        for g_, r_ in zip(info.E, r.E):
+            assert rel(npy(g_), r_) < 1e-10
+        assert rel(npy(info.n_e), r.n_e) < 1e-10 and rel(npy(info.n_p), r.n_p) < 1e-10
+        ge, gp = info.n_e, info.n_p
+        oe, op, ophi = r.n_e, r.n_p, r.phi
+
+
+def test_semi_implicit_time_steps_mixed_in_place():
+    """Mixed precision, densities updated in place (out = the inputs), 128^3:
+    every warm-started step converges, its phi checked with the oracle's
+    operator on the coefficient and right side of eq. semi2, and the density
+    update equals n + tau L recomputed from the returned field."""
+    from oracle.semi_implicit import coefficient, right_side
+    p, ne, npp, prm = _step_case(128)
+    tau = 1.0
+    st = gm.SemiImplicitStepper(T(ne), p.phi_bot, p.phi_top, prm.eps0_over_e, prm.mu_e, prm.mu_p, prm.De)
+    ge, gp = T(ne), T(npp)
+    for k in range(3):
+        e0, p0 = npy(ge), npy(gp)
+        info = st.step(ge, gp, tau, _ionisation_and_recombination, out=(ge, gp))
+        a = coefficient(e0, p0, prm.eps0_over_e, tau / 2, prm.mu_e, prm.mu_p)
+        b = rhs(right_side(e0, p0, p.h, tau / 2, prm.De), a, p.h, p.phi_bot, p.phi_top)
+        r = np.linalg.norm(b - apply_operator(npy(info.phi), a, p.h)) / np.linalg.norm(b)
+        print(f"mixed step {k}: {info.iterations} it, true relres {r:.2e}", flush=True)
+        assert info.status == 0 and r < 1e-8
+        E = tuple(npy(x) for x in info.E)
+        le, lp = _ionisation_and_recombination(e0, p0, E)
+        he, hp = e0 + tau / 2 * le, p0 + tau / 2 * lp
+        le, lp = _ionisation_and_recombination(he, hp, E)
+        np.testing.assert_allclose(npy(info.n_e), e0 + tau * le, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(npy(info.n_p), p0 + tau * lp, rtol=1e-12, atol=1e-14)
 
 
 def test_two_filament_time_loop_full_size():
