@@ -185,6 +185,34 @@ int fgmres_solve(gmg_ctx* ctx, const double* f_dev, double phi_bot,
                  int* iterations, double* res_hist, int res_hist_cap,
                  int* res_hist_len, double* final_true_relres);
 
+/* Largest workspace (gmg_workspace_bytes) fgmres_solve_static accepts: 64 MiB,
+ * enough for a 64^3 grid in either precision.  The library holds this much
+ * device memory on every GPU it runs fgmres_solve_static on, from the first
+ * such call until the process ends. */
+#define GMG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): gmg_setup followed by fgmres_solve and
+ * gmg_destroy in one call, whose workspace is a device array of
+ * GMG_STATIC_SCRATCH_BYTES the library holds per GPU instead of a
+ * caller-allocated one.  It allocates no device or pinned host memory and
+ * calls no allocating HIP or torch routine (its host bookkeeping uses the C++
+ * heap).  Arguments: those of gmg_setup without the workspace (the grid,
+ * spacings, coefficient a_dev, options, stream), then those of fgmres_solve
+ * without the context; results, the initial guess (use_x0) and every status
+ * as there.  opt->graphs must be 0 (GMG_ERR_ARG otherwise: capturing a graph
+ * allocates).  GMG_ERR_WORKSPACE, with nothing launched, when the grid's
+ * workspace exceeds GMG_STATIC_SCRATCH_BYTES; GMG_ERR_HIP when the array's
+ * device address cannot be obtained.  Every call on one GPU uses the same
+ * array and nothing in it needs clearing (each buffer is written before it is
+ * read), which the next call overwrites: calls that overlapped on one GPU
+ * would race on it, so the library runs them one at a time (a lock per GPU,
+ * held until the call has synchronised its stream). */
+int fgmres_solve_static(int nx, int ny, int nz, double hx, double hy, double hz, const double* a_dev,
+                        const gmg_options* opt, void* hip_stream, const double* f_dev, double phi_bot,
+                        double phi_top, double tol, double* phi_dev, int use_x0, int* iterations, double* res_hist,
+                        int res_hist_cap, int* res_hist_len, double* final_true_relres);
+
 /* Krylov methods with the same multigrid preconditioner, for the comparison
  * of Sec. 5.3 (Table t1).  GMRES is right-preconditioned (Arnoldi on A M, the
  * update applies M to V y); CG is the preconditioned conjugate gradient; FCG

@@ -18,5 +18,6 @@ from .solver import (  # noqa: E402,F401
     SemiImplicitStepper,
     SolveResult,
     StepInfo,
+    fgmres_solve_static,
     poisson_solve,
 )

@@ -47,6 +47,9 @@ SIGNATURES = {
     "gmg_set_stream": (c_int, [c_void_p, c_void_p]),
     "fgmres_solve": (c_int, [c_void_p, c_void_p, c_double, c_double, c_double, c_void_p, c_int,
                              P_int, P_double, c_int, P_int, P_double]),
+    "fgmres_solve_static": (c_int, [c_int, c_int, c_int, c_double, c_double, c_double, c_void_p,
+                                    ctypes.POINTER(Options), c_void_p, c_void_p, c_double, c_double, c_double,
+                                    c_void_p, c_int, P_int, P_double, c_int, P_int, P_double]),
     "gmg_krylov_solve": (c_int, [c_void_p, c_int, c_void_p, c_double, c_double, c_double, c_void_p, c_int,
                                  P_int, P_int, P_double]),
     "gmg_apply_operator": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double]),

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -2063,6 +2064,78 @@ int fgmres_solve(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top
                  double* final_true_relres) {
   return fgmres_core(c, f_dev, phi_bot, phi_top, tol, phi_dev, use_x0, iterations, res_hist, res_hist_cap,
                      res_hist_len, final_true_relres, true, false);
+}
+
+// ---------------------------------------------------------------------------
+// Solve without allocation: the workspace is a device array the library
+// holds on every GPU it runs on.
+// ---------------------------------------------------------------------------
+
+// The array itself.  In host code its name is a host-side stand-in, not a
+// device address: only scratch_device() below yields the address kernels may
+// use.
+static __device__ __align__(256) unsigned char scratch[GMG_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+void* g_scratch_ptr[STATIC_MAX_DEVICES];  // device address of scratch, per device
+std::mutex g_scratch_mu[STATIC_MAX_DEVICES];
+
+// Device address of scratch on the current device (taken once per device,
+// with that device current), or null with *dev < 0 on failure.
+void* scratch_device(int* dev) {
+  if (hipGetDevice(dev) != hipSuccess || *dev < 0 || *dev >= STATIC_MAX_DEVICES) {
+    (void)hipGetLastError();
+    *dev = -1;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu[*dev]);
+  if (!g_scratch_ptr[*dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[*dev] = p;
+  }
+  return g_scratch_ptr[*dev];
+}
+
+}  // namespace
+
+int fgmres_solve_static(int nx, int ny, int nz, double hx, double hy, double hz, const double* a_dev,
+                        const gmg_options* opt, void* hip_stream, const double* f_dev, double phi_bot,
+                        double phi_top, double tol, double* phi_dev, int use_x0, int* iterations, double* res_hist,
+                        int res_hist_cap, int* res_hist_len, double* final_true_relres) {
+  int st = check_setup_args(hx, hy, hz, a_dev, opt);
+  if (st != GMG_OK) return st;
+  if (opt->graphs != 0) return GMG_ERR_ARG;  // capturing a graph allocates
+  Layout L;
+  st = make_layout(nx, ny, nz, hx, hy, hz, opt, &L);
+  if (st != GMG_OK) return st;
+  if (L.total > GMG_STATIC_SCRATCH_BYTES) return GMG_ERR_WORKSPACE;
+  int dev = -1;
+  void* ws = scratch_device(&dev);
+  if (!ws) return GMG_ERR_HIP;
+  // one call at a time per GPU: every call on it uses the same array
+  std::lock_guard<std::mutex> g(g_scratch_mu[dev]);
+  double host_buf[MAX_RESTART + 8];
+  gmg_ctx c;
+  st = init_ctx(&c, nx, ny, nz, hx, hy, hz, a_dev, opt, ws, GMG_STATIC_SCRATCH_BYTES, hip_stream, L, host_buf);
+  if (st == GMG_OK)
+    st = fgmres_solve(&c, f_dev, phi_bot, phi_top, tol, phi_dev, use_x0, iterations, res_hist, res_hist_cap,
+                      res_hist_len, final_true_relres);
+  // nothing of this call may still run on the array when the next one starts
+  if (hipStreamSynchronize(c.stream) != hipSuccess && st >= 0) st = GMG_ERR_HIP;
+  if (c.prof.on || !c.prof.pending.empty() || !c.prof.pool.empty()) {
+    for (auto& r : c.prof.pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : c.prof.pool) (void)hipEventDestroy(e);
+  }
+  return st;
 }
 
 int gmg_krylov_solve(gmg_ctx* c, int method, const double* f_dev, double phi_bot, double phi_top, double tol,

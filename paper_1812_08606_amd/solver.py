@@ -445,6 +445,57 @@ class SemiImplicitStepper:
         return StepInfo(oe, op, self.phi, self.E, st, its.value, rel.value)
 
 
+STATIC_SCRATCH_BYTES = 64 << 20  # GMG_STATIC_SCRATCH_BYTES of include/gmg.h
+
+
+def fgmres_solve_static(a: torch.Tensor, f: torch.Tensor, phi_bot: float, phi_top: float, tol: float,
+                        out: torch.Tensor, h=None, x0: torch.Tensor | None = None, precision: str = "mixed",
+                        **options) -> SolveResult:
+    """fgmres_solve_static of the C ABI: hierarchy set-up and FGMRES solve in
+    one call, on the device array the library holds per GPU (it allocates no
+    device memory; the grid's workspace must fit STATIC_SCRATCH_BYTES, else
+    GMGError with status -4).  out: the caller's phi (float64, a's shape);
+    x0: initial guess (copied into out first).  options: integer fields of
+    gmg_options by name (restart, max_iter, nu_pre, nu_post, fine_sweep,
+    cold_cycle, smoother, warm_cycle, restriction, ...), on top of
+    gmg_default_options."""
+    lib = _lib.load()
+    shape = tuple(a.shape)
+    if len(shape) != 3:
+        raise ValueError("a must be 3-D (nz, ny, nx)")
+    nz, ny, nx = shape
+    for t, name in ((a, "a"), (f, "f"), (out, "out")):
+        _check_field(t, shape, name, a.device)
+    if precision not in _PRECISION:
+        raise ValueError(f"precision must be one of {sorted(_PRECISION)}")
+    opt = _lib.Options()
+    lib.gmg_default_options(ctypes.byref(opt))
+    opt.precision = _PRECISION[precision]
+    names = {fld[0] for fld in _lib.Options._fields_}
+    for k, v in options.items():
+        if k not in names or k == "precision":
+            raise ValueError(f"unknown option {k}")
+        setattr(opt, k, int(v))
+    hh = tuple(float(v) for v in (h if h is not None else (1.0 / nx, 1.0 / ny, 1.0 / nz)))
+    if x0 is not None:
+        _check_field(x0, shape, "x0", a.device)
+        if x0.data_ptr() != out.data_ptr():
+            out.copy_(x0)
+    cap = int(opt.max_iter) + 2
+    hist = (ctypes.c_double * cap)()
+    its, nh = ctypes.c_int(0), ctypes.c_int(0)
+    rel = ctypes.c_double(float("nan"))
+    with torch.cuda.device(a.device):
+        stream = torch.cuda.current_stream(a.device).cuda_stream
+        st = lib.fgmres_solve_static(nx, ny, nz, *hh, _ptr(a), ctypes.byref(opt), ctypes.c_void_p(stream), _ptr(f),
+                                     float(phi_bot), float(phi_top), float(tol), _ptr(out), int(x0 is not None),
+                                     ctypes.byref(its), hist, cap, ctypes.byref(nh), ctypes.byref(rel))
+    if st < 0:
+        raise GMGError(st, "fgmres_solve_static")
+    return SolveResult(phi=out, status=st, iterations=its.value, res_hist=list(hist[:nh.value]),
+                       final_relres=rel.value)
+
+
 class _PoissonSolve(torch.autograd.Function):
     """phi = A(a)^{-1} (f + lifting(a)); the backward solves the adjoint with
     the same (self-adjoint) operator and hierarchy: lambda = A^{-1} dL/dphi,
