@@ -937,12 +937,12 @@ void vcycle_fine_cheb(gmg_ctx* c, const double* u, const double* bscale, T* X) {
 // threads, about 2048 * 1024 threads in all, z-chunks of at least 8 planes.
 template <typename T>
 Launch sym_launch(const LevelShape& s) {
-  constexpr int R = SymRows<T>::value;
-  const int gx = (s.nx / 2 + SYM_IN_X - 1) / SYM_IN_X, gy = (s.ny + R - 3) / (R - 2);
-  const long long target = 2048LL * 16 / R;
+  constexpr int SX = SymShape<T>::SX, R = SymShape<T>::R, IX = SymShape<T>::IX, IY = SymShape<T>::IY;
+  const int gx = (s.nx / 2 + IX - 1) / IX, gy = (s.ny + IY - 1) / IY;
+  const long long target = 2048LL * 1024 / (SX * R);
   int kc = (int)std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
   kc = std::min(kc, s.nz);
-  return Launch{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(BX, R, 1), kc};
+  return Launch{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(SX, R, 1), kc};
 }
 
 // One fused symmetric sweep (k_sym_split) on the finest level: colour c1
