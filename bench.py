@@ -56,11 +56,11 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SOURCES = ["gmg_common.hpp", "gmg_kernels.hpp", "gmg_fine.hpp"]
 LAUNCH_SOURCES = {
     "sym_fine_f32": ("gmg.hip", r"Launch sym_launch\(.*?\n}\n"),
-    "gs_fine_f64": ("gmg.hip", r"void gs_split\(.*?\n}\n"),
+    "sym_fine_f64": ("gmg.hip", r"Launch sym_launch\(.*?\n}\n"),
 }
 TRAFFIC_FILES = {
     "sym_fine_f32": os.path.join(ROOT, "profiles", "traffic_sym_fine_f32_filament512.md"),
-    "gs_fine_f64": os.path.join(ROOT, "profiles", "traffic_gs_fine_f64_filament512.md"),
+    "sym_fine_f64": os.path.join(ROOT, "profiles", "traffic_sym_fine_f64_filament512.md"),
 }
 
 

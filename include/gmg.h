@@ -115,10 +115,10 @@ typedef struct gmg_options {
   int coarse_max_cells; /* largest coarsest level solved directly (default 4096) */
   int fine_sweep;       /* GMG_SWEEP_HALF: one kernel per red or black half-sweep;
                            GMG_SWEEP_FUSED: one kernel per symmetric sweep
-                           (float32 V-cycle with nu_pre, nu_post >= 1 on a grid
-                           of at least two levels; half-sweeps otherwise);
+                           (nu_pre, nu_post >= 1 on a grid of at least two
+                           levels; half-sweeps otherwise);
                            GMG_SWEEP_AUTO (default): fused where it was
-                           measured faster (float32, long z-chunks) */
+                           measured faster (long z-chunks) */
   int cold_cycle;       /* preconditioner of a solve with use_x0 = 0: GMG_CYCLE_FMG
                            (default) one full multigrid cycle per step,
                            GMG_CYCLE_V one V-cycle per step. */

@@ -995,18 +995,18 @@ void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z, bo
   for (int p = npre + 1; p <= L; ++p) sym_split<T, false>(c, buf(p - 1), buf(p), B, nullptr, nullptr, a, 1);
 }
 
-// Fused symmetric sweeps on the finest level (float32 only, both smoothing
-// phases present): on request, or by default when their z-chunks are long.
-// Each chunk of the fused sweep adds two planes of first-colour work and a
-// pipeline fill, so it only wins with chunks of 32 planes or more (measured:
-// 5% per V-cycle at 768^3, 2% at 512^3; 9-22% slower at 384^3 and 256^3,
-// with 21- and 8-plane chunks).  In float64 the fused kernel's register
-// demand halves its block size and it was slower at every size.
+// Fused symmetric sweeps on the finest level (both smoothing phases
+// present): on request, or by default when their z-chunks are long.  Each
+// chunk of the fused sweep adds two planes of first-colour work and a
+// pipeline fill, so it only wins with chunks of 16 planes or more (measured,
+// solve with full multigrid cycles, V(2,3), mixed / float64: 2% / 6% faster
+// at 384^3 with 21-22-plane chunks, 10% / 12% at 512^3, 9% / 13% at 768^3;
+// 13% / 4% slower at 256^3 with 8-plane chunks).
 template <typename T>
 bool fused_sweeps(gmg_ctx* c) {
   const int fs = c->opt.fine_sweep;
-  return sizeof(T) == 4 && c->L.shapes.size() > 1 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 &&
-         (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(c->L.shapes[0]).kc >= 32));
+  return c->L.shapes.size() > 1 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 &&
+         (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(c->L.shapes[0]).kc >= 16));
 }
 
 // z = M (s * u) on the finest level with right side u scaled by *bscale

@@ -216,12 +216,13 @@ __device__ __forceinline__ void lds_barrier() {
 //
 // Block shape: SX = 64 lanes per row (one row per wave; 32-lane rows were
 // measured slower) times R rows; the block owns (SX - 2) x (R - 2) pairs.
-// Float64 halves the rows: 1024 threads would leave too few registers per
-// thread.
+// Float64 takes 12 rows: 1024 threads would leave too few registers per
+// thread (measured at 512^3: 1.16, 1.03 and 1.12 ms per sweep with 8, 12
+// and 16 rows, the last spilling).
 template <typename T>
 struct SymShape {
   static constexpr int SX = 64;
-  static constexpr int R = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int R = sizeof(T) == 4 ? 16 : 12;
   static constexpr int IX = SX - 2;  // pairs per block row that the block owns
   static constexpr int IY = R - 2;   // rows the block owns
 };

@@ -58,7 +58,7 @@ def test_nv_sequence_restarts():
     assert bench.nv_sequence(12, 5) == [1, 2, 3, 4, 5, 1, 2, 3, 4, 5, 1, 2]
 
 
-@pytest.mark.parametrize("kernel", ["sym_fine_f32", "gs_fine_f64"])
+@pytest.mark.parametrize("kernel", ["sym_fine_f32", "sym_fine_f64"])
 def test_traffic_only_for_matching_sources(monkeypatch, tmp_path, kernel):
     f = tmp_path / "traffic.md"
     f.write_text("traffic_bytes_per_launch: 2141258775\nkernel_source_sha256_16: 0123456789abcdef\n")
@@ -74,9 +74,9 @@ def test_traffic_only_for_matching_sources(monkeypatch, tmp_path, kernel):
 
 def test_kernel_sources_hash_per_kernel():
     """Each counted kernel hashes the device sources plus its own launch
-    function, so a change to one launch shape voids only that summary."""
-    h32, h64 = bench.kernel_source_hash("sym_fine_f32"), bench.kernel_source_hash("gs_fine_f64")
-    assert len(h32) == len(h64) == 16 and h32 != h64
+    function (the float32 and float64 fused sweeps share one)."""
+    h32, h64 = bench.kernel_source_hash("sym_fine_f32"), bench.kernel_source_hash("sym_fine_f64")
+    assert len(h32) == 16 and h32 == h64
 
 
 def test_kernel_table_and_roofline():

@@ -104,29 +104,30 @@ def test_vcycle_colour_split_finest_level(shape, sweep):
     assert rel(z, ref32) < 2e-5
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("n, fused_by_default", [(256, False), (512, True)])
-def test_fused_and_half_sweeps_agree_full_size(n, fused_by_default):
-    """Filament workload at 256^3 and 512^3 (max(a) = 1e3, 1e4): the float32
-    V-cycle with fused symmetric sweeps equals the one with half-sweep
-    kernels to float32 rounding, and the default picks the fused kernel only
-    on the long-chunk grid."""
-    print(f"fused vs half sweeps {n}^3", flush=True)
+def test_fused_and_half_sweeps_agree_full_size(n, fused_by_default, precision):
+    """Filament workload at 256^3 and 512^3 (max(a) = 1e3, 1e4): the V-cycle
+    with fused symmetric sweeps equals the one with half-sweep kernels to
+    rounding (float32 or float64), and the default picks the fused kernel
+    only on the long-chunk grid."""
+    print(f"fused vs half sweeps {n}^3 {precision}", flush=True)
     p = make_config(2 if n == 256 else 3, n=n)
     a, f = T(p.a), T(p.f)
     v = f / f.norm()
     z = {}
+    fused_name = "sym_fine_f32" if precision == "mixed" else "sym_fine_f64"
     for sweep in ("half", "fused", "auto"):
-        s = gm.GMGPoisson(a, precision="mixed", fine_sweep=sweep)
+        s = gm.GMGPoisson(a, precision=precision, fine_sweep=sweep)
         s.profile(True)
         z[sweep] = s.vcycle(v)
         names = set(s.profile_read())
         s.profile(False)
-        if sweep == "auto":
-            assert ("sym_fine_f32" in names) == fused_by_default
+        assert (fused_name in names) == (sweep == "fused" or (sweep == "auto" and fused_by_default))
         del s
     d = ((z["fused"] - z["half"]).norm() / z["half"].norm()).item()
     print(f"  |z_fused - z_half| / |z_half| = {d:.2e}", flush=True)
-    assert d < 1e-5
+    assert d < (1e-5 if precision == "mixed" else 1e-13)
     assert torch.equal(z["auto"], z["fused" if fused_by_default else "half"])
 
 
