@@ -108,9 +108,9 @@ def test_vcycle_colour_split_finest_level(shape, sweep):
 @pytest.mark.parametrize("n, fused_by_default", [(256, False), (512, True)])
 def test_fused_and_half_sweeps_agree_full_size(n, fused_by_default, precision):
     """Filament workload at 256^3 and 512^3 (max(a) = 1e3, 1e4): the V-cycle
-    with fused symmetric sweeps equals the one with half-sweep kernels to
-    rounding (float32 or float64), and the default picks the fused kernel
-    only on the long-chunk grid."""
+    with fused symmetric sweeps on the finest level equals the one with
+    half-sweep kernels to rounding (float32 or float64), and the default
+    picks the fused kernel only on the long-chunk grid."""
     print(f"fused vs half sweeps {n}^3 {precision}", flush=True)
     p = make_config(2 if n == 256 else 3, n=n)
     a, f = T(p.a), T(p.f)
