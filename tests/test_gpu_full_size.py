@@ -95,14 +95,15 @@ def test_config3_full_size_converged_solutions_checked_by_oracle_operator():
     for precision in ("mixed", "fp64"):
         s = gm.GMGPoisson(a_d, precision=precision, nu_pre=2, nu_post=3)
         res = s.solve(f_d, p.phi_bot, p.phi_top, tol=1e-8)
-        phi = npy(res.phi)
+        phi, reported = npy(res.phi), res.final_relres
         del s, res
         torch.cuda.empty_cache()
         r = np.linalg.norm(b - apply_operator(phi, p.a, p.h))
         phis[precision], rn[precision] = phi, r
-        say(f"512^3 {precision}: true relres {r / bn:.3e}; bound on |phi - phi*| / |phi| "
+        say(f"512^3 {precision}: true relres {r / bn:.3e} (reported {reported:.3e}); bound on |phi - phi*| / |phi| "
             f"{r / lam / np.linalg.norm(phi):.2e}")
         assert r < 1e-8 * bn
+        assert abs(r / bn - reported) <= 1e-3 * r / bn
     d = np.linalg.norm(phis["mixed"] - phis["fp64"])
     say(f"512^3: |phi_mixed - phi_fp64| / |phi_fp64| = {d / np.linalg.norm(phis['fp64']):.2e} "
         f"(bound {(rn['mixed'] + rn['fp64']) / lam / np.linalg.norm(phis['fp64']):.2e})")
