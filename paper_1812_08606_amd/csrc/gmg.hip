@@ -32,6 +32,13 @@ constexpr int MAX_RESTART = 32;
 constexpr double BREAKDOWN_TOL = 1e-14;
 constexpr int CHEB_ARNOLDI = 10;  // Arnoldi steps of the Chebyshev bound estimate
 constexpr int CHEB_DEGREE = 2;    // degree of the Chebyshev smoothing polynomial
+// device scalars of level l's bound estimate, CHEB_STRIDE doubles: column j
+// of the Hessenberg matrix at j * (CHEB_ARNOLDI + 1) (entries 0 .. j + 1),
+// the basis scales at CHEB_SCALES, the start vector's norm at CHEB_NORM0
+constexpr int CHEB_SCALES = CHEB_ARNOLDI * (CHEB_ARNOLDI + 1);
+constexpr int CHEB_NORM0 = CHEB_SCALES + CHEB_ARNOLDI + 1;
+constexpr int CHEB_STRIDE = 128;
+static_assert(CHEB_NORM0 < CHEB_STRIDE, "estimate scalars overflow their slot");
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -69,6 +76,7 @@ struct Layout {
   size_t V, Z, a32, b0, xs, partials, scal, cinv, bargs, total;
   size_t cr0, cd0;  // Chebyshev smoother, finest level: float64 natural residual, T colour-split direction
   size_t rr;        // transpose restriction: residual of the level being restricted (finest: float64)
+  size_t chs;       // Chebyshev smoother: device scalars of every level's bound estimate
   size_t tsize;  // bytes of the V-cycle precision
   size_t ldv;    // elements between consecutive Krylov vectors (v_i and z_i)
   size_t hn;     // elements of one colour array of a colour-split finest-level field
@@ -163,6 +171,7 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   L->rr = o->restriction == GMG_RESTRICT_TRANSPOSE && nl > 1 ? take(N * 8) : 0;
   L->cr0 = cheb && nl > 1 ? take(N * 8) : 0;
   L->cd0 = cheb && nl > 1 ? take(L->ldv * L->tsize) : 0;
+  L->chs = cheb && nl > 1 ? take((size_t)(nl - 1) * CHEB_STRIDE * 8) : 0;
   L->partials = take((size_t)MAXV * MAX_RED_BLOCKS * 8);
   L->scal = take((size_t)(L->m * (L->m + 2) + (L->m + 2) + 32) * 8);
   const size_t nc = last.n();
@@ -1003,10 +1012,14 @@ void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z, bo
 // at 384^3 with 21-22-plane chunks, 10% / 12% at 512^3, 9% / 13% at 768^3;
 // 13% / 4% slower at 256^3 with 8-plane chunks).
 template <typename T>
-bool fused_sweeps(gmg_ctx* c) {
+bool sym_chosen(gmg_ctx* c) {
   const int fs = c->opt.fine_sweep;
-  return c->L.shapes.size() > 1 && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 &&
+  return c->L.shapes.size() > 1 &&
          (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(c->L.shapes[0]).kc >= 16));
+}
+template <typename T>
+bool fused_sweeps(gmg_ctx* c) {
+  return c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 && sym_chosen<T>(c);
 }
 
 // z = M (s * u) on the finest level with right side u scaled by *bscale
@@ -1152,6 +1165,8 @@ void cycle_any(gmg_ctx* c, const double* u, const double* bscale, void* z, bool 
 // ---------------------------------------------------------------------------
 
 Launch red_launch(gmg_ctx* c) { return col_launch(c->nx, c->ny, c->nz, MAX_RED_BLOCKS); }
+// the same with one lane per x-pair of the finest level (nx even)
+Launch pair_red_launch(gmg_ctx* c) { return col_launch(c->nx / 2, c->ny, c->nz, MAX_RED_BLOCKS); }
 
 void finalize(gmg_ctx* c, int nblocks, int nv, int mode, double* out, const double* scale, double* out2) {
   const Launch one{dim3(1), dim3(FIN_THREADS, 1, 1), 0};
@@ -1162,10 +1177,22 @@ void finalize(gmg_ctx* c, int nblocks, int nv, int mode, double* out, const doub
 // r0 = b - A x (x may be null), ||b||^2 and ||r0||^2 into misc[0..1],
 // v_1 scale 1/||r0|| into vscale[0]; r0 stored into V[0] when store.
 void init_residual(gmg_ctx* c, const double* f, const double* x, double pb, double pt, bool store) {
-  const Launch rl = red_launch(c);
+  // the pair kernel loads f and x (caller's buffers) as 16-byte vectors
+  auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool pairs = c->nx % 2 == 0 && a16(f) && a16(x) && a16(c->a);
+  const Launch rl = pairs ? pair_red_launch(c) : red_launch(c);
   double* misc = scal_misc(c);
-  GMG_LAUNCH(c, "init_residual", k_init_residual, rl, f, c->a, x, c->L.shapes[0].geom(), pb, pt,
-             store ? wsp<double>(c, c->L.V) : (double*)nullptr, wsp<double>(c, c->L.partials), rl.kc);
+  double* r = store ? wsp<double>(c, c->L.V) : (double*)nullptr;
+  const Geom g = c->L.shapes[0].geom();
+  if (!pairs)
+    GMG_LAUNCH(c, "init_residual", k_init_residual, rl, f, c->a, x, g, pb, pt, r, wsp<double>(c, c->L.partials),
+               rl.kc);
+  else if (x)
+    GMG_LAUNCH(c, "init_residual", k_init_residual_pair<true>, rl, f, c->a, x, g, pb, pt, r,
+               wsp<double>(c, c->L.partials), rl.kc);
+  else
+    GMG_LAUNCH(c, "init_residual", k_init_residual_pair<false>, rl, f, c->a, x, g, pb, pt, r,
+               wsp<double>(c, c->L.partials), rl.kc);
   finalize(c, rl.nblocks(), 2, 0, misc, nullptr, nullptr);
   // misc[2] = ||r0||, vscale[0] = 1/||r0||
   const Launch one{dim3(1), dim3(FIN_THREADS, 1, 1), 0};
@@ -1321,10 +1348,13 @@ double* kscal(gmg_ctx* c) { return scal_misc(c) + 4; }
 
 // ---------------------------------------------------------------------------
 // Bounds of the Chebyshev smoother (Sec. 3.2, eq. qntn): per smoothed level,
-// 10 Arnoldi steps (modified Gram-Schmidt, Algorithm 1 without a
-// preconditioner) on M_l^{-1} A_l, the largest real part of the Ritz values
-// on the host.  Basis in the Krylov slots V[0..10] (natural float64, first
-// n_l entries), scalars in misc[16..31].
+// 10 Arnoldi steps (Algorithm 1 without a preconditioner) on M_l^{-1} A_l,
+// the largest real part of the Ritz values on the host.  Basis in the Krylov
+// slots V[0..10] (natural float64, first n_l entries), stored unnormalised
+// with the scales on the device as in the FGMRES steps; classical
+// Gram-Schmidt with the dots fused into the pass that writes the new vector.
+// Every level's steps are queued without a host wait, and one read-back
+// brings all Hessenberg matrices.
 // ---------------------------------------------------------------------------
 
 // Largest real part of the eigenvalues of the m x m upper Hessenberg matrix
@@ -1423,101 +1453,134 @@ int ritz_max_real(const double* Hin, int m, int ldh, double* out) {
   return GMG_OK;
 }
 
-// out = M_l^{-1} A_l v for natural float64 vectors of level l: the
-// operator in float64 (the finest level's from the float64 coefficient,
-// the coarser levels' from their float64 faces), M_l the smoother's SSOR
-// solve in the V-cycle precision T.
-template <typename T>
-void cheb_minv_a(gmg_ctx* c, int l, const double* v, double* out) {
+// Arnoldi step j = NV - 1 of level l's estimate: w = M_l^{-1} A_l v_j into
+// slot j + 1, where v_j = s_j u_j (u_j the raw vector in slot j, s_j =
+// vs[j]); the operator in float64 (the finest level's from the float64
+// coefficient, the coarser levels' from their float64 faces), M_l the
+// smoother's SSOR solve in the V-cycle precision T.  Then h_ij = (w, v_i)
+// for i <= j into hcol (dots fused into the pass that writes w), w -= sum_i
+// h_ij v_i, and h_{j+1,j} = ||w||, s_{j+1} = 1 / ||w|| (0 when w = 0).
+template <typename T, int NV>
+void cheb_step(gmg_ctx* c, int l, double* hcol, double* vs) {
+  constexpr int j = NV - 1;
   const LevelShape& s = c->L.shapes[l];
   const Geom g = s.geom();
-  double* w = wsp<double>(c, c->L.cr0);
+  const size_t n = s.n();
+  const double* U = kvec(c, 0);
+  const double* v = kvec(c, j);
+  double* w = kvec(c, j + 1);
+  double* part = wsp<double>(c, c->L.partials);
+  double* r = wsp<double>(c, c->L.cr0);  // A_l v_j
+  int nb;
   if (l == 0) {
-    const Launch rl = red_launch(c);
-    GMG_LAUNCH(c, "cheb_op_fine", k_op_natural<1>, rl, v, c->a, g, w, v, c->L.ldv, wsp<double>(c, c->L.partials),
-               rl.kc);
+    if (((uintptr_t)c->a & 15) == 0) {  // a loaded as 16-byte vectors
+      const Launch rl = pair_red_launch(c);
+      GMG_LAUNCH(c, "cheb_op_fine", k_op_pair<0>, rl, v, (const double*)(vs + j), c->a, g, r,
+                 (const double*)nullptr, c->L.ldv, part, rl.kc);
+    } else {
+      const Launch rl = red_launch(c);
+      GMG_LAUNCH(c, "cheb_op_fine", k_op_natural<0>, rl, v, (const double*)(vs + j), c->a, g, r,
+                 (const double*)nullptr, c->L.ldv, part, rl.kc);
+    }
     const T* a = c->mixed ? (const T*)wsp<float>(c, c->L.a32) : (const T*)c->a;
     T* E = wsp<T>(c, c->L.xs);
     T* Bs = wsp<T>(c, c->L.b0);
-    gs_split<T, true>(c, E, Bs, w, nullptr, a, 0);
-    gs_split<T, false>(c, E, Bs, nullptr, nullptr, a, 1);
+    // one symmetric sweep from zero: colours 0, 1, 0
+    if (sym_chosen<T>(c)) {
+      sym_split<T, true>(c, E, E, Bs, r, nullptr, a, 0);
+    } else {
+      gs_split<T, true>(c, E, Bs, r, nullptr, a, 0);
+      gs_split<T, false>(c, E, Bs, nullptr, nullptr, a, 1);
+    }
     gs_split<T, false>(c, E, Bs, nullptr, nullptr, a, 0);
-    const Launch pl = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
-    GMG_LAUNCH(c, "split_to_natural", k_split_to_natural<T>, pl, (const T*)E, c->L.hn, g, out, pl.kc);
-    return;
+    const Launch dl = opdot_launch(c);
+    GMG_LAUNCH(c, "cheb_natural_dots", (k_split_to_natural_dots<T, NV>), dl, (const T*)E, c->L.hn, g, w, U,
+               c->L.ldv, part, dl.kc);
+    nb = dl.nblocks();
+  } else {
+    const LevelOffsets& o = c->L.lv[l];
+    const FaceCoef<double> co64{wsp<double>(c, o.wx64), wsp<double>(c, o.wy64), wsp<double>(c, o.wz64),
+                                wsp<double>(c, o.tp64)};
+    const Launch fl = flat_launch(n);
+    double* vn = r + n;  // v_j made explicit (n_l <= N / 8)
+    GMG_LAUNCH(c, "cheb_scale", k_scale_by, fl, vn, v, (const double*)(vs + j), n);
+    const Launch cl = cell_launch(s.nx, s.ny, s.nz, 4096, 4);
+    GMG_LAUNCH(c, kname("cheb_op", l, 8), k_resid_face<double>, cl, (const double*)vn, (const double*)nullptr,
+               co64, g, r, cl.kc);
+    T* R = wsp<T>(c, o.cr);
+    T* E = wsp<T>(c, o.ce);
+    GMG_LAUNCH(c, "convert", (k_convert<T, double>), fl, (const double*)r, R, n);
+    const FaceCoef<T> co = face_coef<T>(c, l);
+    const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
+    GMG_LAUNCH(c, kname("ssor_first", l, sizeof(T)), (k_gs_pair_face<T, true>), pl, E, (const T*)R, co, g, pl.kc,
+               0);
+    GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, (const T*)R, co, g, pl.kc, 1);
+    GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, (const T*)R, co, g, pl.kc, 0);
+    Launch rf = fl;
+    rf.grid.x = std::min<unsigned>(fl.grid.x, MAX_RED_BLOCKS);
+    GMG_LAUNCH(c, "cheb_convert_dots", (k_convert_dots<T, NV>), rf, (const T*)E, w, n, U, c->L.ldv, part);
+    nb = rf.nblocks();
   }
-  const LevelOffsets& o = c->L.lv[l];
-  const size_t n = s.n();
-  const FaceCoef<double> co64{wsp<double>(c, o.wx64), wsp<double>(c, o.wy64), wsp<double>(c, o.wz64),
-                              wsp<double>(c, o.tp64)};
-  const Launch cl = cell_launch(s.nx, s.ny, s.nz, 4096, 4);
-  GMG_LAUNCH(c, kname("cheb_op", l, 8), k_resid_face<double>, cl, (const double*)v, (const double*)nullptr, co64,
-             g, w, cl.kc);
-  T* R = wsp<T>(c, o.cr);
-  T* E = wsp<T>(c, o.ce);
-  const Launch fl = flat_launch(n);
-  GMG_LAUNCH(c, "convert", (k_convert<T, double>), fl, (const double*)w, R, n);
-  const FaceCoef<T> co = face_coef<T>(c, l);
-  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
-  GMG_LAUNCH(c, kname("ssor_first", l, sizeof(T)), (k_gs_pair_face<T, true>), pl, E, (const T*)R, co, g, pl.kc, 0);
-  GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, (const T*)R, co, g, pl.kc, 1);
-  GMG_LAUNCH(c, kname("ssor", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, E, (const T*)R, co, g, pl.kc, 0);
-  GMG_LAUNCH(c, "convert", (k_convert<double, T>), fl, (const T*)E, out, n);
+  finalize(c, nb, NV, 1, hcol, vs, nullptr);
+  Launch rf = flat_launch(n);
+  rf.grid.x = std::min<unsigned>(rf.grid.x, MAX_RED_BLOCKS);
+  GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<NV>, rf, w, n, U, c->L.ldv, (const double*)hcol, (const double*)vs, 1,
+             part);
+  finalize(c, rf.nblocks(), 1, 2, hcol + NV, nullptr, vs + NV);
+}
+
+template <typename T, size_t... I>
+void cheb_step_nv(int nv, gmg_ctx* c, int l, double* hcol, double* vs, std::index_sequence<I...>) {
+  using F = void (*)(gmg_ctx*, int, double*, double*);
+  static constexpr F table[] = {&cheb_step<T, (int)I + 1>...};
+  table[nv - 1](c, l, hcol, vs);
 }
 
 // Arnoldi estimates and recurrence coefficients of every smoothed level.
 template <typename T>
 int cheb_estimate(gmg_ctx* c) {
   const int nl = (int)c->L.shapes.size();
-  c->cheb_lam.assign(std::max(nl - 1, 0), 0.0);
-  c->cheb_coef.assign(std::max(nl - 1, 0), {});
-  double* sd = scal_misc(c) + 16;  // dots 0..10, ||w||^2 at 11, the constant 1 at 12
-  double* part = wsp<double>(c, c->L.partials);
-  GMG_LAUNCH(c, "fill", k_fill<double>, flat_launch(1), sd + 12, 1.0, (size_t)1);
-  for (int l = 0; l < nl - 1; ++l) {
+  const int ns = std::max(nl - 1, 0);
+  c->cheb_lam.assign(ns, 0.0);
+  c->cheb_coef.assign(ns, {});
+  if (ns == 0) return GMG_OK;
+  double* S = wsp<double>(c, c->L.chs);
+  const auto seq = std::make_index_sequence<CHEB_ARNOLDI>{};
+  for (int l = 0; l < ns; ++l) {
+    double* Sl = S + (size_t)l * CHEB_STRIDE;
+    double* vs = Sl + CHEB_SCALES;
     const size_t n = c->L.shapes[l].n();
     const Launch fl = flat_launch(n);
     Launch rf = fl;
     rf.grid.x = std::min<unsigned>(fl.grid.x, MAX_RED_BLOCKS);
-    const int nb = rf.nblocks();
     double* V0 = kvec(c, 0);
     GMG_LAUNCH(c, "uniform_start", k_uniform_start, fl, V0, n, (unsigned long long)l);
-    GMG_LAUNCH(c, "multidot", k_multidot<1>, rf, (const double*)V0, n, (const double*)V0, c->L.ldv, part);
-    finalize(c, nb, 1, 0, sd + 11, nullptr, nullptr);
-    if (read_back(c, sd + 11, 1) != GMG_OK) return GMG_ERR_HIP;
-    const double n0 = std::sqrt(c->pinned[0]);
+    GMG_LAUNCH(c, "multidot", k_multidot<1>, rf, (const double*)V0, n, (const double*)V0, c->L.ldv,
+               wsp<double>(c, c->L.partials));
+    finalize(c, rf.nblocks(), 1, 2, Sl + CHEB_NORM0, nullptr, vs);
+    for (int j = 0; j < CHEB_ARNOLDI; ++j)
+      cheb_step_nv<T>(j + 1, c, l, Sl + (size_t)j * (CHEB_ARNOLDI + 1), vs, seq);
+  }
+  std::vector<double> h((size_t)ns * CHEB_STRIDE);
+  note(c, hipMemcpyAsync(h.data(), S, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  note(c, hipStreamSynchronize(c->stream));
+  if (c->err != hipSuccess) return GMG_ERR_HIP;
+  for (int l = 0; l < ns; ++l) {
+    const double* Sl = h.data() + (size_t)l * CHEB_STRIDE;
+    const double n0 = Sl[CHEB_NORM0];
     if (!(n0 > 0.0) || !std::isfinite(n0)) return GMG_ERR_NONFINITE;
-    GMG_LAUNCH(c, "lincomb", k_lincomb3, fl, V0, (const double*)V0, (const double*)nullptr, (const double*)nullptr,
-               1.0 / n0, 0.0, 0.0, n, 0, part);
     double H[(CHEB_ARNOLDI + 1) * CHEB_ARNOLDI] = {};
     int m = CHEB_ARNOLDI;
     for (int j = 0; j < CHEB_ARNOLDI; ++j) {
-      double* w = kvec(c, j + 1);
-      cheb_minv_a<T>(c, l, kvec(c, j), w);
-      // modified Gram-Schmidt: h_i = (w, v_i), w -= h_i v_i in turn, each
-      // update fused with the next dot
-      GMG_LAUNCH(c, "multidot", k_multidot<1>, rf, (const double*)w, n, (const double*)kvec(c, 0), c->L.ldv, part);
-      finalize(c, nb, 1, 0, sd, nullptr, nullptr);
-      for (int i = 0; i < j; ++i) {
-        GMG_LAUNCH(c, "mgs_axpy_dot", k_mgs_axpy_dot, rf, w, n, (const double*)kvec(c, i),
-                   (const double*)kvec(c, i + 1), (const double*)(sd + i), part);
-        finalize(c, nb, 1, 0, sd + i + 1, nullptr, nullptr);
-      }
-      GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<1>, rf, w, n, (const double*)kvec(c, j), c->L.ldv,
-                 (const double*)(sd + j), (const double*)(sd + 12), 1, part);
-      finalize(c, nb, 1, 0, sd + 11, nullptr, nullptr);
-      if (read_back(c, sd, 12) != GMG_OK) return GMG_ERR_HIP;
-      for (int i = 0; i <= j; ++i) H[i * CHEB_ARNOLDI + j] = c->pinned[i];
-      const double hn = std::sqrt(c->pinned[11]);
+      const double* col = Sl + (size_t)j * (CHEB_ARNOLDI + 1);
+      for (int i = 0; i <= j; ++i) H[i * CHEB_ARNOLDI + j] = col[i];
+      const double hn = col[j + 1];
       if (!std::isfinite(hn)) return GMG_ERR_NONFINITE;
-      if (hn == 0.0) {
+      if (hn == 0.0) {  // invariant subspace: the later steps ran on zero vectors
         m = j + 1;
         break;
       }
       H[(j + 1) * CHEB_ARNOLDI + j] = hn;
-      if (j + 1 < CHEB_ARNOLDI)
-        GMG_LAUNCH(c, "lincomb", k_lincomb3, fl, w, (const double*)w, (const double*)nullptr, (const double*)nullptr,
-                   1.0 / hn, 0.0, 0.0, n, 0, part);
     }
     double lam = 0.0;
     const int st = ritz_max_real(H, m, CHEB_ARNOLDI, &lam);
@@ -1538,7 +1601,7 @@ int cheb_estimate(gmg_ctx* c) {
       rho_prev = rho;
     }
   }
-  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+  return GMG_OK;
 }
 
 // out = M u (one V-cycle from zero) in the natural layout, float64.
@@ -1584,13 +1647,19 @@ void kdots(gmg_ctx* c, const double* w, const double* U, int nv, double* out) {
 
 // w = A x (homogeneous plates) with the dots (w, u_q), q < nv (1 or 2), into out.
 void kapply(gmg_ctx* c, const double* x, double* w, const double* U, int nv, double* out) {
-  const Launch rl = red_launch(c);
-  if (nv == 1)
-    GMG_LAUNCH(c, "op_natural", k_op_natural<1>, rl, x, c->a, c->L.shapes[0].geom(), w, U, c->L.ldv,
-               wsp<double>(c, c->L.partials), rl.kc);
+  const bool pairs = c->nx % 2 == 0 && ((uintptr_t)c->a & 15) == 0;  // a loaded as 16-byte vectors
+  const Launch rl = pairs ? pair_red_launch(c) : red_launch(c);
+  const Geom g = c->L.shapes[0].geom();
+  double* part = wsp<double>(c, c->L.partials);
+  const double* one = nullptr;
+  if (pairs && nv == 1)
+    GMG_LAUNCH(c, "op_natural", k_op_pair<1>, rl, x, one, c->a, g, w, U, c->L.ldv, part, rl.kc);
+  else if (pairs)
+    GMG_LAUNCH(c, "op_natural", k_op_pair<2>, rl, x, one, c->a, g, w, U, c->L.ldv, part, rl.kc);
+  else if (nv == 1)
+    GMG_LAUNCH(c, "op_natural", k_op_natural<1>, rl, x, one, c->a, g, w, U, c->L.ldv, part, rl.kc);
   else
-    GMG_LAUNCH(c, "op_natural", k_op_natural<2>, rl, x, c->a, c->L.shapes[0].geom(), w, U, c->L.ldv,
-               wsp<double>(c, c->L.partials), rl.kc);
+    GMG_LAUNCH(c, "op_natural", k_op_natural<2>, rl, x, one, c->a, g, w, U, c->L.ldv, part, rl.kc);
   finalize(c, rl.nblocks(), nv, 0, out, nullptr, nullptr);
 }
 

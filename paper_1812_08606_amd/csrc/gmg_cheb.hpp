@@ -2,8 +2,9 @@
 // Arnoldi estimate of its bounds.  The SSOR steps themselves are the
 // red-black half-sweep kernels of the Gauss-Seidel smoother (one symmetric
 // sweep from zero: red, black, red); these kernels add the residuals the
-// Chebyshev recurrence needs, its vector update, and the start vector of the
-// estimate.  All are single streaming passes bound by HBM bandwidth.
+// Chebyshev recurrence needs, its vector update, and the start vector and
+// coarse-level vector passes of the estimate.  All are single streaming
+// passes bound by HBM bandwidth.
 #pragma once
 
 #include "gmg_fine.hpp"
@@ -143,24 +144,30 @@ __global__ __launch_bounds__(NTHREADS) void k_cheb_update(T* __restrict__ x, T* 
   }
 }
 
-// One modified Gram-Schmidt step of the bound estimate fused with the dot of
-// the next: w -= h u (h = *hcol), then the per-block partial sums of
-// (w, u2) (flat launch).  Each thread does exactly what the update and the
-// dot kernels would do in turn, so the result is the same to the bit.
-__global__ __launch_bounds__(NTHREADS) void k_mgs_axpy_dot(double* __restrict__ w, size_t n,
-                                                           const double* __restrict__ u,
-                                                           const double* __restrict__ u2,
-                                                           const double* __restrict__ hcol,
+// Bound estimate, coarse levels: y = x * (*s) (the lazily normalised
+// Arnoldi vector made explicit for the operator kernel; flat launch).
+__global__ __launch_bounds__(NTHREADS) void k_scale_by(double* __restrict__ y, const double* __restrict__ x,
+                                                       const double* __restrict__ s, size_t n) {
+  const double sv = *s;
+  GMG_FLAT_LOOP(c, n) { y[c] = x[c] * sv; }
+}
+
+// Bound estimate, coarse levels: out = x promoted to float64 and the
+// per-block partial sums of the dots (out, u_v), v < NV (flat launch).
+template <typename T, int NV>
+__global__ __launch_bounds__(NTHREADS) void k_convert_dots(const T* __restrict__ x, double* __restrict__ out,
+                                                           size_t n, const double* __restrict__ U, size_t stride,
                                                            double* __restrict__ partials) {
-  const double cf = *hcol;
-  double acc[1] = {0.0};
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
   GMG_FLAT_LOOP(c, n) {
-    double wv = w[c];
-    wv -= cf * u[c];
-    w[c] = wv;
-    acc[0] += wv * u2[c];
+    const double v = (double)x[c];
+    out[c] = v;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] += v * U[(size_t)q * stride + c];
   }
-  block_store_partials<1>(acc, 1, partials, gridDim.x);
+  block_store_partials<NV>(acc, NV, partials, gridDim.x);
 }
 
 }  // namespace gmg

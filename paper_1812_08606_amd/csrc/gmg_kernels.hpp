@@ -775,6 +775,188 @@ __global__ __launch_bounds__(NTHREADS) void k_init_residual(const double* __rest
   block_store_partials<2>(acc, 2, partials, gridDim.x * gridDim.y * gridDim.z);
 }
 
+// The operator of e18 (homogeneous plates) on natural-layout float64
+// fields with one lane per x-pair (cells 2m, 2m + 1; nx even).  Each lane
+// marches its pair through a z-chunk with x and a of the planes below and
+// above in registers, loads the pair and its y-neighbours as 16-byte
+// vectors and takes the x-neighbours from the adjacent lanes (the block's
+// edge lanes load them).  PairOp::apply returns A x on both cells of plane
+// k, summed in the order of the one-cell kernels (west, east, south,
+// north, bottom, top), so the values are the same to the bit.  Lanes past
+// the row's end (m >= H) run with clamped addresses so that every lane of
+// a wave takes part in the exchange; their results are not used.
+struct PairOp {
+  double hx, hy, hz, pz;
+  bool hw, he;  // x-faces of the pair outside it are interior faces
+  __device__ explicit PairOp(const Geom& g, int m) {
+    hx = 0.5 * g.ihx2;
+    hy = 0.5 * g.ihy2;
+    hz = 0.5 * g.ihz2;
+    pz = 2.0 * g.ihz2;
+    const int H = g.nx >> 1;
+    hw = m > 0 && m < H;
+    he = m < H - 1;
+  }
+  __device__ __forceinline__ double cell(double xc, double ac, bool hwest, double xw, double aw, bool heast,
+                                         double xe, double ae, bool hs, double xs, double as, bool hn, double xn,
+                                         double an, bool bot, double xb, double ab, bool top, double xt,
+                                         double at) const {
+    double s = hwest ? (ac + aw) * hx * (xc - xw) : 0.0;
+    s += heast ? (ac + ae) * hx * (xc - xe) : 0.0;
+    s += hs ? (ac + as) * hy * (xc - xs) : 0.0;
+    s += hn ? (ac + an) * hy * (xc - xn) : 0.0;
+    s += bot ? (ac + ab) * hz * (xc - xb) : pz * ac * xc;
+    s += !top ? (ac + at) * hz * (xc - xt) : pz * ac * xc;
+    return s;
+  }
+};
+
+// March state and loads of one lane: X (scaled by sv as it is read) and a.
+struct PairMarch {
+  const double* __restrict__ x;
+  const double* __restrict__ a;
+  double sv;
+  size_t sy, sz;
+  __device__ __forceinline__ double2 ld2(const double* __restrict__ p, size_t c) const {
+    return *reinterpret_cast<const double2*>(p + c);
+  }
+  __device__ __forceinline__ double2 lx2(size_t c) const {
+    const double2 v = ld2(x, c);
+    return make_double2(v.x * sv, v.y * sv);
+  }
+};
+
+// Runs fn(c, s0, s1) for every pair of the lane's rows and z-chunk with
+// s = A (sv x) on its two cells (c = natural index of cell 2m).
+template <typename F>
+__device__ __forceinline__ void pair_op_march(const double* __restrict__ x, double sv,
+                                              const double* __restrict__ a, const Geom& g, int kc, F&& fn) {
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int lane = threadIdx.x;
+  const int m = tl.x * BX + lane;
+  const bool act = m < H;
+  const int mm = act ? m : H - 1;
+  const PairOp op(g, m);
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const PairMarch pm{x, a, sv, sy, sz};
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    const bool hs = j > 0, hn = j < g.ny - 1;
+    size_t c = ((size_t)k0 * g.ny + j) * g.nx + 2 * mm;
+    double2 xc = pm.lx2(c), ac = pm.ld2(a, c);
+    double2 xb = xc, ab = ac;
+    if (k0 > 0) {
+      xb = pm.lx2(c - sz);
+      ab = pm.ld2(a, c - sz);
+    }
+    for (int k = k0; k < k1; ++k, c += sz) {
+      const bool top = k == g.nz - 1, bot = k > 0;
+      const double2 xt = top ? xc : pm.lx2(c + sz), at = top ? ac : pm.ld2(a, c + sz);
+      const double2 xs = hs ? pm.lx2(c - sy) : xc, as = hs ? pm.ld2(a, c - sy) : ac;
+      const double2 xn = hn ? pm.lx2(c + sy) : xc, an = hn ? pm.ld2(a, c + sy) : ac;
+      double xw = __shfl_up(xc.y, 1, 64), aw = __shfl_up(ac.y, 1, 64);
+      double xe = __shfl_down(xc.x, 1, 64), ae = __shfl_down(ac.x, 1, 64);
+      if (lane == 0 && op.hw) {
+        xw = x[c - 1] * sv;
+        aw = a[c - 1];
+      }
+      if (lane == BX - 1 && op.he) {
+        xe = x[c + 2] * sv;
+        ae = a[c + 2];
+      }
+      const double s0 = op.cell(xc.x, ac.x, op.hw, xw, aw, true, xc.y, ac.y, hs, xs.x, as.x, hn, xn.x, an.x, bot,
+                                xb.x, ab.x, top, xt.x, at.x);
+      const double s1 = op.cell(xc.y, ac.y, true, xc.x, ac.x, op.he, xe, ae, hs, xs.y, as.y, hn, xn.y, an.y, bot,
+                                xb.y, ab.y, top, xt.y, at.y);
+      if (act) fn(c, k, s0, s1, ac);
+      xb = xc;
+      ab = ac;
+      xc = xt;
+      ac = at;
+    }
+  }
+}
+
+// w = A (s x) (s = *xscale, 1 when null) on natural-layout float64 vectors,
+// one lane per x-pair (nx even), and the dots (w, u_v), v < NV (none when
+// NV = 0): the values of k_op_natural.
+template <int NV>
+__global__ __launch_bounds__(NTHREADS) void k_op_pair(const double* __restrict__ x,
+                                                      const double* __restrict__ xscale,
+                                                      const double* __restrict__ a, Geom g,
+                                                      double* __restrict__ w, const double* __restrict__ U,
+                                                      size_t stride, double* __restrict__ partials, int kc) {
+  double acc[NV > 0 ? NV : 1];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  const double sv = xscale ? *xscale : 1.0;
+  pair_op_march(x, sv, a, g, kc, [&](size_t c, int, double s0, double s1, const double2&) {
+    *reinterpret_cast<double2*>(w + c) = make_double2(s0, s1);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double2 u = *reinterpret_cast<const double2*>(U + (size_t)q * stride + c);
+      acc[q] += s0 * u.x + s1 * u.y;
+    }
+  });
+  if constexpr (NV > 0) block_store_partials<NV>(acc, NV, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// k_init_residual with one lane per x-pair (nx even): b = f + lifting, r =
+// b - A x0 (r = b without x0, which then reads a on the plates only), the
+// same values; partial sums of ||b||^2 and ||r||^2; r stored when r_out is
+// given.
+template <bool HAS_X>
+__global__ __launch_bounds__(NTHREADS) void k_init_residual_pair(const double* __restrict__ f,
+                                                                 const double* __restrict__ a,
+                                                                 const double* __restrict__ x0, Geom g, double pb,
+                                                                 double pt, double* __restrict__ r_out,
+                                                                 double* __restrict__ partials, int kc) {
+  double acc[2] = {0.0, 0.0};
+  auto rhs = [&](size_t c, int k, double& b0, double& b1, const double2& ac) {
+    const double2 fv = *reinterpret_cast<const double2*>(f + c);
+    b0 = fv.x;
+    b1 = fv.y;
+    if (k == 0) {
+      b0 += 2.0 * ac.x * pb * g.ihz2;
+      b1 += 2.0 * ac.y * pb * g.ihz2;
+    }
+    if (k == g.nz - 1) {
+      b0 += 2.0 * ac.x * pt * g.ihz2;
+      b1 += 2.0 * ac.y * pt * g.ihz2;
+    }
+  };
+  if constexpr (HAS_X) {
+    pair_op_march(x0, 1.0, a, g, kc, [&](size_t c, int k, double s0, double s1, const double2& ac) {
+      double b0, b1;
+      rhs(c, k, b0, b1, ac);
+      const double r0 = b0 - s0, r1 = b1 - s1;
+      if (r_out) *reinterpret_cast<double2*>(r_out + c) = make_double2(r0, r1);
+      acc[0] += b0 * b0 + b1 * b1;
+      acc[1] += r0 * r0 + r1 * r1;
+    });
+  } else {
+    const Tile tl = xcd_tile();
+    const int m = tl.x * BX + threadIdx.x;
+    if (m < (g.nx >> 1)) {
+      const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+      for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+        for (int k = k0; k < k1; ++k) {
+          const size_t c = ((size_t)k * g.ny + j) * g.nx + 2 * m;
+          const double2 ac = (k == 0 || k == g.nz - 1) ? *reinterpret_cast<const double2*>(a + c)
+                                                      : make_double2(0.0, 0.0);
+          double b0, b1;
+          rhs(c, k, b0, b1, ac);
+          if (r_out) *reinterpret_cast<double2*>(r_out + c) = make_double2(b0, b1);
+          acc[0] += b0 * b0 + b1 * b1;
+          acc[1] += b0 * b0 + b1 * b1;
+        }
+      }
+    }
+  }
+  block_store_partials<2>(acc, 2, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
 // Flat grid-stride loop over n cells, block size NTHREADS.
 #define GMG_FLAT_LOOP(c, n)                                                                        \
   for (size_t c = (size_t)blockIdx.x * NTHREADS + threadIdx.y * BX + threadIdx.x; c < (n);       \

@@ -44,21 +44,26 @@ __global__ __launch_bounds__(NTHREADS) void k_lincomb3(double* y, const double* 
   if (want_norm) block_store_partials<1>(acc, 1, partials, gridDim.x);
 }
 
-// w = A x on natural float64 vectors (the operator of e18 with homogeneous
-// plate values) and the dots (w, u_v), v < NV.  Each thread marches one
-// (i, j) column through its z-chunk (rows strided when the grid has more
-// columns than blocks allow), x and a of the planes below / above in
-// registers; x- and y-neighbours are loaded from clamped addresses, which
-// make the flux through a side face exactly zero (Neumann).
+// w = A (s x) on natural float64 vectors (the operator of e18 with
+// homogeneous plate values; s = *xscale, 1 when xscale is null, applied to
+// every value of x as it is read) and the dots (w, u_v), v < NV (none when
+// NV = 0).  Each thread marches one (i, j) column through its z-chunk (rows
+// strided when the grid has more columns than blocks allow), x and a of the
+// planes below / above in registers; x- and y-neighbours are loaded from
+// clamped addresses, which make the flux through a side face exactly zero
+// (Neumann).
 template <int NV>
-__global__ __launch_bounds__(NTHREADS) void k_op_natural(const double* __restrict__ x, const double* __restrict__ a,
-                                                         Geom g, double* __restrict__ w,
-                                                         const double* __restrict__ U, size_t stride,
-                                                         double* __restrict__ partials, int kc) {
+__global__ __launch_bounds__(NTHREADS) void k_op_natural(const double* __restrict__ xr,
+                                                         const double* __restrict__ xscale,
+                                                         const double* __restrict__ a, Geom g,
+                                                         double* __restrict__ w, const double* __restrict__ U,
+                                                         size_t stride, double* __restrict__ partials, int kc) {
   const Tile tl = xcd_tile();
-  double acc[NV];
+  double acc[NV > 0 ? NV : 1];
 #pragma unroll
   for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  const double sv = xscale ? *xscale : 1.0;
+  auto x = [&](size_t c) { return xr[c] * sv; };
   const int i = tl.x * BX + threadIdx.x;
   if (i < g.nx) {
     const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
@@ -68,14 +73,14 @@ __global__ __launch_bounds__(NTHREADS) void k_op_natural(const double* __restric
     for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
       const size_t ds = j > 0 ? sy : 0, dn = j < g.ny - 1 ? sy : 0;
       size_t c = cidx(g, i, j, k0);
-      double xc = x[c], ac = a[c];
-      double xb = x[k0 > 0 ? c - sz : c], ab = a[k0 > 0 ? c - sz : c];
+      double xc = x(c), ac = a[c];
+      double xb = x(k0 > 0 ? c - sz : c), ab = a[k0 > 0 ? c - sz : c];
       for (int k = k0; k < k1; ++k, c += sz) {
         const bool top = k == g.nz - 1;
         const size_t ct = top ? c : c + sz;
-        const double xt = x[ct], at = a[ct];
-        const double xw = x[c - dw], aw = a[c - dw], xe = x[c + de], ae = a[c + de];
-        const double xs = x[c - ds], as = a[c - ds], xn = x[c + dn], an = a[c + dn];
+        const double xt = x(ct), at = a[ct];
+        const double xw = x(c - dw), aw = a[c - dw], xe = x(c + de), ae = a[c + de];
+        const double xs = x(c - ds), as = a[c - ds], xn = x(c + dn), an = a[c + dn];
         double s = (ac + aw) * hx * (xc - xw);
         s += (ac + ae) * hx * (xc - xe);
         s += (ac + as) * hy * (xc - xs);
@@ -89,6 +94,41 @@ __global__ __launch_bounds__(NTHREADS) void k_op_natural(const double* __restric
         xc = xt;
         ab = ac;
         ac = at;
+      }
+    }
+  }
+  if constexpr (NV > 0) block_store_partials<NV>(acc, NV, partials, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// out = z promoted to float64 in the natural layout (z colour-split, colour
+// c at offset c * hn) and the per-block partial sums of the dots (out, u_v),
+// v < NV.  One lane per x-pair of a row, rows strided when the grid has
+// fewer rows than the level, z-chunks of kc planes.
+template <typename T, int NV>
+__global__ __launch_bounds__(NTHREADS) void k_split_to_natural_dots(const T* __restrict__ Z, size_t hn, Geom g,
+                                                                    double* __restrict__ out,
+                                                                    const double* __restrict__ U, size_t stride,
+                                                                    double* __restrict__ partials, int kc) {
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int m = tl.x * BX + threadIdx.x;
+  if (m < H) {
+    const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+    for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+      for (int k = k0; k < k1; ++k) {
+        const size_t q = sidx(g, m, j, k);
+        const int e = (j + k) & 1;  // colour of cell 2m
+        const double v0 = (double)Z[(size_t)e * hn + q], v1 = (double)Z[(size_t)(1 - e) * hn + q];
+        const size_t c = ((size_t)k * g.ny + j) * g.nx + 2 * m;
+        *reinterpret_cast<double2*>(out + c) = make_double2(v0, v1);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double2 u = *reinterpret_cast<const double2*>(U + (size_t)v * stride + c);
+          acc[v] += v0 * u.x + v1 * u.y;
+        }
       }
     }
   }
