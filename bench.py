@@ -51,9 +51,13 @@ if ROOT not in sys.path:
 
 METRIC = "converged cells/s per 1e-8 Poisson solve + HBM GB/s, FP64 vs mixed, 512^3"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-# what the counted kernels (the finest-level sweeps) are built from: their
-# device code and the host functions that set their launch shapes
-KERNEL_SOURCES = ["gmg_common.hpp", "gmg_kernels.hpp", "gmg_fine.hpp"]
+# what the counted kernels (the fused finest-level sweeps) are built from:
+# their device code (the fused sweep's header and the shared helpers it
+# includes) and the host functions that set their launch shapes
+KERNEL_SOURCES = {
+    "sym_fine_f32": ["gmg_common.hpp", "gmg_sym.hpp"],
+    "sym_fine_f64": ["gmg_common.hpp", "gmg_sym.hpp"],
+}
 LAUNCH_SOURCES = {
     "sym_fine_f32": ("gmg.hip", r"Launch sym_launch\(.*?\n}\n"),
     "sym_fine_f64": ("gmg.hip", r"Launch sym_launch\(.*?\n}\n"),
@@ -208,7 +212,7 @@ def kernel_source_hash(kernel="sym_fine_f32"):
     """Hash of the device sources and of the kernel's launch function."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1812_08606_amd", "csrc")
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     fname, pattern = LAUNCH_SOURCES[kernel]

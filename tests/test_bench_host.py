@@ -79,6 +79,22 @@ def test_kernel_sources_hash_per_kernel():
     assert len(h32) == 16 and h32 == h64
 
 
+def test_hashed_sources_close_over_the_fused_sweep():
+    """The hash covers everything the fused sweep's device code is compiled
+    from: its header includes only the shared helpers, which include only
+    system headers, so a change to any other kernel keeps the counted
+    traffic valid and a change to these files drops it."""
+    import re
+    csrc = os.path.join(os.path.dirname(bench.__file__), "paper_1812_08606_amd", "csrc")
+    for kernel in ("sym_fine_f32", "sym_fine_f64"):
+        files = bench.KERNEL_SOURCES[kernel]
+        for f in files:
+            text = open(os.path.join(csrc, f)).read()
+            for inc in re.findall(r'#include\s+"([^"]+)"', text):
+                assert inc in files, (f, inc)
+        assert "void k_sym_split(" in open(os.path.join(csrc, "gmg_sym.hpp")).read()
+
+
 def test_kernel_table_and_roofline():
     """Byte models per kernel from an event pass: the fused sweep's 14 B/cell
     per launch at 512^3 (mixed) over its average launch, and the float64
