@@ -113,12 +113,17 @@ typedef struct gmg_options {
                            (coefficients, smoother, transfers, coarse solve) in
                            float32, FGMRES in float64 (default GMG_MIXED)       */
   int coarse_max_cells; /* largest coarsest level solved directly (default 4096) */
-  int fine_sweep;       /* GMG_SWEEP_HALF: one kernel per red or black half-sweep;
+  int fine_sweep;       /* red-black Gauss-Seidel smoothing kernels:
+                           GMG_SWEEP_HALF: one kernel per red or black half-sweep;
                            GMG_SWEEP_FUSED: one kernel per symmetric sweep
-                           (nu_pre, nu_post >= 1 on a grid of at least two
-                           levels; half-sweeps otherwise);
+                           (nu_pre, nu_post >= 1; on the finest level of a grid
+                           of at least two levels, and on coarse levels above
+                           the one-workgroup bottom with rows of at most 128
+                           x-pairs in float32, 64 in float64; half-sweeps
+                           elsewhere);
                            GMG_SWEEP_AUTO (default): fused where it was
-                           measured faster (long z-chunks) */
+                           measured faster (finest level: long z-chunks;
+                           coarse levels: at least 128^3 cells) */
   int cold_cycle;       /* preconditioner of a solve with use_x0 = 0: GMG_CYCLE_FMG
                            (default) one full multigrid cycle per step,
                            GMG_CYCLE_V one V-cycle per step. */

@@ -302,10 +302,12 @@ __global__ __launch_bounds__(NTHREADS) void k_resid_restrict_split(const T* __re
 // in the bit mask cmask (1 red, 2 black) are written; otherwise the fine x
 // is natural (every cell).
 // SET: x = P xc (the interpolated initial guess of a full multigrid cycle)
-// instead of x += P xc.
+// instead of x += P xc.  xin (natural layout only; null otherwise): x = xin
+// + P xc, xin another buffer.
 template <typename T, bool SPLIT, bool SET = false>
 __global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, const T* __restrict__ xc, Geom g,
-                                                           size_t hn, int cmask, int kc) {
+                                                           size_t hn, int cmask, int kc,
+                                                           const T* __restrict__ xin) {
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
   const int m = tl.x * BX + threadIdx.x;
@@ -355,8 +357,16 @@ __global__ __launch_bounds__(NTHREADS) void k_prolong_pair(T* __restrict__ x, co
         }
       } else {
         const size_t cn = ((size_t)k * g.ny + j) * g.nx + 2 * m;
-        x[cn] = SET ? vl : x[cn] + vl;
-        x[cn + 1] = SET ? vr : x[cn + 1] + vr;
+        if (SET) {
+          x[cn] = vl;
+          x[cn + 1] = vr;
+        } else if (xin) {
+          x[cn] = xin[cn] + vl;
+          x[cn + 1] = xin[cn + 1] + vr;
+        } else {
+          x[cn] = x[cn] + vl;
+          x[cn + 1] = x[cn + 1] + vr;
+        }
       }
     }
     lb = lc;

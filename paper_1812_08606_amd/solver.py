@@ -66,8 +66,9 @@ class GMGPoisson:
 
     a: float64 CUDA/HIP tensor (nz, ny, nx), > 0.  h: (hx, hy, hz), default
     unit cube.  precision: "mixed" (float32 V-cycle) or "fp64".  fine_sweep:
-    finest-level smoother kernels, "half" (one per half-sweep), "fused" (one
-    per symmetric sweep, float32 only) or "auto".  cold_cycle: preconditioner
+    Gauss-Seidel smoother kernels, "half" (one per half-sweep), "fused" (one
+    per symmetric sweep on the finest level and the coarse levels that allow
+    it) or "auto" (fused where it was measured faster).  cold_cycle: preconditioner
     of a solve without an initial guess, "fmg" (full multigrid, the default)
     or "vcycle"; warm_cycle: the same for a warm-started solve, "vcycle"
     (the paper's choice, the default) or "fmg".  graphs: replay each
