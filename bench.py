@@ -147,6 +147,10 @@ def bytes_per_cell(base, level, s, nu_post=2):
             return 0.5 * s + s / 8
         return None
     if level is not None and level > 0:  # face coefficients wx, wy, wz (plates neglected)
+        if base == "sym":  # fused symmetric sweep: old x of the second colour, faces, b read; x written
+            return 0.5 * s + 3 * s + s + s
+        if base == "sym_first":  # from x = 0: faces, b read; x written
+            return 3 * s + s + s
         if base == "gs":  # x, faces read; b, x of the own colour read / written
             return s + 3 * s + 0.5 * s + 0.5 * s
         if base == "gs_first":  # faces, b of the own colour read; x written

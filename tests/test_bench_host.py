@@ -115,3 +115,16 @@ def test_more_than_one_gpu_is_refused(monkeypatch):
     with pytest.raises(SystemExit) as e:
         bench.main()
     assert e.value.code == 2
+
+
+def test_coarse_fused_sweep_byte_model():
+    """The coarse levels' fused sweep moves 5.5 s per cell (old second colour
+    s/2, three face arrays, b read; x written), against 2 x 5 s for the two
+    half-sweeps it replaces; its rows get a bandwidth in the kernel table."""
+    assert bench.bytes_per_cell("sym", 1, 4) == 22 and bench.bytes_per_cell("sym", 2, 8) == 44
+    assert bench.bytes_per_cell("sym_first", 1, 4) == 20
+    assert bench.bytes_per_cell("gs", 1, 4) == 20
+    N = 512 ** 3
+    table, _ = bench.kernel_table({"sym_L1_f32": (6.7, 45)}, 1, [5], 4, N)
+    row = table[0]
+    assert row[0] == "sym_L1_f32" and row[5] == 22 * (N // 8)
