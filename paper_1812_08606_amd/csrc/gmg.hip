@@ -2371,9 +2371,16 @@ int gmg_fmg(gmg_ctx* c, const double* v_dev, double* z_dev) {
 int gmg_face_flux_grad(gmg_ctx* c, const double* phi_dev, const double* lam_dev, double phi_bot, double phi_top,
                        double* dLda_dev) {
   if (!valid_ctx(c) || !phi_dev || !lam_dev || !dLda_dev) return GMG_ERR_ARG;
-  const Launch lc = col_launch(c->nx, c->ny, c->nz, 1 << 16);
-  GMG_LAUNCH(c, "face_grad", k_face_grad, lc, phi_dev, lam_dev, c->L.shapes[0].geom(), phi_bot, phi_top,
-             dLda_dev, lc.kc);
+  auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  if (c->nx % 2 == 0 && a16(phi_dev) && a16(lam_dev) && a16(dLda_dev)) {
+    const Launch lc = col_launch(c->nx / 2, c->ny, c->nz, 1 << 16);
+    GMG_LAUNCH(c, "face_grad", k_face_grad_pair, lc, phi_dev, lam_dev, c->L.shapes[0].geom(), phi_bot, phi_top,
+               dLda_dev, lc.kc);
+  } else {
+    const Launch lc = col_launch(c->nx, c->ny, c->nz, 1 << 16);
+    GMG_LAUNCH(c, "face_grad", k_face_grad, lc, phi_dev, lam_dev, c->L.shapes[0].geom(), phi_bot, phi_top,
+               dLda_dev, lc.kc);
+  }
   note(c, hipStreamSynchronize(c->stream));
   return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
 }
@@ -2390,8 +2397,16 @@ int launch_assemble(gmg_ctx* c, const double* ne_dev, const double* np_dev, cons
   if (c->ny > 65535 * BY) return GMG_ERR_SHAPE;
   const StepCoef p{prm->eps0_over_e, prm->tau_eff, prm->mu_e, prm->mu_p,
                    prm->De[0] / (c->hx * c->hx), prm->De[1] / (c->hy * c->hy), prm->De[2] / (c->hz * c->hz)};
-  const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
-  GMG_LAUNCH(c, "assemble_step", k_assemble_step, l, ne_dev, np_dev, c->L.shapes[0].geom(), p, a_dev, f_dev, l.kc);
+  auto a16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+  if (c->nx % 2 == 0 && a16(ne_dev) && a16(np_dev) && a16(a_dev) && a16(f_dev)) {
+    const Launch l = cell_launch(c->nx / 2, c->ny, c->nz, 8192, 8);
+    GMG_LAUNCH(c, "assemble_step", k_assemble_step_pair, l, ne_dev, np_dev, c->L.shapes[0].geom(), p, a_dev, f_dev,
+               l.kc);
+  } else {
+    const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
+    GMG_LAUNCH(c, "assemble_step", k_assemble_step, l, ne_dev, np_dev, c->L.shapes[0].geom(), p, a_dev, f_dev,
+               l.kc);
+  }
   return GMG_OK;
 }
 
@@ -2400,9 +2415,16 @@ int launch_field(gmg_ctx* c, const double* phi_dev, double phi_bot, double phi_t
   if (!phi_dev || !ex_dev || !ey_dev || !ez_dev || !emag_dev) return GMG_ERR_ARG;
   if (!std::isfinite(phi_bot) || !std::isfinite(phi_top)) return GMG_ERR_ARG;
   if (c->ny > 65535 * BY) return GMG_ERR_SHAPE;
-  const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
-  GMG_LAUNCH(c, "electric_field", k_electric_field, l, phi_dev, c->L.shapes[0].geom(), c->hx, c->hy, c->hz,
-             phi_bot, phi_top, ex_dev, ey_dev, ez_dev, emag_dev, l.kc);
+  auto a16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+  if (c->nx % 2 == 0 && a16(phi_dev) && a16(ex_dev) && a16(ey_dev) && a16(ez_dev) && a16(emag_dev)) {
+    const Launch l = cell_launch(c->nx / 2, c->ny, c->nz, 8192, 8);
+    GMG_LAUNCH(c, "electric_field", k_electric_field_pair, l, phi_dev, c->L.shapes[0].geom(), c->hx, c->hy, c->hz,
+               phi_bot, phi_top, ex_dev, ey_dev, ez_dev, emag_dev, l.kc);
+  } else {
+    const Launch l = cell_launch(c->nx, c->ny, c->nz, 8192, 8);
+    GMG_LAUNCH(c, "electric_field", k_electric_field, l, phi_dev, c->L.shapes[0].geom(), c->hx, c->hy, c->hz,
+               phi_bot, phi_top, ex_dev, ey_dev, ez_dev, emag_dev, l.kc);
+  }
   return GMG_OK;
 }
 

@@ -1136,6 +1136,77 @@ __global__ __launch_bounds__(NTHREADS) void k_face_grad(const double* __restrict
   }
 }
 
+// k_face_grad with one lane per x-pair (nx even): phi and lam of the pair
+// and of its y-neighbours as 16-byte loads, the x-neighbours outside the
+// pair from the adjacent lanes (the block's edge lanes load them), the same
+// arithmetic in the same order (a missing neighbour is the cell itself, so
+// its term is zero).  Lanes past the row's end run clamped, for the
+// exchange, and store nothing.
+__global__ __launch_bounds__(NTHREADS) void k_face_grad_pair(const double* __restrict__ phi,
+                                                             const double* __restrict__ lam, Geom g, double pb,
+                                                             double pt, double* __restrict__ out, int kc) {
+  const Tile tl = xcd_tile();
+  const int H = g.nx >> 1;
+  const int lane = threadIdx.x;
+  const int m = tl.x * BX + lane;
+  const bool act = m < H;
+  const int mm = act ? m : H - 1;
+  const bool hw = mm > 0, he = mm < H - 1;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  auto ld2 = [](const double* __restrict__ p, size_t c) { return *reinterpret_cast<const double2*>(p + c); };
+  for (int j = tl.y * BY + threadIdx.y; j < g.ny; j += gridDim.y * BY) {
+    const size_t ds = j > 0 ? sy : 0, dn = j < g.ny - 1 ? sy : 0;
+    size_t c = ((size_t)k0 * g.ny + j) * g.nx + 2 * mm;
+    double2 pc = ld2(phi, c), lc = ld2(lam, c);
+    double2 pbv = k0 > 0 ? ld2(phi, c - sz) : pc, lbv = k0 > 0 ? ld2(lam, c - sz) : lc;
+    for (int k = k0; k < k1; ++k, c += sz) {
+      const bool top = k == g.nz - 1;
+      const size_t ct = top ? c : c + sz;
+      const double2 ptv = ld2(phi, ct), ltv = ld2(lam, ct);
+      const double2 ps = ld2(phi, c - ds), ls = ld2(lam, c - ds), pn = ld2(phi, c + dn), ln = ld2(lam, c + dn);
+      double pw = __shfl_up(pc.y, 1, 64), lw = __shfl_up(lc.y, 1, 64);
+      double pe = __shfl_down(pc.x, 1, 64), le = __shfl_down(lc.x, 1, 64);
+      if (lane == 0 && hw) {
+        pw = phi[c - 1];
+        lw = lam[c - 1];
+      }
+      if (lane == BX - 1 && he) {
+        pe = phi[c + 2];
+        le = lam[c + 2];
+      }
+      if (!hw) {
+        pw = pc.x;
+        lw = lc.x;
+      }
+      if (!he) {
+        pe = pc.y;
+        le = lc.y;
+      }
+      auto cell = [&](double p0, double l0, double pwv, double lwv, double pev, double lev, double psv, double lsv,
+                      double pnv, double lnv, double pbc, double lbc, double ptc, double ltc) {
+        double s = (pwv - p0) * (lwv - l0) * g.ihx2;
+        s += (pev - p0) * (lev - l0) * g.ihx2;
+        s += (psv - p0) * (lsv - l0) * g.ihy2;
+        s += (pnv - p0) * (lnv - l0) * g.ihy2;
+        s += (pbc - p0) * (lbc - l0) * g.ihz2;  // zero at k = 0 (the cell itself)
+        s += (ptc - p0) * (ltc - l0) * g.ihz2;  // zero on the top layer
+        double gsum = -0.5 * s;
+        if (k == 0) gsum -= 2.0 * (p0 - pb) * l0 * g.ihz2;
+        if (top) gsum -= 2.0 * (p0 - pt) * l0 * g.ihz2;
+        return gsum;
+      };
+      const double g0 = cell(pc.x, lc.x, pw, lw, pc.y, lc.y, ps.x, ls.x, pn.x, ln.x, pbv.x, lbv.x, ptv.x, ltv.x);
+      const double g1 = cell(pc.y, lc.y, pc.x, lc.x, pe, le, ps.y, ls.y, pn.y, ln.y, pbv.y, lbv.y, ptv.y, ltv.y);
+      if (act) *reinterpret_cast<double2*>(out + c) = make_double2(g0, g1);
+      pbv = pc;
+      lbv = lc;
+      pc = ptv;
+      lc = ltv;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Setup kernels (hierarchy of face coefficients, float64).
 // ---------------------------------------------------------------------------
