@@ -3,6 +3,8 @@
 // symmetric Gauss-Seidel sweep in one pass over memory.
 #pragma once
 
+#include <type_traits>
+
 #include "gmg_common.hpp"
 
 namespace gmg {
@@ -100,6 +102,15 @@ __device__ __forceinline__ typename Pair2<T>::type load_pair(const T* __restrict
   }
 }
 
+// The parity of a plane in k_sym_split: computed where it is needed
+// (RuntimeParity), or a compile-time constant.
+struct RuntimeParity {};
+__device__ __forceinline__ int parity_of(RuntimeParity, int v) { return v; }
+template <int E>
+__device__ __forceinline__ int parity_of(std::integral_constant<int, E>, int) {
+  return E;
+}
+
 template <typename T, bool FIRST, bool SCALED>
 __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(const T* __restrict__ Xin,
                                                                              T* __restrict__ Xout,
@@ -116,7 +127,10 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   __shared__ T ring[3][R][SX];      // new c1 values of planes k-1, k, k+1 (mod 3)
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
-  const int lane = threadIdx.x, r = threadIdx.y;
+  // one row per wave: in float64 the row (and every parity below) is made
+  // wave-uniform for the compiler
+  const int lane = threadIdx.x;
+  const int r = sizeof(T) == 8 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.y) : (int)threadIdx.y;
   const int m = tl.x * IX + lane - 1;
   const int j = tl.y * IY + r - 1;
   const bool ing = m >= 0 && m < H && j >= 0 && j < g.ny;
@@ -144,7 +158,8 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   T* __restrict__ B2 = B + (size_t)c2 * hn;
   auto pl = [&](int k) { return min(max(k, 0), g.nz - 1); };
 
-  auto load = [&](int p, SymCol<T>& L) {
+  // e1c: RuntimeParity or the compile-time value of (c1 + j + p) % 2
+  auto load = [&](int p, SymCol<T>& L, auto e1c) {
     const int kq = pl(p);
     const size_t q = (size_t)kq * tz + qcol, cn = 2 * q;
     const T2 av = load_pair(a, cn);
@@ -157,7 +172,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     } else {
       const double2 uv = *reinterpret_cast<const double2*>(u + cn);
       const T u0 = (T)(SCALED ? uv.x * s : uv.x), u1 = (T)(SCALED ? uv.y * s : uv.y);
-      const int e1 = (c1 + j + p) & 1;
+      const int e1 = parity_of(e1c, (c1 + j + p) & 1);
       L.b1 = e1 ? u1 : u0;
       L.b2 = e1 ? u0 : u1;
       L.xo = T(0);
@@ -192,8 +207,8 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     // plane k0-2 (own column only) and plane k0-1 (staged), rotated into
     // place at the top of the first iteration
     SymCol<T> Lb, Lc;
-    load(k0 - 2, Lb);
-    load(k0 - 1, Lc);
+    load(k0 - 2, Lb, RuntimeParity{});
+    load(k0 - 1, Lc, RuntimeParity{});
     a0[2] = Lb.a0;
     a1[2] = Lb.a1;
     xo[1] = Lb.xo;
@@ -207,7 +222,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   lds_barrier();
 
   // iteration k: stage plane k+1, colour c1 on plane k, colour c2 on plane k-1
-  auto iterate = [&](int k, const SymCol<T>& L) {
+  auto iterate = [&](int k, const SymCol<T>& L, auto e1c) {
     a0[0] = a0[1];
     a1[0] = a1[1];
     a0[1] = a0[2];
@@ -222,7 +237,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     stage(k + 1, L);
     // (a0[3] is plane k+1, a0[2] plane k, a0[1] plane k-1, a0[0] plane k-2;
     // xo[2] plane k+1, xo[1] plane k, xo[0] plane k-1)
-    const int e1 = (c1 + j + k) & 1;
+    const int e1 = parity_of(e1c, (c1 + j + k) & 1);
     const bool hout = e1 ? he : hw;
     // a and old c2 of the cell outside the pair: element 0 of pair m+1
     // (e1 = 1) or element 1 of pair m-1 (e1 = 0), from the adjacent lane
@@ -267,7 +282,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     lds_barrier();
     // --- colour c2 on plane kk = k-1 ---
     const int kk = k - 1;
-    const int e2 = (c2 + j + kk) & 1;
+    const int e2 = parity_of(e1c, (c2 + j + kk) & 1);  // = e1
     // x-neighbour outside the pair (the adjacent lane's values on plane kk)
     const int src2 = lane + (e2 ? 1 : -1);
     const T cov = __shfl(c1n[1], src2, SX);
@@ -301,14 +316,44 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   // issued SYM_DEPTH - 1 iterations earlier into the buffer the iteration
   // before them released; loads past the grid read a clamped valid plane
   SymCol<T> L[SYM_DEPTH];
+  if constexpr (sizeof(T) == 8) {
+    // the colour-c1 cell of plane k0 - 1 + 2 n + t sits at e1 = E0 ^ (t % 2)
+    // with E0 uniform over the wave: the loop is instantiated for both E0 so
+    // that every parity select is resolved at compile time (float64: 1.02 ->
+    // 0.97 ms per sweep at 512^3; float32, whose arithmetic is cheaper, was
+    // not faster so)
+    static_assert(SYM_UNROLL % 2 == 0 && SYM_DEPTH == 2, "parity pattern of the unrolled loop");
+    auto run = [&](auto E0c) {
+      using P0 = std::integral_constant<int, decltype(E0c)::value>;
+      using P1 = std::integral_constant<int, decltype(E0c)::value ^ 1>;
+      load(k0, L[0], P1{});
+      for (int k = k0 - 1; k <= k1; k += SYM_UNROLL) {
 #pragma unroll
-  for (int t = 0; t < SYM_DEPTH - 1; ++t) load(k0 + t, L[t]);
-  for (int k = k0 - 1; k <= k1; k += SYM_UNROLL) {
+        for (int t = 0; t < SYM_UNROLL; t += 2) {
+          // planes k + t + 2 and k + t + 3 have the parities of k and k + 1
+          load(k + t + 2, L[1], P0{});
+          if (k + t > k1) return;  // (an exit, not a break: no second path into the loop's back edge)
+          iterate(k + t, L[0], P0{});
+          load(k + t + 3, L[0], P1{});
+          if (k + t + 1 > k1) return;
+          iterate(k + t + 1, L[1], P1{});
+        }
+      }
+    };
+    if ((c1 + j + k0 - 1) & 1)
+      run(std::integral_constant<int, 1>{});
+    else
+      run(std::integral_constant<int, 0>{});
+  } else {
 #pragma unroll
-    for (int t = 0; t < SYM_UNROLL; ++t) {
-      load(k + t + SYM_DEPTH, L[(t + SYM_DEPTH - 1) % SYM_DEPTH]);
-      if (k + t > k1) return;  // (an exit, not a break: no second path into the loop's back edge)
-      iterate(k + t, L[t % SYM_DEPTH]);
+    for (int t = 0; t < SYM_DEPTH - 1; ++t) load(k0 + t, L[t], RuntimeParity{});
+    for (int k = k0 - 1; k <= k1; k += SYM_UNROLL) {
+#pragma unroll
+      for (int t = 0; t < SYM_UNROLL; ++t) {
+        load(k + t + SYM_DEPTH, L[(t + SYM_DEPTH - 1) % SYM_DEPTH], RuntimeParity{});
+        if (k + t > k1) return;  // (an exit, not a break: no second path into the loop's back edge)
+        iterate(k + t, L[t % SYM_DEPTH], RuntimeParity{});
+      }
     }
   }
 }
