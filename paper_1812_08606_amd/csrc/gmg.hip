@@ -30,6 +30,9 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int MAX_RESTART = 32;
+// coarsest levels of more cells than this are inverted on the GPU
+// (Gauss-Jordan), smaller ones on the host (Cholesky)
+constexpr int GJ_MIN_CELLS = 1024;
 constexpr double BREAKDOWN_TOL = 1e-14;
 constexpr int CHEB_ARNOLDI = 10;  // Arnoldi steps of the Chebyshev bound estimate
 constexpr int CHEB_DEGREE = 2;    // degree of the Chebyshev smoothing polynomial
@@ -76,6 +79,7 @@ struct Layout {
   std::vector<LevelShape> shapes;
   std::vector<LevelOffsets> lv;
   size_t V, Z, a32, b0, xs, partials, scal, cinv, bargs, total;
+  size_t cgjm, cgjb;  // GPU inverse of a large coarsest level: float64 matrix (mixed), row / column buffers
   size_t cr0, cd0;  // Chebyshev smoother, finest level: float64 natural residual, T colour-split direction
   size_t rr;        // transpose restriction: residual of the level being restricted (finest: float64)
   size_t chs;       // Chebyshev smoother: device scalars of every level's bound estimate
@@ -179,6 +183,8 @@ int make_layout(int nx, int ny, int nz, double hx, double hy, double hz, const g
   L->scal = take((size_t)(L->m * (L->m + 2) + (L->m + 2) + 32) * 8);
   const size_t nc = last.n();
   L->cinv = take(nc * nc * L->tsize);
+  L->cgjm = nc > GJ_MIN_CELLS && mixed ? take(nc * nc * 8) : 0;
+  L->cgjb = nc > GJ_MIN_CELLS ? take(2 * nc * 8) : 0;
   L->bargs = take(sizeof(BottomArgs<double>));
   L->total = off;
   return GMG_OK;
@@ -455,6 +461,41 @@ void assemble_coarsest(const LevelShape& s, const std::vector<double>& wx, const
       }
 }
 
+// Inverse of the coarsest matrix M (n x n, SPD, row-major host copy) on the
+// GPU by in-place Gauss-Jordan elimination without pivoting (every pivot of
+// an SPD matrix is positive): n steps, each saving row and column k, then
+// updating every element.  O(n^3) work spread over the GPU instead of the
+// host's O(n^3) Cholesky inverse (about 20 s at n = 4096 on 8 host cores);
+// the result lands in cinv in the V-cycle precision.
+int gpu_inverse(gmg_ctx* c, const std::vector<double>& M, int n) {
+  const Layout& L = c->L;
+  double* A = c->mixed ? wsp<double>(c, L.cgjm) : wsp<double>(c, L.cinv);
+  double* rk = wsp<double>(c, L.cgjb);
+  double* ck = rk + n;
+  note(c, hipMemcpyAsync(A, M.data(), (size_t)n * n * 8, hipMemcpyHostToDevice, c->stream));
+  const Launch vl{dim3((unsigned)((n + 255) / 256)), dim3(256, 1, 1), 0};
+  const Launch ml{dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256, 1, 1), 0};
+  for (int k = 0; k < n; ++k) {
+    GMG_LAUNCH(c, "gj_save", k_gj_save, vl, (const double*)A, n, k, rk, ck);
+    GMG_LAUNCH(c, "gj_step", k_gj_step, ml, A, n, k, (const double*)rk, (const double*)ck);
+  }
+  // the diagonal of an SPD inverse is positive
+  GMG_LAUNCH(c, "gj_diag", k_gj_diag, vl, (const double*)A, n, rk);
+  std::vector<double> d(n);
+  note(c, hipMemcpyAsync(d.data(), rk, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  note(c, hipStreamSynchronize(c->stream));
+  if (c->err != hipSuccess) return GMG_ERR_HIP;
+  for (double v : d)
+    if (!(v > 0.0) || !std::isfinite(v)) return GMG_ERR_NONFINITE;
+  if (c->mixed) {
+    const size_t nn = (size_t)n * n;
+    GMG_LAUNCH(c, "convert_f64_f32", (k_convert<float, double>), flat_launch(nn), (const double*)A,
+               wsp<float>(c, L.cinv), nn);
+    note(c, hipStreamSynchronize(c->stream));
+  }
+  return c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP;
+}
+
 int build_hierarchy(gmg_ctx* c) {
   Layout& L = c->L;
   const int nl = (int)L.shapes.size();
@@ -531,6 +572,7 @@ int build_hierarchy(gmg_ctx* c) {
   note(c, hipStreamSynchronize(c->stream));
   if (c->err != hipSuccess) return GMG_ERR_HIP;
   assemble_coarsest(s, wx, wy, wz, tp, afine.data(), nl == 1, M);
+  if (n > GJ_MIN_CELLS) return gpu_inverse(c, M, n);
   if (!spd_inverse(M, n)) return GMG_ERR_NONFINITE;
   if (c->mixed) {
     std::vector<float> Mf(M.begin(), M.end());

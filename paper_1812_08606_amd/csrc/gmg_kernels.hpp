@@ -1207,6 +1207,40 @@ __global__ __launch_bounds__(NTHREADS) void k_face_grad_pair(const double* __res
   }
 }
 
+// In-place Gauss-Jordan inversion of an SPD matrix A (n x n, row-major),
+// step k: k_gj_save copies row k and column k, then k_gj_step updates every
+// element from the copies (pivot p = A[k][k]): A[k][k] = 1/p, row k / p,
+// column k / -p, A[i][j] -= A[i][k] A[k][j] / p elsewhere.  After steps 0 ..
+// n-1, A holds A^{-1}.  Grid of k_gj_step: x over columns, y over rows.
+__global__ __launch_bounds__(256) void k_gj_save(const double* __restrict__ A, int n, int k,
+                                                 double* __restrict__ rk, double* __restrict__ ck) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    rk[i] = A[(size_t)k * n + i];
+    ck[i] = A[(size_t)i * n + k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gj_step(double* __restrict__ A, int n, int k,
+                                                 const double* __restrict__ rk, const double* __restrict__ ck) {
+  const int j = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+  if (j >= n) return;
+  const double ip = 1.0 / rk[k];
+  double v;
+  if (i == k)
+    v = j == k ? ip : rk[j] * ip;
+  else if (j == k)
+    v = -ck[i] * ip;
+  else
+    v = A[(size_t)i * n + j] - ck[i] * (rk[j] * ip);
+  A[(size_t)i * n + j] = v;
+}
+
+__global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, int n, double* __restrict__ d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = A[(size_t)i * n + i];
+}
+
 // ---------------------------------------------------------------------------
 // Setup kernels (hierarchy of face coefficients, float64).
 // ---------------------------------------------------------------------------

@@ -453,6 +453,37 @@ def test_single_level_grid_breaks_down_happily():
     assert np.linalg.norm(b - apply_operator(npy(res.phi), a, h)) <= 1e-12 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("shape", [(15, 16, 17), (30, 32, 34)])
+def test_large_coarsest_level_inverted_on_gpu(shape):
+    """Coarsest levels of more than 1024 cells are inverted on the GPU
+    (Gauss-Jordan): a single-level grid of 4080 cells is solved in one
+    FGMRES step to 1e-12 (checked with the oracle's operator), a two-level
+    grid over that coarsest level gives the oracle's V-cycle (whose coarse
+    solve is a Cholesky solve), and the mixed solve converges."""
+    import time
+    print(f"large coarsest level {shape}", flush=True)
+    a, f, h = _rand_problem(shape, 41)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = gm.GMGPoisson(T(a), h=h, precision="fp64")
+    torch.cuda.synchronize()
+    nx, ny, nz = s.levels[-1]
+    print(f"  set-up {time.perf_counter() - t0:.2f} s, coarsest {nx} x {ny} x {nz}", flush=True)
+    assert nx * ny * nz == 4080
+    b = rhs(f, a, h, 0.2, 0.7)
+    if len(s.levels) == 1:
+        res = s.solve(T(f), 0.2, 0.7, tol=1e-12)
+        assert res.status == 0 and res.iterations == 1
+        assert np.linalg.norm(b - apply_operator(npy(res.phi), a, h)) <= 1e-12 * np.linalg.norm(b)
+    else:
+        hier = build_hierarchy(a, h)
+        assert rel(npy(s.vcycle(T(f))), vcycle(hier, f)) < 1e-10
+    sm = gm.GMGPoisson(T(a), h=h, precision="mixed")
+    res = sm.solve(T(f), 0.2, 0.7, tol=1e-10)
+    assert res.status == 0
+    assert np.linalg.norm(b - apply_operator(npy(res.phi), a, h)) <= 1e-10 * np.linalg.norm(b)
+
+
 def test_error_statuses():
     p = make_config(1, n=16)
     a = T(p.a)
