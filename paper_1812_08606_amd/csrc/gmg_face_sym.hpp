@@ -18,11 +18,12 @@ namespace gmg {
 template <typename T>
 struct FaceCol {
   T b1, b2;        // right sides of the c1 and the c2 cell
-  T ws1, ws2;      // their south faces
-  T wn1, wn2;      // their north faces (row j + 1's south faces)
+  T wy0, wy1;      // south faces of cells 2m and 2m + 1 (also staged: row j - 1's north faces)
+  T hwy0, hwy1;    // the same of row j + 1 (row R - 1 stages it for itself)
   T wb1, wb2;      // their bottom faces
   T tp1, tp2;      // their top-plate faces (last plane only)
-  T wx0, wx1, wxe; // x-faces: west of cell 2m, between the cells, east of 2m + 1
+  T wx0, wx1, wxe; // x-faces: west of cell 2m, between the cells, east of 2m + 1 (the last lane
+                   // of a wave loads wxe; the others take the next lane's wx0)
   T xo;            // old value of the c2 cell
   T hxo;           // old c2 value of the same column in the row beyond the block (rows 0 and R - 1)
 };
@@ -54,6 +55,10 @@ __global__ __launch_bounds__((FaceSymShape<T, WX>::W * FaceSymShape<T, WX>::R)) 
   constexpr int W = FaceSymShape<T, WX>::W, R = FaceSymShape<T, WX>::R, IY = FaceSymShape<T, WX>::IY;
   constexpr int NS = 2;  // planes of staged old values (c2 updates read only the ring)
   __shared__ T sx[NS][R + 2][W];  // old c2 values of block rows -1 .. R (array rows 0 .. R+1)
+  // south-face pairs of block rows 0 .. R (array rows 1 .. R+1): the north
+  // faces of rows -1 .. R-1; four planes, since the c2 update reads plane
+  // k-1's after the barrier while plane k+1's is staged
+  __shared__ T2 swy[4][R + 2][W];
   __shared__ T ring[3][R][W];     // new c1 values of planes k-1, k, k+1 (mod 3)
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
@@ -80,19 +85,22 @@ __global__ __launch_bounds__((FaceSymShape<T, WX>::W * FaceSymShape<T, WX>::R)) 
     const int kq = pl(p);
     const int e1 = (c1 + j + p) & 1;
     const size_t c = (size_t)kq * sz + ccol;
-    const T2 bv = load_pair(b, c), ws = load_pair(co.wy, c), wn = load_pair(co.wy, c + dn);
+    const T2 bv = load_pair(b, c), ws = load_pair(co.wy, c);
     const T2 wb = load_pair(co.wz, c), wx = load_pair(co.wx, c);
     L.b1 = e1 ? bv.y : bv.x;
     L.b2 = e1 ? bv.x : bv.y;
-    L.ws1 = e1 ? ws.y : ws.x;
-    L.ws2 = e1 ? ws.x : ws.y;
-    L.wn1 = e1 ? wn.y : wn.x;
-    L.wn2 = e1 ? wn.x : wn.y;
+    L.wy0 = ws.x;
+    L.wy1 = ws.y;
+    if (r == R - 1) {
+      const T2 hn2 = load_pair(co.wy, c + dn);
+      L.hwy0 = hn2.x;
+      L.hwy1 = hn2.y;
+    }
     L.wb1 = e1 ? wb.y : wb.x;
     L.wb2 = e1 ? wb.x : wb.y;
     L.wx0 = wx.x;
     L.wx1 = wx.y;
-    L.wxe = co.wx[c + de];
+    if ((m & 63) == 63) L.wxe = co.wx[c + de];
     if (kq == g.nz - 1) {
       const T2 tp = load_pair(co.tp, ccol);
       L.tp1 = e1 ? tp.y : tp.x;
@@ -108,6 +116,8 @@ __global__ __launch_bounds__((FaceSymShape<T, WX>::W * FaceSymShape<T, WX>::R)) 
     }
   };
   auto stage = [&](int p, const FaceCol<T>& L) {
+    swy[p & 3][r + 1][m] = T2{L.wy0, L.wy1};
+    if (r == R - 1) swy[p & 3][R + 1][m] = T2{L.hwy0, L.hwy1};
     if (!FIRST) {
       const int sl = p & (NS - 1);
       sx[sl][r + 1][m] = L.xo;
@@ -153,8 +163,11 @@ __global__ __launch_bounds__((FaceSymShape<T, WX>::W * FaceSymShape<T, WX>::R)) 
       else xw = sx[sl][r + 1][mw];     // cell 2m - 1 (pair m - 1)
     }
     const T xs = FIRST ? T(0) : sx[sl][r][m], xn = FIRST ? T(0) : sx[sl][r + 2][m];
-    const T v1 = update(k, e1, P1.b1, P1.ws1, P1.wn1, P1.wb1, top ? P1.tp1 : P2.wb2, P1.wx0, P1.wx1, P1.wxe, xw,
-                        xe, xs, xn, P0.xo, P2.xo, FIRST);
+    const bool wave_end = (m & 63) == 63;
+    const T wxe1 = __shfl_down(P1.wx0, 1, 64), wxe2 = __shfl_down(P0.wx0, 1, 64);
+    const T2 pn1 = swy[k & 3][r + 2][m];
+    const T v1 = update(k, e1, P1.b1, e1 ? P1.wy1 : P1.wy0, e1 ? pn1.y : pn1.x, P1.wb1, top ? P1.tp1 : P2.wb2, P1.wx0, P1.wx1,
+                        wave_end ? P1.wxe : wxe1, xw, xe, xs, xn, P0.xo, P2.xo, FIRST);
     if (owner && k >= k0 && k < k1) Xout[(size_t)k * sz + ccol + e1] = v1;
     c1n[0] = c1n[1];
     c1n[1] = c1n[2];
@@ -169,8 +182,10 @@ __global__ __launch_bounds__((FaceSymShape<T, WX>::W * FaceSymShape<T, WX>::R)) 
       const T yw = e2 ? c1n[1] : ring[rl][r][mw];
       const T ye = e2 ? ring[rl][r][me] : c1n[1];
       const bool ktop = kk >= g.nz - 1;
-      const T v2 = update(kk, e2, P0.b2, P0.ws2, P0.wn2, P0.wb2, ktop ? P0.tp2 : P1.wb1, P0.wx0, P0.wx1, P0.wxe, yw,
-                          ye, ring[rl][r - 1][m], ring[rl][r + 1][m], c1n[0], c1n[2], false);
+      const T2 pn2 = swy[kk & 3][r + 2][m];
+      const T v2 = update(kk, e2, P0.b2, e2 ? P0.wy1 : P0.wy0, e2 ? pn2.y : pn2.x, P0.wb2, ktop ? P0.tp2 : P1.wb1, P0.wx0, P0.wx1,
+                          wave_end ? P0.wxe : wxe2, yw, ye, ring[rl][r - 1][m], ring[rl][r + 1][m], c1n[0], c1n[2],
+                          false);
       Xout[(size_t)kk * sz + ccol + e2] = v2;
     }
   };
