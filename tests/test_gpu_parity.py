@@ -484,6 +484,52 @@ def test_large_coarsest_level_inverted_on_gpu(shape):
     assert np.linalg.norm(b - apply_operator(npy(res.phi), a, h)) <= 1e-10 * np.linalg.norm(b)
 
 
+def _offset(t):
+    """A contiguous copy of t whose storage starts 8 bytes past a 16-byte
+    boundary (the pair-lane kernels load 16-byte vectors; such buffers take
+    the one-cell kernels)."""
+    buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+    v = buf[1:].view(t.shape)
+    v.copy_(t)
+    assert v.data_ptr() % 16 == 8
+    return v
+
+
+def test_unaligned_buffers_take_the_one_cell_kernels():
+    """Caller buffers that are not 16-byte aligned (8 bytes past a
+    boundary): the solve (initial and true residuals), dL/da, the assembly of
+    a time step and E give what aligned buffers give, to rounding (the one-
+    cell kernels may contract products into FMAs differently, and the sums of
+    the residual norms run in another order)."""
+
+    def close(x, y):
+        assert x.data_ptr() != y.data_ptr()
+        assert (x - y).abs().max().item() <= 1e-14 * y.abs().max().item()
+
+    p = make_config(2, n=32)
+    a, f = T(p.a), T(p.f)
+    s = gm.GMGPoisson(a, precision="fp64")
+    r0 = s.solve(f, p.phi_bot, p.phi_top, tol=1e-10)
+    out = _offset(torch.zeros_like(f))
+    r1 = s.solve(_offset(f), p.phi_bot, p.phi_top, tol=1e-10, out=out)
+    assert r1.iterations == r0.iterations
+    assert rel(npy(r1.phi), npy(r0.phi)) < 1e-13
+    lam = s.solve(f * 0.5 + 1.0, 0.0, 0.0, tol=1e-10).phi
+    g0 = s.face_flux_grad(r0.phi, lam, p.phi_bot, p.phi_top)
+    g1 = s.face_flux_grad_into(_offset(r0.phi), _offset(lam), p.phi_bot, p.phi_top, _offset(torch.zeros_like(f)))
+    close(g1, g0)
+    ne, np_ = T(p.a) * 0.1, T(p.a) * 0.2
+    a0, f0 = s.assemble_elliptic(ne, np_, 1.0, 1e-3, 2.0, 0.5, De=(0.1, 0.2, 0.3))
+    a1, f1 = s.assemble_elliptic(_offset(ne), _offset(np_), 1.0, 1e-3, 2.0, 0.5, De=(0.1, 0.2, 0.3),
+                                 out=(_offset(a0), _offset(f0)))
+    close(a1, a0)
+    close(f1, f0)
+    e0 = s.electric_field(r0.phi, p.phi_bot, p.phi_top)
+    e1 = s.electric_field(_offset(r0.phi), p.phi_bot, p.phi_top, out=tuple(_offset(x) for x in e0))
+    for x, y in zip(e1, e0):
+        close(x, y)
+
+
 def test_error_statuses():
     p = make_config(1, n=16)
     a = T(p.a)
