@@ -1053,16 +1053,25 @@ void vcycle_fine_cheb(gmg_ctx* c, const double* u, const double* bscale, T* X) {
   smooth(false, c->opt.nu_post);
 }
 
+// Planes of the largest array a block of the fused sweep may address (the
+// natural-layout float64 u and a: 16 bytes per pair and plane) within the
+// 2^31 bytes of its 32-bit buffer offsets.
+inline long long sym_max_planes(const LevelShape& s) {
+  return (1LL << 31) / (16LL * (s.nx / 2) * s.ny);
+}
+
 // Launch of the fused symmetric sweep on the finest level: blocks of 64 x R
-// threads, about 2048 * 1024 threads in all, z-chunks of at least 8 planes.
+// threads, about 2048 * 1024 threads in all, z-chunks of at least 8 planes
+// (and at most sym_max_planes - 4: a block reads two planes below its chunk
+// and one above).
 template <typename T>
 Launch sym_launch(const LevelShape& s) {
   constexpr int SX = SymShape<T>::SX, R = SymShape<T>::R, IX = SymShape<T>::IX, IY = SymShape<T>::IY;
   const int gx = (s.nx / 2 + IX - 1) / IX, gy = (s.ny + IY - 1) / IY;
   const long long target = 2048LL * 1024 / (SX * R);
-  int kc = (int)std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
-  kc = std::min(kc, s.nz);
-  return Launch{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(SX, R, 1), kc};
+  long long kc = std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
+  kc = std::min<long long>({kc, s.nz, std::max<long long>(1, sym_max_planes(s) - 4)});
+  return Launch{dim3(gx, gy, (unsigned)((s.nz + kc - 1) / kc)), dim3(SX, R, 1), (int)kc};
 }
 
 // One fused symmetric sweep (k_sym_split) on the finest level: colour c1
@@ -1126,7 +1135,7 @@ void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z, bo
 template <typename T>
 bool sym_chosen(gmg_ctx* c) {
   const int fs = c->opt.fine_sweep;
-  return c->L.shapes.size() > 1 &&
+  return c->L.shapes.size() > 1 && sym_max_planes(c->L.shapes[0]) >= 5 &&
          (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(c->L.shapes[0]).kc >= 16));
 }
 template <typename T>

@@ -34,10 +34,13 @@ __device__ __forceinline__ void lds_barrier() {
 // puts the new values into an LDS ring, waits at a barrier, and updates c2
 // on plane k-1 from the new c1 values of planes k-2, k-1, k: its own column
 // from registers, rows j-1 and j+1 from LDS, the x-neighbour outside the
-// pair from the adjacent lane.  Planes k0-1 and k1 of the chunk are computed
-// (c1 only) for the same reason and not stored.  FIRST: the first sweep
-// from x = 0 (c1 = b / D; b from the natural-layout u times *bscale when
-// SCALED, stored by colour into B).
+// pair from the adjacent lane.  Each face joins one cell of either colour, so
+// the c2 update computes no face weight: it takes the six weights its c1
+// neighbours computed (kept in registers, passed through LDS with the c1
+// values, or from the adjacent lane).  Planes k0-1 and k1 of the chunk are
+// computed (c1 only) for the same reason and not stored.  FIRST: the first
+// sweep from x = 0 (c1 = b / D; b from the natural-layout u times *bscale
+// when SCALED, stored by colour into B).
 //
 // Each thread loads only its own column of every plane -- the coefficient
 // pair, the old colour-c2 value and the two right sides -- and stages the
@@ -55,21 +58,22 @@ __device__ __forceinline__ void lds_barrier() {
 // Float64 takes 12 rows: 1024 threads would leave too few registers per
 // thread (measured at 512^3: 1.16, 1.03 and 1.12 ms per sweep with 8, 12
 // and 16 rows, the last spilling).
+//
+// DEPTH: planes whose loads are in flight (the loads of iteration k+1 are
+// issued before iteration k runs); UNROLL: iterations per loop trip, a
+// multiple of DEPTH, so the load buffers rotate whole periods per trip and
+// no value still in flight is copied at the back edge (copying one makes the
+// compiler wait for every load).
 template <typename T>
 struct SymShape {
   static constexpr int SX = 64;
   static constexpr int R = sizeof(T) == 4 ? 16 : 12;
   static constexpr int IX = SX - 2;  // pairs per block row that the block owns
   static constexpr int IY = R - 2;   // rows the block owns
+  static constexpr int DEPTH = 2;
+  static constexpr int UNROLL = 4;
+  static_assert(UNROLL % DEPTH == 0, "the load buffers must rotate whole periods per trip");
 };
-// Planes whose loads are in flight (the loads of iteration k+1 are issued
-// before iteration k runs; a third buffer was slower), and iterations per
-// loop trip: a multiple of SYM_DEPTH, so the load buffers rotate whole
-// periods per trip and no value still in flight is copied at the back edge
-// (copying one makes the compiler wait for every load).
-constexpr int SYM_DEPTH = 2;
-constexpr int SYM_UNROLL = 4;
-static_assert(SYM_UNROLL % SYM_DEPTH == 0, "the load buffers must rotate whole periods per trip");
 
 template <typename T>
 struct SymCol {
@@ -102,6 +106,43 @@ __device__ __forceinline__ typename Pair2<T>::type load_pair(const T* __restrict
   }
 }
 
+// Raw buffer resource over `bytes` bytes from p (no stride, no swizzle).
+// Loads and stores through it add a per-lane byte offset and a wave-uniform
+// byte offset held in a scalar register, so a block marching the planes
+// computes each plane's offset once in scalar arithmetic rather than a
+// 64-bit address per lane and array.  Both offsets are 32-bit: the launch
+// keeps a block's planes within 2^31 bytes of its base.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, size_t bytes) {
+  const uint32_t n = bytes < 0xFFFFFFFFull ? (uint32_t)bytes : 0xFFFFFFFFu;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, (int)voff, (int)soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), rs,
+                                          (int)voff, (int)soff, 0);
+}
+// The coefficient pair at byte offset voff + soff: one 8-byte load in float32;
+// two loads in float64 (the caller's array is only 8-byte aligned).
+template <typename T>
+__device__ __forceinline__ typename Pair2<T>::type buf_load_pair(__amdgpu_buffer_rsrc_t rs, uint32_t voff,
+                                                                 uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+  } else {
+    return double2{buf_load<double>(rs, voff, soff), buf_load<double>(rs, voff + 8, soff)};
+  }
+}
+
 // The parity of a plane in k_sym_split: computed where it is needed
 // (RuntimeParity), or a compile-time constant.
 struct RuntimeParity {};
@@ -125,6 +166,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   __shared__ T2 sa[NS][R + 2][SX];  // a pairs of block rows -1 .. R (array rows 0 .. R+1)
   __shared__ T so[NS][R + 2][SX];   // old values of colour c2, same rows
   __shared__ T ring[3][R][SX];      // new c1 values of planes k-1, k, k+1 (mod 3)
+  __shared__ T2 ringw[3][R][SX];    // their south and north face weights, same planes
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
   // one row per wave: in float64 the row (and every parity below) is made
@@ -140,9 +182,10 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
   const double s = SCALED ? *bscale : 1.0;
   const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
-  // faces outside the pair (false for threads outside the grid, whose
-  // addresses are clamped to it)
-  const bool hw = m > 0 && m < H, he = m >= 0 && m < H - 1, hs = j > 0, hn_ = j < g.ny - 1;
+  // faces outside the pair: present when both cells lie in the grid (for
+  // threads outside it, whose addresses are clamped to it, every such face
+  // weight is zero)
+  const bool hw = m > 0 && m < H, he = m >= 0 && m < H - 1, hs = j > 0 && j < g.ny, hn_ = j >= 0 && j < g.ny - 1;
   // clamped (always valid) column of this thread, and of the row beyond the
   // block that rows 0 and R-1 stage (array row 0 or R+1)
   const int mm = min(max(m, 0), H - 1), jj = min(max(j, 0), g.ny - 1);
@@ -151,38 +194,51 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   const int jh = min(max(r == 0 ? j - 1 : j + 1, 0), g.ny - 1);
   const size_t qhcol = (size_t)jh * H + mm;
   const int arow = r == 0 ? 0 : R + 1;
-  const T* __restrict__ Xo = Xin + (size_t)c2 * hn;  // old values of colour c2
-  T* __restrict__ Y1 = Xout + (size_t)c1 * hn;
-  T* __restrict__ Y2 = Xout + (size_t)c2 * hn;
-  T* __restrict__ B1 = B + (size_t)c1 * hn;
-  T* __restrict__ B2 = B + (size_t)c2 * hn;
   auto pl = [&](int k) { return min(max(k, 0), g.nz - 1); };
+  // every array is addressed from plane kb, the lowest the block reads, with
+  // per-lane byte offsets of the column (colour arrays: ST per pair; a and the
+  // natural-layout u: two cells per pair) and a scalar offset per plane
+  const int kb = pl(k0 - 2);
+  const size_t pb = (size_t)kb * tz;  // first pair of plane kb
+  constexpr uint32_t ST = sizeof(T);
+  const size_t cbytes = (hn - pb) * ST, nbytes = 2 * (hn - pb) * ST;
+  // (Xin is not read by the first sweep, u only by it)
+  const auto rXo = buf_rsrc(FIRST ? nullptr : Xin + (size_t)c2 * hn + pb, FIRST ? 0 : cbytes);  // old colour c2
+  const auto rY1 = buf_rsrc(Xout + (size_t)c1 * hn + pb, cbytes);
+  const auto rY2 = buf_rsrc(Xout + (size_t)c2 * hn + pb, cbytes);
+  const auto rB1 = buf_rsrc(B + (size_t)c1 * hn + pb, cbytes);
+  const auto rB2 = buf_rsrc(B + (size_t)c2 * hn + pb, cbytes);
+  const auto rA = buf_rsrc(a + 2 * pb, nbytes);
+  const auto rU = buf_rsrc(FIRST ? u + 2 * pb : nullptr, FIRST ? 2 * (hn - pb) * sizeof(double) : 0);
+  const uint32_t vq = (uint32_t)qcol * ST, vqh = (uint32_t)qhcol * ST;
+  const uint32_t ptb = (uint32_t)tz * ST;  // bytes per plane of a colour array
+  auto soff = [&](int k) { return (uint32_t)(k - kb) * ptb; };
 
   // e1c: RuntimeParity or the compile-time value of (c1 + j + p) % 2
   auto load = [&](int p, SymCol<T>& L, auto e1c) {
-    const int kq = pl(p);
-    const size_t q = (size_t)kq * tz + qcol, cn = 2 * q;
-    const T2 av = load_pair(a, cn);
+    const uint32_t so1 = soff(pl(p));
+    const T2 av = buf_load_pair<T>(rA, 2 * vq, 2 * so1);
     L.a0 = av.x;
     L.a1 = av.y;
     if (!FIRST) {
-      L.xo = Xo[q];
-      L.b1 = B1[q];
-      L.b2 = B2[q];
+      L.xo = buf_load<T>(rXo, vq, so1);
+      L.b1 = buf_load<T>(rB1, vq, so1);
+      L.b2 = buf_load<T>(rB2, vq, so1);
     } else {
-      const double2 uv = *reinterpret_cast<const double2*>(u + cn);
-      const T u0 = (T)(SCALED ? uv.x * s : uv.x), u1 = (T)(SCALED ? uv.y * s : uv.y);
+      constexpr uint32_t W = sizeof(double) / ST;  // u bytes per colour-array byte, per cell pair
+      const double u0d = buf_load<double>(rU, 2 * W * vq, 2 * W * so1);
+      const double u1d = buf_load<double>(rU, 2 * W * vq + 8, 2 * W * so1);
+      const T u0 = (T)(SCALED ? u0d * s : u0d), u1 = (T)(SCALED ? u1d * s : u1d);
       const int e1 = parity_of(e1c, (c1 + j + p) & 1);
       L.b1 = e1 ? u1 : u0;
       L.b2 = e1 ? u0 : u1;
       L.xo = T(0);
     }
     if (hrow) {
-      const size_t qh = (size_t)kq * tz + qhcol;
-      const T2 hv = load_pair(a, 2 * qh);
+      const T2 hv = buf_load_pair<T>(rA, 2 * vqh, 2 * so1);
       L.ha0 = hv.x;
       L.ha1 = hv.y;
-      L.hxo = FIRST ? T(0) : Xo[qh];
+      L.hxo = FIRST ? T(0) : buf_load<T>(rXo, vqh, so1);
     }
   };
   auto stage = [&](int p, const SymCol<T>& L) {
@@ -195,13 +251,16 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     }
   };
 
-  // registers: a of the pair on planes k-2 .. k+1, old c2 of the column on
+  // registers: a of the pair on planes k-1 .. k+1, old c2 of the column on
   // k-1 .. k+1, new c1 of the column on k-2 .. k; right sides: c1 and c2 of
-  // plane k (cb1, cb2), c2 of plane k-1 (pb2)
-  T a0[4], a1[4], xo[3], c1n[3], cb1, cb2, pb2 = T(0);
+  // plane k (cb1, cb2), c2 of plane k-1 (pb2); face weights of the column's
+  // c1 cell: inner and outer x-faces on plane k-1 (wip, wop), top faces on
+  // planes k-1 and k-2 (wtp, wtpp)
+  T a0[3], a1[3], xo[3], c1n[3], cb1, cb2, pb2 = T(0);
+  T wip = T(0), wop = T(0), wtp = T(0), wtpp = T(0);
 #pragma unroll
   for (int t = 0; t < 3; ++t) c1n[t] = T(0);
-  a0[0] = a1[0] = a0[1] = a1[1] = T(0);
+  a0[0] = a1[0] = T(0);
   xo[0] = T(0);
   {
     // plane k0-2 (own column only) and plane k0-1 (staged), rotated into
@@ -209,11 +268,11 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     SymCol<T> Lb, Lc;
     load(k0 - 2, Lb, RuntimeParity{});
     load(k0 - 1, Lc, RuntimeParity{});
-    a0[2] = Lb.a0;
-    a1[2] = Lb.a1;
+    a0[1] = Lb.a0;
+    a1[1] = Lb.a1;
     xo[1] = Lb.xo;
-    a0[3] = Lc.a0;
-    a1[3] = Lc.a1;
+    a0[2] = Lc.a0;
+    a1[2] = Lc.a1;
     xo[2] = Lc.xo;
     cb1 = Lc.b1;
     cb2 = Lc.b2;
@@ -221,115 +280,115 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   }
   lds_barrier();
 
-  // iteration k: stage plane k+1, colour c1 on plane k, colour c2 on plane k-1
+  // iteration k: stage plane k+1, colour c1 on plane k, colour c2 on plane k-1.
+  // Every face joins a c1 and a c2 cell, so the c2 update takes all six face
+  // weights from the c1 updates: inner and outer x-faces from its pair's and
+  // the adjacent lane's c1 cell on plane k-1, the y-faces from rows j-1 and
+  // j+1 on plane k-1 (LDS), the z-faces from the column's c1 cells on planes
+  // k-2 and k.
   auto iterate = [&](int k, const SymCol<T>& L, auto e1c) {
     a0[0] = a0[1];
     a1[0] = a1[1];
     a0[1] = a0[2];
     a1[1] = a1[2];
-    a0[2] = a0[3];
-    a1[2] = a1[3];
-    a0[3] = L.a0;
-    a1[3] = L.a1;
+    a0[2] = L.a0;
+    a1[2] = L.a1;
     xo[0] = xo[1];
     xo[1] = xo[2];
     xo[2] = L.xo;
     stage(k + 1, L);
-    // (a0[3] is plane k+1, a0[2] plane k, a0[1] plane k-1, a0[0] plane k-2;
-    // xo[2] plane k+1, xo[1] plane k, xo[0] plane k-1)
+    // (a0[2] is plane k+1, a0[1] plane k, a0[0] plane k-1; xo[2] plane k+1,
+    // xo[1] plane k, xo[0] plane k-1)
     const int e1 = parity_of(e1c, (c1 + j + k) & 1);
     const bool hout = e1 ? he : hw;
     // a and old c2 of the cell outside the pair: element 0 of pair m+1
     // (e1 = 1) or element 1 of pair m-1 (e1 = 0), from the adjacent lane
     const int src = lane + (e1 ? 1 : -1);
-    const T aout = __shfl(e1 ? a0[2] : a1[2], src, SX);
+    const T aout = __shfl(e1 ? a0[1] : a1[1], src, SX);
     const T xout = __shfl(xo[1], src, SX);
-    T v1;
+    T v1, wi, wo, wb, wt;
     {
       const int sl = k & (NS - 1);
       const T2 ps = sa[sl][r][lane], pn = sa[sl][r + 2][lane];
       const bool top = k >= g.nz - 1, bot = k <= 0;
-      const T acv = e1 ? a1[2] : a0[2], ain = e1 ? a0[2] : a1[2];
-      const T abv = e1 ? a1[1] : a0[1], atv = e1 ? a1[3] : a0[3];
-      const T wi = (acv + ain) * hx;
-      const T wo = hout ? (acv + aout) * hx : T(0);
+      const T acv = e1 ? a1[1] : a0[1], ain = e1 ? a0[1] : a1[1];
+      const T abv = e1 ? a1[0] : a0[0], atv = e1 ? a1[2] : a0[2];
+      wi = (acv + ain) * hx;
+      wo = hout ? (acv + aout) * hx : T(0);
       const T ws = hs ? (acv + (e1 ? ps.y : ps.x)) * hy : T(0);
       const T wn = hn_ ? (acv + (e1 ? pn.y : pn.x)) * hy : T(0);
-      const T wb = !bot ? (acv + abv) * hz : T(0);
-      const T wt = !top ? (acv + atv) * hz : T(0);
+      wb = (acv + abv) * hz;
+      wt = (acv + atv) * hz;
       const T D = wi + wo + ws + wn + (!bot ? wb : pz * acv) + (!top ? wt : pz * acv);
       if (FIRST) {
         v1 = cb1 * recip(D);
       } else {
+        // (absent faces have zero weight and finite neighbour values)
         const T xs = so[sl][r][lane], xn = so[sl][r + 2][lane];
-        const T off = wi * xo[1] + (hout ? wo * xout : T(0)) + (hs ? ws * xs : T(0)) + (hn_ ? wn * xn : T(0)) +
-                      (!bot ? wb * xo[0] : T(0)) + (!top ? wt * xo[2] : T(0));
+        const T off = wi * xo[1] + wo * xout + ws * xs + wn * xn + (!bot ? wb * xo[0] : T(0)) +
+                      (!top ? wt * xo[2] : T(0));
         v1 = (cb1 + off) * recip(D);
       }
       if (owner && k >= k0 && k < k1) {
-        const size_t q = (size_t)k * tz + qcol;
-        Y1[q] = v1;
+        const uint32_t so1 = soff(k);
+        buf_store<T>(v1, rY1, vq, so1);
         if (FIRST) {
-          B1[q] = cb1;
-          B2[q] = cb2;
+          buf_store<T>(cb1, rB1, vq, so1);
+          buf_store<T>(cb2, rB2, vq, so1);
         }
       }
+      ringw[(k + 3) % 3][r][lane] = T2{ws, wn};
     }
     c1n[0] = c1n[1];
     c1n[1] = c1n[2];
     c1n[2] = v1;
     ring[(k + 3) % 3][r][lane] = v1;
     lds_barrier();
-    // --- colour c2 on plane kk = k-1 ---
+    // --- colour c2 on plane kk = k-1 (element e1 of the pair) ---
     const int kk = k - 1;
-    const int e2 = parity_of(e1c, (c2 + j + kk) & 1);  // = e1
-    // x-neighbour outside the pair (the adjacent lane's values on plane kk)
-    const int src2 = lane + (e2 ? 1 : -1);
+    // the adjacent lane's new c1 value and outer x-face on plane kk
+    const int src2 = lane + (e1 ? 1 : -1);
     const T cov = __shfl(c1n[1], src2, SX);
-    const T aov = __shfl(e2 ? a0[1] : a1[1], src2, SX);
+    const T wov = __shfl(wop, src2, SX);
     if (owner && kk >= k0 && kk < k1) {
-      const int sl = kk & (NS - 1);
-      const T2 ps = sa[sl][r][lane], pn = sa[sl][r + 2][lane];
       const bool top = kk == g.nz - 1, bot = kk == 0;
-      const bool ho = e2 ? he : hw;
-      const T acv = e2 ? a1[1] : a0[1], ain = e2 ? a0[1] : a1[1];
-      const T abv = e2 ? a1[0] : a0[0], atv = e2 ? a1[2] : a0[2];
-      const T wi = (acv + ain) * hx;
-      const T wo = ho ? (acv + aov) * hx : T(0);
-      const T ws = hs ? (acv + (e2 ? ps.y : ps.x)) * hy : T(0);
-      const T wn = hn_ ? (acv + (e2 ? pn.y : pn.x)) * hy : T(0);
-      const T wb = !bot ? (acv + abv) * hz : T(0);
-      const T wt = !top ? (acv + atv) * hz : T(0);
-      const T D = wi + wo + ws + wn + (!bot ? wb : pz * acv) + (!top ? wt : pz * acv);
       const int rl = (kk + 3) % 3;
       const T ys = ring[rl][r - 1][lane], yn = ring[rl][r + 1][lane];
-      const T off = wi * c1n[1] + (ho ? wo * cov : T(0)) + (hs ? ws * ys : T(0)) + (hn_ ? wn * yn : T(0)) +
-                    (!bot ? wb * c1n[0] : T(0)) + (!top ? wt * c1n[2] : T(0));
-      Y2[(size_t)kk * tz + qcol] = (pb2 + off) * recip(D);
+      const T wsv = ringw[rl][r - 1][lane].y, wnv = ringw[rl][r + 1][lane].x;
+      const T acv = e1 ? a1[0] : a0[0];
+      const T D = wip + wov + wsv + wnv + (!bot ? wtpp : pz * acv) + (!top ? wb : pz * acv);
+      const T off = wip * c1n[1] + wov * cov + wsv * ys + wnv * yn + (!bot ? wtpp * c1n[0] : T(0)) +
+                    (!top ? wb * c1n[2] : T(0));
+      buf_store<T>((pb2 + off) * recip(D), rY2, vq, soff(kk));
     }
+    wtpp = wtp;
+    wtp = wt;
+    wip = wi;
+    wop = wo;
     pb2 = cb2;
     cb1 = L.b1;
     cb2 = L.b2;
   };
 
-  // SYM_DEPTH load buffers: iteration k consumes plane k+1, whose loads were
-  // issued SYM_DEPTH - 1 iterations earlier into the buffer the iteration
-  // before them released; loads past the grid read a clamped valid plane
-  SymCol<T> L[SYM_DEPTH];
+  // DEPTH load buffers: iteration k consumes plane k+1, whose loads were
+  // issued DEPTH - 1 iterations earlier into the buffer the iteration before
+  // them released; loads past the grid read a clamped valid plane
+  constexpr int DEPTH = SymShape<T>::DEPTH, UNROLL = SymShape<T>::UNROLL;
+  SymCol<T> L[DEPTH];
   if constexpr (sizeof(T) == 8) {
     // the colour-c1 cell of plane k0 - 1 + 2 n + t sits at e1 = E0 ^ (t % 2)
     // with E0 uniform over the wave: the loop is instantiated for both E0 so
     // that every parity select is resolved at compile time (float64: 1.02 ->
     // 0.97 ms per sweep at 512^3; float32, whose arithmetic is cheaper, was
     // not faster so)
-    static_assert(SYM_UNROLL % 2 == 0 && SYM_DEPTH == 2, "parity pattern of the unrolled loop");
+    static_assert(UNROLL % 2 == 0 && DEPTH == 2, "parity pattern of the unrolled loop");
     auto run = [&](auto E0c) {
       using P0 = std::integral_constant<int, decltype(E0c)::value>;
       using P1 = std::integral_constant<int, decltype(E0c)::value ^ 1>;
       load(k0, L[0], P1{});
-      for (int k = k0 - 1; k <= k1; k += SYM_UNROLL) {
+      for (int k = k0 - 1; k <= k1; k += UNROLL) {
 #pragma unroll
-        for (int t = 0; t < SYM_UNROLL; t += 2) {
+        for (int t = 0; t < UNROLL; t += 2) {
           // planes k + t + 2 and k + t + 3 have the parities of k and k + 1
           load(k + t + 2, L[1], P0{});
           if (k + t > k1) return;  // (an exit, not a break: no second path into the loop's back edge)
@@ -346,13 +405,13 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
       run(std::integral_constant<int, 0>{});
   } else {
 #pragma unroll
-    for (int t = 0; t < SYM_DEPTH - 1; ++t) load(k0 + t, L[t], RuntimeParity{});
-    for (int k = k0 - 1; k <= k1; k += SYM_UNROLL) {
+    for (int t = 0; t < DEPTH - 1; ++t) load(k0 + t, L[t], RuntimeParity{});
+    for (int k = k0 - 1; k <= k1; k += UNROLL) {
 #pragma unroll
-      for (int t = 0; t < SYM_UNROLL; ++t) {
-        load(k + t + SYM_DEPTH, L[(t + SYM_DEPTH - 1) % SYM_DEPTH], RuntimeParity{});
+      for (int t = 0; t < UNROLL; ++t) {
+        load(k + t + DEPTH, L[(t + DEPTH - 1) % DEPTH], RuntimeParity{});
         if (k + t > k1) return;  // (an exit, not a break: no second path into the loop's back edge)
-        iterate(k + t, L[t % SYM_DEPTH], RuntimeParity{});
+        iterate(k + t, L[t % DEPTH], RuntimeParity{});
       }
     }
   }
