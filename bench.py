@@ -133,6 +133,8 @@ def bytes_per_cell(base, level, s, nu_post=2):
             return 0.5 * s + s + s + s
         if base == "sym_first":  # from x = 0: u (float64) and a read; B and X (both colours) written
             return 8 + s + s + s
+        if base == "sym_resid":  # fused symmetric sweep and its residual restricted: + coarse right side (1/8)
+            return 0.5 * s + s + s + s + s / 8
         if base == "gs":  # X of the other colour, a, B of the own colour read; X own colour written
             return 0.5 * s + s + 0.5 * s + 0.5 * s
         if base == "gs_first":  # u (float64) and a read; B (both colours) and X (own colour) written

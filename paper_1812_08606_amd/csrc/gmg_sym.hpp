@@ -49,30 +49,48 @@ __device__ __forceinline__ void lds_barrier() {
 // block): 4 loads per thread and plane, each cache line requested once per
 // block.  (Loading the side rows from global memory as well, 14 loads per
 // thread and plane with every line requested by three rows, took 0.66-0.70
-// ms per sweep at 512^3 against 0.50 ms.)  LDS holds NS = 4 planes of side
-// values: plane k+1 is staged at iteration k, read at iterations k+1 and
-// k+2, and its slot is rewritten four iterations later, after two barriers.
+// ms per sweep at 512^3 against 0.50 ms.)  LDS holds NS = 2 planes of side
+// values: plane k+1 is staged at iteration k (after every wave has passed
+// the barrier that ends iteration k-1's c1 update, the slot's last reader)
+// and read at iteration k+1.
+//
+// RESID: the block also forms the residual b - A x of the result and its
+// mean over each 2 x 2 x 2 cell group, the right side bc of level 1 (the
+// values of k_resid_restrict_split to rounding, formed as it forms them:
+// b minus the face fluxes w (x - x_nb) in the same order).  Iteration k
+// takes plane k-2, whose values are final once c2 of plane k-1 is: the c2
+// cell's residual is formed in its update (its equation was just solved
+// with the final c1 neighbours: rounding only); the c1 cell's from the
+// weights and right side its update used two planes earlier and the new c2
+// values around it (own column from registers, rows j-1, j+1 from an LDS
+// ring, the outer x-neighbour from the adjacent lane).  Pairs of planes
+// add in registers, pairs of rows (waves r, r+1) through LDS.  A residual
+// needs the final values one cell beyond it, so the block updates c1 and c2
+// one lane, row and plane further and owns (SX - 4) x (R - 4) pairs.
 //
 // Block shape: SX = 64 lanes per row (one row per wave; 32-lane rows were
 // measured slower) times R rows; the block owns (SX - 2) x (R - 2) pairs.
 // Float64 takes 12 rows: 1024 threads would leave too few registers per
 // thread (measured at 512^3: 1.16, 1.03 and 1.12 ms per sweep with 8, 12
-// and 16 rows, the last spilling).
+// and 16 rows, the last spilling).  The residual variant runs in float32
+// (126 registers at 1024 threads).
 //
 // DEPTH: planes whose loads are in flight (the loads of iteration k+1 are
 // issued before iteration k runs); UNROLL: iterations per loop trip, a
 // multiple of DEPTH, so the load buffers rotate whole periods per trip and
 // no value still in flight is copied at the back edge (copying one makes the
 // compiler wait for every load).
-template <typename T>
+template <typename T, bool RESID = false>
 struct SymShape {
   static constexpr int SX = 64;
   static constexpr int R = sizeof(T) == 4 ? 16 : 12;
-  static constexpr int IX = SX - 2;  // pairs per block row that the block owns
-  static constexpr int IY = R - 2;   // rows the block owns
+  static constexpr int HALO = RESID ? 2 : 1;  // lanes and rows on each side the block does not own
+  static constexpr int IX = SX - 2 * HALO;    // pairs per block row that the block owns
+  static constexpr int IY = R - 2 * HALO;     // rows the block owns
   static constexpr int DEPTH = 2;
   static constexpr int UNROLL = 4;
   static_assert(UNROLL % DEPTH == 0, "the load buffers must rotate whole periods per trip");
+  static_assert(IY % 2 == 0, "a block owns whole coarse rows");
 };
 
 template <typename T>
@@ -152,36 +170,47 @@ __device__ __forceinline__ int parity_of(std::integral_constant<int, E>, int) {
   return E;
 }
 
-template <typename T, bool FIRST, bool SCALED>
-__global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(const T* __restrict__ Xin,
-                                                                             T* __restrict__ Xout,
-                                                                             T* __restrict__ B,
-                                                                             const double* __restrict__ u,
-                                                                             const double* __restrict__ bscale,
-                                                                             const T* __restrict__ a, Geom g,
-                                                                             size_t hn, int kc, int c1) {
+template <typename T, bool FIRST, bool SCALED, bool RESID>
+__global__ __launch_bounds__((SymShape<T, RESID>::SX * SymShape<T, RESID>::R)) void k_sym_split(
+    const T* __restrict__ Xin, T* __restrict__ Xout, T* __restrict__ B, const double* __restrict__ u,
+    const double* __restrict__ bscale, const T* __restrict__ a, Geom g, size_t hn, int kc, int c1,
+    T* __restrict__ bc) {
+  static_assert(!(FIRST && RESID), "the residual is fused into a sweep from a guess only");
   using T2 = typename Pair2<T>::type;
-  constexpr int SX = SymShape<T>::SX, IX = SymShape<T>::IX, R = SymShape<T>::R, IY = SymShape<T>::IY;
-  constexpr int NS = 4;              // planes of side values held in LDS
+  using S = SymShape<T, RESID>;
+  constexpr int SX = S::SX, IX = S::IX, R = S::R, IY = S::IY, HALO = S::HALO;
+  constexpr int NS = 2;              // planes of side values held in LDS
   __shared__ T2 sa[NS][R + 2][SX];  // a pairs of block rows -1 .. R (array rows 0 .. R+1)
   __shared__ T so[NS][R + 2][SX];   // old values of colour c2, same rows
-  __shared__ T ring[3][R][SX];      // new c1 values of planes k-1, k, k+1 (mod 3)
-  __shared__ T2 ringw[3][R][SX];    // their south and north face weights, same planes
+  __shared__ T ring[4][R][SX];      // new c1 values of planes k-3 .. k (mod 4)
+  __shared__ T2 ringw[4][R][SX];    // their south and north face weights, same planes
+  // RESID: new c2 values of planes k-2, k-1 (mod 2) and the odd rows' halves
+  // of the restricted residual
+  __shared__ T ring2[RESID ? 2 : 1][RESID ? R : 1][SX];
+  __shared__ T part[RESID ? R : 1][SX];
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
   // one row per wave: in float64 the row (and every parity below) is made
   // wave-uniform for the compiler
   const int lane = threadIdx.x;
   const int r = sizeof(T) == 8 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.y) : (int)threadIdx.y;
-  const int m = tl.x * IX + lane - 1;
-  const int j = tl.y * IY + r - 1;
+  const int m = tl.x * IX + lane - HALO;
+  const int j = tl.y * IY + r - HALO;
   const bool ing = m >= 0 && m < H && j >= 0 && j < g.ny;
-  const bool owner = ing && lane >= 1 && lane <= IX && r >= 1 && r <= IY;
+  const bool owner = ing && lane >= HALO && lane < SX - HALO && r >= HALO && r < R - HALO;
+  // colour c2 is updated one lane and row inside the block's edge (where all
+  // its c1 neighbours are), on the chunk's planes and, for the residual, on
+  // the planes next to it
+  const bool calc2 = ing && lane >= 1 && lane <= SX - 2 && r >= 1 && r <= R - 2;
   const int c2 = 1 - c1;
   const size_t tz = (size_t)H * g.ny;
   const T hx = (T)(0.5 * g.ihx2), hy = (T)(0.5 * g.ihy2), hz = (T)(0.5 * g.ihz2), pz = (T)(2.0 * g.ihz2);
   const double s = SCALED ? *bscale : 1.0;
   const int k0 = tl.z * kc, k1 = min(g.nz, k0 + kc);
+  const int c2lo = RESID ? max(k0 - 1, 0) : k0, c2hi = RESID ? min(k1 + 1, g.nz) : k1;
+  // iterations kstart .. kend update c1 on plane k, c2 on plane k-1 and (RESID)
+  // take the residual of plane k-2
+  const int kstart = k0 - HALO, kend = k1 + HALO - 1;
   // faces outside the pair: present when both cells lie in the grid (for
   // threads outside it, whose addresses are clamped to it, every such face
   // weight is zero)
@@ -198,7 +227,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   // every array is addressed from plane kb, the lowest the block reads, with
   // per-lane byte offsets of the column (colour arrays: ST per pair; a and the
   // natural-layout u: two cells per pair) and a scalar offset per plane
-  const int kb = pl(k0 - 2);
+  const int kb = pl(kstart - 1);
   const size_t pb = (size_t)kb * tz;  // first pair of plane kb
   constexpr uint32_t ST = sizeof(T);
   const size_t cbytes = (hn - pb) * ST, nbytes = 2 * (hn - pb) * ST;
@@ -252,22 +281,29 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   };
 
   // registers: a of the pair on planes k-1 .. k+1, old c2 of the column on
-  // k-1 .. k+1, new c1 of the column on k-2 .. k; right sides: c1 and c2 of
+  // k-1 .. k+1, new c1 of the column on k-3 .. k; right sides: c1 and c2 of
   // plane k (cb1, cb2), c2 of plane k-1 (pb2); face weights of the column's
   // c1 cell: inner and outer x-faces on plane k-1 (wip, wop), top faces on
-  // planes k-1 and k-2 (wtp, wtpp)
-  T a0[3], a1[3], xo[3], c1n[3], cb1, cb2, pb2 = T(0);
+  // planes k-1 and k-2 (wtp, wtpp).  RESID: new c2 of the column on k-3 ..
+  // k-1 (c2h), and of the c1 cell on planes k-2 .. k its right side, plate
+  // coefficient (2 a / hz^2) and inner, outer x-, bottom and top face weights
+  // (index 0: plane k-2)
+  T a0[3], a1[3], xo[3], c1n[4], cb1, cb2, pb2 = T(0);
   T wip = T(0), wop = T(0), wtp = T(0), wtpp = T(0);
+  T c2h[3], hb1[3], hdz[3], hwi[3], hwo[3], hwb[3], hwt[3];
+  T r2p = T(0), accz = T(0);  // RESID: residual of the c2 cell on plane k-2; coarse-plane sum
 #pragma unroll
-  for (int t = 0; t < 3; ++t) c1n[t] = T(0);
+  for (int t = 0; t < 3; ++t) c2h[t] = hb1[t] = hdz[t] = hwi[t] = hwo[t] = hwb[t] = hwt[t] = T(0);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) c1n[t] = T(0);
   a0[0] = a1[0] = T(0);
   xo[0] = T(0);
   {
-    // plane k0-2 (own column only) and plane k0-1 (staged), rotated into
-    // place at the top of the first iteration
+    // plane kstart-1 (own column only) and plane kstart (staged), rotated
+    // into place at the top of the first iteration
     SymCol<T> Lb, Lc;
-    load(k0 - 2, Lb, RuntimeParity{});
-    load(k0 - 1, Lc, RuntimeParity{});
+    load(kstart - 1, Lb, RuntimeParity{});
+    load(kstart, Lc, RuntimeParity{});
     a0[1] = Lb.a0;
     a1[1] = Lb.a1;
     xo[1] = Lb.xo;
@@ -276,7 +312,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     xo[2] = Lc.xo;
     cb1 = Lc.b1;
     cb2 = Lc.b2;
-    stage(k0 - 1, Lc);
+    stage(kstart, Lc);
   }
   lds_barrier();
 
@@ -306,7 +342,7 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     const int src = lane + (e1 ? 1 : -1);
     const T aout = __shfl(e1 ? a0[1] : a1[1], src, SX);
     const T xout = __shfl(xo[1], src, SX);
-    T v1, wi, wo, wb, wt;
+    T v1, wi, wo, wb, wt, D1, dz1;
     {
       const int sl = k & (NS - 1);
       const T2 ps = sa[sl][r][lane], pn = sa[sl][r + 2][lane];
@@ -319,15 +355,16 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
       const T wn = hn_ ? (acv + (e1 ? pn.y : pn.x)) * hy : T(0);
       wb = (acv + abv) * hz;
       wt = (acv + atv) * hz;
-      const T D = wi + wo + ws + wn + (!bot ? wb : pz * acv) + (!top ? wt : pz * acv);
+      dz1 = pz * acv;
+      D1 = wi + wo + ws + wn + (!bot ? wb : dz1) + (!top ? wt : dz1);
       if (FIRST) {
-        v1 = cb1 * recip(D);
+        v1 = cb1 * recip(D1);
       } else {
         // (absent faces have zero weight and finite neighbour values)
         const T xs = so[sl][r][lane], xn = so[sl][r + 2][lane];
         const T off = wi * xo[1] + wo * xout + ws * xs + wn * xn + (!bot ? wb * xo[0] : T(0)) +
                       (!top ? wt * xo[2] : T(0));
-        v1 = (cb1 + off) * recip(D);
+        v1 = (cb1 + off) * recip(D1);
       }
       if (owner && k >= k0 && k < k1) {
         const uint32_t so1 = soff(k);
@@ -337,29 +374,103 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
           buf_store<T>(cb2, rB2, vq, so1);
         }
       }
-      ringw[(k + 3) % 3][r][lane] = T2{ws, wn};
+      ringw[k & 3][r][lane] = T2{ws, wn};
     }
     c1n[0] = c1n[1];
     c1n[1] = c1n[2];
-    c1n[2] = v1;
-    ring[(k + 3) % 3][r][lane] = v1;
+    c1n[2] = c1n[3];
+    c1n[3] = v1;
+    ring[k & 3][r][lane] = v1;
     lds_barrier();
     // --- colour c2 on plane kk = k-1 (element e1 of the pair) ---
     const int kk = k - 1;
     // the adjacent lane's new c1 value and outer x-face on plane kk
     const int src2 = lane + (e1 ? 1 : -1);
-    const T cov = __shfl(c1n[1], src2, SX);
+    const T cov = __shfl(c1n[2], src2, SX);
     const T wov = __shfl(wop, src2, SX);
-    if (owner && kk >= k0 && kk < k1) {
+    T v2 = T(0), r2 = T(0);
+    if (calc2 && kk >= c2lo && kk < c2hi) {
       const bool top = kk == g.nz - 1, bot = kk == 0;
-      const int rl = (kk + 3) % 3;
+      const int rl = kk & 3;
       const T ys = ring[rl][r - 1][lane], yn = ring[rl][r + 1][lane];
       const T wsv = ringw[rl][r - 1][lane].y, wnv = ringw[rl][r + 1][lane].x;
       const T acv = e1 ? a1[0] : a0[0];
       const T D = wip + wov + wsv + wnv + (!bot ? wtpp : pz * acv) + (!top ? wb : pz * acv);
-      const T off = wip * c1n[1] + wov * cov + wsv * ys + wnv * yn + (!bot ? wtpp * c1n[0] : T(0)) +
-                    (!top ? wb * c1n[2] : T(0));
-      buf_store<T>((pb2 + off) * recip(D), rY2, vq, soff(kk));
+      const T off = wip * c1n[2] + wov * cov + wsv * ys + wnv * yn + (!bot ? wtpp * c1n[1] : T(0)) +
+                    (!top ? wb * c1n[3] : T(0));
+      v2 = (pb2 + off) * recip(D);
+      if (owner && kk >= k0 && kk < k1) buf_store<T>(v2, rY2, vq, soff(kk));
+      if (RESID) {
+        // its residual b - A x, the fluxes summed face by face as
+        // k_resid_restrict_split does (the update solved this equation with
+        // these neighbours: only rounding is left)
+        T Ax = wip * (v2 - c1n[2]);
+        Ax += wov * (v2 - cov);
+        Ax += wsv * (v2 - ys);
+        Ax += wnv * (v2 - yn);
+        Ax += !bot ? wtpp * (v2 - c1n[1]) : pz * acv * v2;
+        Ax += !top ? wb * (v2 - c1n[3]) : pz * acv * v2;
+        r2 = pb2 - Ax;
+      }
+    }
+    if constexpr (RESID) {
+      c2h[0] = c2h[1];
+      c2h[1] = c2h[2];
+      c2h[2] = v2;
+      ring2[kk & 1][r][lane] = v2;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        hb1[t] = hb1[t + 1];
+        hdz[t] = hdz[t + 1];
+        hwi[t] = hwi[t + 1];
+        hwo[t] = hwo[t + 1];
+        hwb[t] = hwb[t + 1];
+        hwt[t] = hwt[t + 1];
+      }
+      hb1[2] = cb1;
+      hdz[2] = dz1;
+      hwi[2] = wi;
+      hwo[2] = wo;
+      hwb[2] = wb;
+      hwt[2] = wt;
+      // --- residual of plane p = k-2, where every value is final: the c1
+      // cell from its kept weights and the new c2 values around it (the own
+      // pair and planes p-1, p+1 from registers, the outer x-neighbour from
+      // the adjacent lane, rows j-1 and j+1 from LDS, written before this
+      // iteration's barrier); summed over the pair and the plane pair of a
+      // coarse cell, then over the row pair through LDS ---
+      const int p = k - 2;
+      const int srcr = lane + (e1 ? 1 : -1);  // the c1 cell of plane p is element e1 of the pair, as on plane k
+      const T x2out = __shfl(c2h[1], srcr, SX);
+      if (p >= k0 && p < k1) {
+        T rsum = T(0);
+        if (owner) {
+          const bool top = p == g.nz - 1, bot = p == 0;
+          const int rl = p & 1;
+          const T ys = ring2[rl][r - 1][lane], yn = ring2[rl][r + 1][lane];
+          const T2 wsn = ringw[p & 3][r][lane];
+          const T x1 = c1n[1];
+          T Ax = hwi[0] * (x1 - c2h[1]);
+          Ax += hwo[0] * (x1 - x2out);
+          Ax += wsn.x * (x1 - ys);
+          Ax += wsn.y * (x1 - yn);
+          Ax += !bot ? hwb[0] * (x1 - c2h[0]) : hdz[0] * x1;
+          Ax += !top ? hwt[0] * (x1 - c2h[2]) : hdz[0] * x1;
+          rsum = (hb1[0] - Ax) + r2p;
+        }
+        if (!(p & 1)) {
+          accz = rsum;
+        } else {
+          accz += rsum;
+          if (r & 1) part[r][lane] = accz;
+          lds_barrier();
+          if (owner && !(r & 1)) {
+            const int NY = g.ny >> 1;
+            bc[((size_t)(p >> 1) * NY + (j >> 1)) * H + m] = (accz + part[r + 1][lane]) * T(0.125);
+          }
+        }
+      }
+      r2p = r2;
     }
     wtpp = wtp;
     wtp = wt;
@@ -373,10 +484,10 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
   // DEPTH load buffers: iteration k consumes plane k+1, whose loads were
   // issued DEPTH - 1 iterations earlier into the buffer the iteration before
   // them released; loads past the grid read a clamped valid plane
-  constexpr int DEPTH = SymShape<T>::DEPTH, UNROLL = SymShape<T>::UNROLL;
+  constexpr int DEPTH = S::DEPTH, UNROLL = S::UNROLL;
   SymCol<T> L[DEPTH];
   if constexpr (sizeof(T) == 8) {
-    // the colour-c1 cell of plane k0 - 1 + 2 n + t sits at e1 = E0 ^ (t % 2)
+    // the colour-c1 cell of plane kstart + 2 n + t sits at e1 = E0 ^ (t % 2)
     // with E0 uniform over the wave: the loop is instantiated for both E0 so
     // that every parity select is resolved at compile time (float64: 1.02 ->
     // 0.97 ms per sweep at 512^3; float32, whose arithmetic is cheaper, was
@@ -385,32 +496,32 @@ __global__ __launch_bounds__(SymShape<T>::SX* SymShape<T>::R) void k_sym_split(c
     auto run = [&](auto E0c) {
       using P0 = std::integral_constant<int, decltype(E0c)::value>;
       using P1 = std::integral_constant<int, decltype(E0c)::value ^ 1>;
-      load(k0, L[0], P1{});
-      for (int k = k0 - 1; k <= k1; k += UNROLL) {
+      load(kstart + 1, L[0], P1{});
+      for (int k = kstart; k <= kend; k += UNROLL) {
 #pragma unroll
         for (int t = 0; t < UNROLL; t += 2) {
           // planes k + t + 2 and k + t + 3 have the parities of k and k + 1
           load(k + t + 2, L[1], P0{});
-          if (k + t > k1) return;  // (an exit, not a break: no second path into the loop's back edge)
+          if (k + t > kend) return;  // (an exit, not a break: no second path into the loop's back edge)
           iterate(k + t, L[0], P0{});
           load(k + t + 3, L[0], P1{});
-          if (k + t + 1 > k1) return;
+          if (k + t + 1 > kend) return;
           iterate(k + t + 1, L[1], P1{});
         }
       }
     };
-    if ((c1 + j + k0 - 1) & 1)
+    if ((c1 + j + kstart) & 1)
       run(std::integral_constant<int, 1>{});
     else
       run(std::integral_constant<int, 0>{});
   } else {
 #pragma unroll
-    for (int t = 0; t < DEPTH - 1; ++t) load(k0 + t, L[t], RuntimeParity{});
-    for (int k = k0 - 1; k <= k1; k += UNROLL) {
+    for (int t = 0; t < DEPTH - 1; ++t) load(kstart + 1 + t, L[t], RuntimeParity{});
+    for (int k = kstart; k <= kend; k += UNROLL) {
 #pragma unroll
       for (int t = 0; t < UNROLL; ++t) {
         load(k + t + DEPTH, L[(t + DEPTH - 1) % DEPTH], RuntimeParity{});
-        if (k + t > k1) return;  // (an exit, not a break: no second path into the loop's back edge)
+        if (k + t > kend) return;  // (an exit, not a break: no second path into the loop's back edge)
         iterate(k + t, L[t % DEPTH], RuntimeParity{});
       }
     }

@@ -128,3 +128,14 @@ def test_coarse_fused_sweep_byte_model():
     table, _ = bench.kernel_table({"sym_L1_f32": (6.7, 45)}, 1, [5], 4, N)
     row = table[0]
     assert row[0] == "sym_L1_f32" and row[5] == 22 * (N // 8)
+
+
+def test_fused_residual_sweep_byte_model():
+    """The finest level's last pre-smoothing sweep, fused with the residual
+    restriction, moves the sweep's 3.5 s per cell plus the coarse right side
+    (s / 8), in place of the sweep and a 3 s + s / 8 residual pass."""
+    assert bench.bytes_per_cell("sym_resid", 0, 4) == 14.5 and bench.bytes_per_cell("sym_resid", 0, 8) == 29
+    assert bench.bytes_per_cell("sym", 0, 4) + bench.bytes_per_cell("resid_restrict", 0, 4) == 26.5
+    N = 512 ** 3
+    table, _ = bench.kernel_table({"sym_resid_fine_f32": (2.6, 5)}, 1, [5], 4, N)
+    assert table[0][0] == "sym_resid_fine_f32" and table[0][5] == 14.5 * N

@@ -89,7 +89,8 @@ def test_vcycle_mixed_matches_float32_oracle(shape):
 def test_vcycle_colour_split_finest_level(shape, sweep):
     """The finest level's colour-split kernels (several wave rows and block
     tiles, ragged last wave and tile, thin grids), with one kernel per
-    half-sweep or one per symmetric sweep, give the oracle's V-cycle."""
+    half-sweep or one per symmetric sweep (the last pre-smoothing one also
+    restricting the residual), give the oracle's V-cycle."""
     print(f"vcycle colour-split {shape} {sweep}", flush=True)
     a, f, h = _rand_problem(shape, 6)
     s64 = gm.GMGPoisson(T(a), h=h, precision="fp64", fine_sweep=sweep)
@@ -100,6 +101,7 @@ def test_vcycle_colour_split_finest_level(shape, sweep):
     names = set(s32.profile_read())
     s32.profile(False)
     assert ("sym_fine_f32" in names) == (sweep == "fused") and ("gs_fine_f32" in names) == (sweep == "half")
+    assert ("sym_resid_fine_f32" in names) == (sweep == "fused") != ("resid_restrict_fine_f32" in names)
     ref32 = vcycle(build_hierarchy(a, h, dtype=np.float32), f.astype(np.float32)).astype(np.float64)
     assert rel(z, ref32) < 2e-5
 
