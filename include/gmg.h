@@ -118,8 +118,8 @@ typedef struct gmg_options {
                            GMG_SWEEP_FUSED: one kernel per symmetric sweep
                            (nu_pre, nu_post >= 1; on the finest level of a grid
                            of at least two levels, and on coarse levels above
-                           the one-workgroup bottom with rows of at most 128
-                           x-pairs in float32, 64 in float64; half-sweeps
+                           the one-workgroup bottom with rows of at most 256
+                           x-pairs in float32, 128 in float64; half-sweeps
                            elsewhere);
                            GMG_SWEEP_AUTO (default): fused where it was
                            measured faster (finest level: long z-chunks;

@@ -618,10 +618,19 @@ Launch pair_launch(int nx, int ny, int nz, long long target, int min_kc) {
   return Launch{dim3(gx, gy, (nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
 }
 
+// Waves per row of the coarse levels' fused sweep (a block spans the row),
+// and the most a precision allows: a block has 16 (float32) or 8 (float64)
+// waves, two of its rows are a halo, and at least one row must own cells.
+inline int face_waves(const LevelShape& s) { return (s.nx / 2 + 63) / 64; }
+template <typename T>
+constexpr int FACE_MAX_WAVES = sizeof(T) == 4 ? 4 : 2;
+
 // Fused symmetric sweeps on coarse level l (k_sym_face): red-black Gauss-
-// Seidel with both smoothing phases, rows of at most 128 pairs in float32
-// and 64 in float64 (a block spans the row); on request, or by default on
-// levels of at least 128^3 cells.  They read the face coefficients once per
+// Seidel with both smoothing phases, rows of at most 256 pairs in float32
+// and 128 in float64 (a block spans the row: with two waves 8 rows in
+// float32 and 4 in float64, of which 6 and 2 own cells; float64 at 256^3:
+// 258 us per sweep against 2 x 163 us for the half-sweeps); on request, or
+// by default on levels of at least 128^3 cells.  They read the face coefficients once per
 // sweep instead of twice; on smaller levels, where a sweep is latency-bound,
 // the fused kernel takes as long as the two half-sweep kernels it replaces
 // (kernel trace of 256^3 solves: 12.2 us against 2 x 5.7 us at 64^3 and
@@ -631,7 +640,7 @@ bool fused_face(gmg_ctx* c, int l) {
   const LevelShape& s = c->L.shapes[l];
   const int fs = c->opt.fine_sweep;
   return c->opt.smoother == GMG_SMOOTH_RBGS && c->opt.nu_pre >= 1 && c->opt.nu_post >= 1 && l >= 1 &&
-         l < (int)c->L.shapes.size() - 1 && s.nx / 2 <= (sizeof(T) == 4 ? 128 : 64) &&
+         l < (int)c->L.shapes.size() - 1 && face_waves(s) <= FACE_MAX_WAVES<T> &&
          (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && s.n() >= ((size_t)1 << 21)));
 }
 
@@ -644,16 +653,25 @@ bool fused_face(gmg_ctx* c, int l) {
 template <typename T, bool FIRST>
 void sym_face(gmg_ctx* c, int l, const T* Xin, T* Xout, const T* b, const FaceCoef<T>& co, int c1) {
   const LevelShape& s = c->L.shapes[l];
-  const int wx = s.nx / 2 > 64 ? 2 : 1;
-  const int R = wx == 2 ? FaceSymShape<T, 2>::R : FaceSymShape<T, 1>::R, iy = R - 2;
-  const int gy = (s.ny + iy - 1) / iy;
-  const int kc = std::min(s.nz, std::max(8, (int)(((long long)s.nz * gy + 1023) / 1024)));
-  const Launch fl{dim3(1, gy, (s.nz + kc - 1) / kc), dim3(64 * wx, R, 1), kc};
   const char* nm = kname(FIRST ? "sym_first" : "sym", l, sizeof(T));
-  if (wx == 2)
-    GMG_LAUNCH(c, nm, (k_sym_face<T, FIRST, 2>), fl, Xin, Xout, b, co, s.geom(), kc, c1);
-  else
-    GMG_LAUNCH(c, nm, (k_sym_face<T, FIRST, 1>), fl, Xin, Xout, b, co, s.geom(), kc, c1);
+  auto go = [&](auto wc) {
+    constexpr int WX = decltype(wc)::value, R = FaceSymShape<T, WX>::R, iy = FaceSymShape<T, WX>::IY;
+    const int gy = (s.ny + iy - 1) / iy;
+    const int kc = std::min(s.nz, std::max(8, (int)(((long long)s.nz * gy + 1023) / 1024)));
+    const Launch fl{dim3(1, gy, (s.nz + kc - 1) / kc), dim3(64 * WX, R, 1), kc};
+    GMG_LAUNCH(c, nm, (k_sym_face<T, FIRST, WX>), fl, Xin, Xout, b, co, s.geom(), kc, c1);
+  };
+  switch (face_waves(s)) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    default:
+      if constexpr (FACE_MAX_WAVES<T> >= 4) {
+        if (face_waves(s) == 3)
+          go(std::integral_constant<int, 3>{});
+        else
+          go(std::integral_constant<int, 4>{});
+      }
+  }
 }
 
 // Coarse level l (not the coarsest, so every dimension is even): red-black

@@ -45,6 +45,7 @@ struct FaceSymShape {
   static constexpr int W = 64 * WX;
   static constexpr int R = (sizeof(T) == 4 ? 16 : 8) / WX;
   static constexpr int IY = R - 2;
+  static_assert(IY >= 1, "a block needs a row that owns cells");
 };
 
 template <typename T, bool FIRST, int WX>

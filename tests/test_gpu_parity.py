@@ -136,10 +136,12 @@ def test_fused_and_half_sweeps_agree_full_size(n, fused_by_default, precision):
 
 
 # (nx, ny, nz) with coarse face levels above the bottom kernel: 512 x 32 x
-# 48 (level 1 256 x 16 x 24: two-wave rows in float32, three row tiles, the
-# last ragged, three z-chunks; level 2 128 x 8 x 12: one-wave rows) and
-# 128 x 96 x 80 (levels 64 x 48 x 40 and 32 x 24 x 20)
-FACE_SHAPES = [(512, 32, 48), (128, 96, 80)]
+# 48 (level 1 256 x 16 x 24: two-wave rows, three row tiles, the last
+# ragged, three z-chunks; level 2 128 x 8 x 12: one-wave rows), 128 x 96 x
+# 80 (levels 64 x 48 x 40 and 32 x 24 x 20), 768 x 32 x 24 and 1024 x 32 x
+# 16 (level 1 with rows of 192 and 256 pairs: three- and four-wave rows in
+# float32, half-sweeps in float64)
+FACE_SHAPES = [(512, 32, 48), (128, 96, 80), (768, 32, 24), (1024, 32, 16)]
 
 
 @pytest.mark.parametrize("shape", FACE_SHAPES)
@@ -163,7 +165,7 @@ def test_fused_coarse_sweeps_match_half_sweeps(shape, nu):
             out[sweep] = (s.vcycle(T(f)), s.fmg(T(f)))
             names = set(s.profile_read())
             s.profile(False)
-            fused_l1 = precision == "mixed" or shape[0] // 4 <= 64
+            fused_l1 = shape[0] // 4 <= (256 if precision == "mixed" else 128)  # pairs per level-1 row
             assert ("sym_L1_" + ("f32" if precision == "mixed" else "f64") in names) == (sweep == "fused" and fused_l1)
             assert any(n.startswith("gs_L2") for n in names) == (sweep == "half")
         tol = 1e-5 if precision == "mixed" else 1e-13
