@@ -2220,11 +2220,17 @@ int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top,
   double* misc = scal_misc(c);
   bool first = true;
   double bnorm = 0.0;
+  // the last cycle ended on a converged estimate (or at max_iter): the true
+  // residual is likely final, so its pass computes the norm without storing
+  // r into V[0] (a quarter of the pass's bytes); if it is not final after
+  // all, the pass runs again with the store for the restart
+  bool likely_last = false;
   while (true) {
     // r_0 = b - A x_0 into V[0] (the true residual at every restart)
-    init_residual(c, f_dev, (first && !use_x0) ? nullptr : phi_dev, phi_bot, phi_top, true);
+    init_residual(c, f_dev, (first && !use_x0) ? nullptr : phi_dev, phi_bot, phi_top, !likely_last);
     if (read_back(c, misc, 3) != GMG_OK) return finish(GMG_ERR_HIP, NAN);
-    const double bn2 = c->pinned[0], beta = c->pinned[2];
+    const double bn2 = c->pinned[0];
+    double beta = c->pinned[2];
     if (!std::isfinite(bn2) || !std::isfinite(beta)) return finish(GMG_ERR_NONFINITE, NAN);
     if (first) {
       bnorm = std::sqrt(bn2);
@@ -2240,6 +2246,13 @@ int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top,
     }
     if (beta < tol * bnorm) return finish(GMG_OK, beta / bnorm);
     if (it >= c->opt.max_iter) return finish(GMG_NOT_CONVERGED, beta / bnorm);
+    if (likely_last) {
+      // (the same kernel and reduction: the same norms)
+      init_residual(c, f_dev, phi_dev, phi_bot, phi_top, true);
+      if (read_back(c, misc, 3) != GMG_OK) return finish(GMG_ERR_HIP, NAN);
+      beta = c->pinned[2];
+    }
+    likely_last = false;
     // Arnoldi cycle
     std::fill(c->g.begin(), c->g.end(), 0.0);
     c->g[0] = beta;
@@ -2274,8 +2287,12 @@ int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top,
       k = j + 1;
       const double est = std::fabs(c->g[j + 1]);
       push_hist(est / bnorm);
-      if (est < tol * bnorm || breakdown) break;
+      if (est < tol * bnorm || breakdown) {
+        likely_last = true;
+        break;
+      }
     }
+    if (it >= c->opt.max_iter) likely_last = true;
     // y = R_k^{-1} g_k, phi += Z_k y
     for (int i = k - 1; i >= 0; --i) {
       double s = c->g[i];

@@ -242,6 +242,30 @@ def test_fgmres_fp64_fixed_steps_matches_oracle(case, cold):
     np.testing.assert_allclose(gh, oh, rtol=1e-6, atol=1e-15)
 
 
+def test_restart_after_a_converged_estimate():
+    """Below the attainable accuracy (float64, tol 1e-14 at 16^3) a cycle's
+    estimate drops under tol while the true residual stays near 2e-14: the
+    residual pass that follows each cycle, run without its store because the
+    solve looked finished, runs again with the store and the solve restarts
+    from it.  Restart after restart, the solve ends where the oracle's does
+    (max_iter reached, or converged if its rounding lands below tol), and it
+    reports the true residual."""
+    p = make_config(2, n=16)
+    s = gm.GMGPoisson(T(p.a), precision="fp64", restart=4, max_iter=30)
+    res = s.solve(T(p.f), p.phi_bot, p.phi_top, tol=1e-14)
+    ref = solve_poisson(p.a, p.f, p.h, p.phi_bot, p.phi_top, tol=1e-14, max_iter=30, restart=4)
+    print(f"  GPU {res.iterations} steps, true relres {res.final_relres:.2e}; oracle {ref.iterations}, "
+          f"{ref.true_relres:.2e}", flush=True)
+    b = rhs(p.f, p.a, p.h, p.phi_bot, p.phi_top)
+    true = np.linalg.norm(b - apply_operator(npy(res.phi), p.a, p.h)) / np.linalg.norm(b)
+    if res.status == 0:
+        assert res.final_relres < 1e-14 and res.iterations <= 30
+    else:
+        assert res.status == gm.solver.NOT_CONVERGED and res.iterations == ref.iterations == 30
+    assert res.final_relres < 1e-13 and true < 1e-13
+    assert rel(npy(res.phi), ref.x) < 1e-10
+
+
 def _converged_pair(p, precision, tol=1e-8, **kw):
     s = gm.GMGPoisson(T(p.a), precision=precision, **kw)
     return s, s.solve(T(p.f), p.phi_bot, p.phi_top, tol=tol)
