@@ -280,6 +280,7 @@ struct gmg_ctx {
   size_t N;
   bool mixed;
   int nc;  // cells on the coarsest level
+  int cus;  // compute units of the device
   int bottom_from;  // first level run by the one-workgroup bottom kernel (-1: none)
   bool fmg_now;     // the running solve preconditions with full multigrid cycles
   bool gmres_mode;  // GMRES: one preconditioned-vector slot, x updated by M (V y)
@@ -618,6 +619,37 @@ Launch pair_launch(int nx, int ny, int nz, long long target, int min_kc) {
   return Launch{dim3(gx, gy, (nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
 }
 
+// z-chunk of a column-marching launch with `cols` blocks per chunk column
+// and `resident` blocks running at once: the chunk (at least min_kc planes)
+// that minimises the rounds of blocks times the planes a block marches (its
+// chunk plus `extra`), the smallest chunk for each chunk count, among
+// chunks that give at least min_rounds rounds when any does.  (A round
+// with few blocks leaves most CUs idle: at level 1 of the 512^3 grid,
+// 11-plane chunks made 1032 blocks of one per CU, 4.03 rounds on 256 CUs;
+// 24-plane chunks, 473 blocks in 2 rounds, took 110.5 us per sweep against
+// 137.8.  The finest level's fused sweep was slower in 3 long rounds than
+// in 8 short ones, 563 against 507 us, at the same modelled cost: it keeps
+// at least 4.)
+inline int rounds_kc(int nz, long long cols, long long resident, int min_kc, int extra, int min_rounds = 1) {
+  int best = std::min(nz, min_kc), best_any = best;
+  double best_cost = 1e300, best_cost_any = 1e300;
+  for (int kc = std::min(nz, min_kc); kc <= nz; ++kc) {
+    const long long gz = (nz + kc - 1) / kc;
+    if (kc > 1 && kc > min_kc && (nz + kc - 2) / (kc - 1) == gz) continue;  // a smaller chunk gives the same count
+    const long long rounds = (cols * gz + resident - 1) / resident;
+    const double cost = (double)rounds * (kc + extra);
+    if (cost < best_cost_any) {
+      best_cost_any = cost;
+      best_any = kc;
+    }
+    if (rounds >= min_rounds && cost < best_cost) {
+      best_cost = cost;
+      best = kc;
+    }
+  }
+  return best_cost < 1e300 ? best : best_any;
+}
+
 // Waves per row of the coarse levels' fused sweep (a block spans the row),
 // and the most a precision allows: a block has 16 (float32) or 8 (float64)
 // waves, two of its rows are a halo, and at least one row must own cells.
@@ -657,7 +689,17 @@ void sym_face(gmg_ctx* c, int l, const T* Xin, T* Xout, const T* b, const FaceCo
   auto go = [&](auto wc) {
     constexpr int WX = decltype(wc)::value, R = FaceSymShape<T, WX>::R, iy = FaceSymShape<T, WX>::IY;
     const int gy = (s.ny + iy - 1) / iy;
-    const int kc = std::min(s.nz, std::max(8, (int)(((long long)s.nz * gy + 1023) / 1024)));
+    // blocks of the kernel resident on one CU (one, for these 16- and 8-wave
+    // blocks and their registers), asked once
+    static const int per_cu = [] {
+      int nb = 0;
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym_face<T, FIRST, WX>, 64 * WX * R, 0) ==
+                         hipSuccess &&
+                     nb > 0
+                 ? nb
+                 : 1;
+    }();
+    const int kc = rounds_kc(s.nz, gy, (long long)per_cu * c->cus, 8, 2);
     const Launch fl{dim3(1, gy, (s.nz + kc - 1) / kc), dim3(64 * WX, R, 1), kc};
     GMG_LAUNCH(c, nm, (k_sym_face<T, FIRST, WX>), fl, Xin, Xout, b, co, s.geom(), kc, c1);
   };
@@ -1084,14 +1126,38 @@ inline long long sym_max_planes(const LevelShape& s) {
 // planes) and at most sym_max_planes - 8 (a block reads up to three planes
 // below its chunk and four above).
 template <typename T, bool RESID = false>
-Launch sym_launch(const LevelShape& s) {
+int sym_default_kc(const LevelShape& s) {
   using S = SymShape<T, RESID>;
   const int gx = (s.nx / 2 + S::IX - 1) / S::IX, gy = (s.ny + S::IY - 1) / S::IY;
   const long long target = 2048LL * 1024 / (S::SX * S::R);
-  long long kc = std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
+  return (int)std::min<long long>(s.nz, std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target));
+}
+// The launch takes the chunk from the rounds model (rounds_kc) over the
+// blocks resident at once; `resident` = 0 keeps sym_default_kc.
+template <typename T, bool RESID = false>
+Launch sym_launch(const LevelShape& s, long long resident = 0) {
+  using S = SymShape<T, RESID>;
+  const int gx = (s.nx / 2 + S::IX - 1) / S::IX, gy = (s.ny + S::IY - 1) / S::IY;
+  long long kc = resident > 0 ? rounds_kc(s.nz, (long long)gx * gy, resident, 8, RESID ? 3 : 2, 4)
+                              : sym_default_kc<T, RESID>(s);
   kc = std::min<long long>({kc, s.nz, std::max<long long>(1, sym_max_planes(s) - 8)});
   if (RESID) kc = std::max<long long>(2, kc & ~1LL);
   return Launch{dim3(gx, gy, (unsigned)((s.nz + kc - 1) / kc)), dim3(S::SX, S::R, 1), (int)kc};
+}
+
+// Blocks of k_sym_split resident on one CU (asked once per instantiation).
+template <typename T, bool FIRST, bool SCALED, bool RESID>
+int sym_blocks_per_cu() {
+  static const int nb = [] {
+    int n = 0;
+    using S = SymShape<T, RESID>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sym_split<T, FIRST, SCALED, RESID>, S::SX * S::R, 0) ==
+                       hipSuccess &&
+                   n > 0
+               ? n
+               : 1;
+  }();
+  return nb;
 }
 
 // One fused symmetric sweep (k_sym_split) on the finest level: colour c1
@@ -1102,16 +1168,18 @@ template <typename T, bool FIRST, bool RESID = false>
 void sym_split(gmg_ctx* c, const T* Xin, T* Xout, T* B, const double* u, const double* bscale, const T* a,
                int c1, T* bc = nullptr) {
   const LevelShape& s = c->L.shapes[0];
-  const Launch l = sym_launch<T, RESID>(s);
   const char* nm = kname(RESID ? "sym_resid" : (FIRST ? "sym_first" : "sym"), 0, sizeof(T));
   if constexpr (RESID) {
     static_assert(!FIRST, "the residual is fused into a sweep from a guess only");
+    const Launch l = sym_launch<T, true>(s, (long long)sym_blocks_per_cu<T, false, false, true>() * c->cus);
     GMG_LAUNCH(c, nm, (k_sym_split<T, false, false, true>), l, Xin, Xout, B, u, bscale, a, s.geom(), c->L.hn,
                l.kc, c1, bc);
   } else if (FIRST && bscale) {
+    const Launch l = sym_launch<T, false>(s, (long long)sym_blocks_per_cu<T, FIRST, true, false>() * c->cus);
     GMG_LAUNCH(c, nm, (k_sym_split<T, FIRST, true, false>), l, Xin, Xout, B, u, bscale, a, s.geom(), c->L.hn,
                l.kc, c1, bc);
   } else {
+    const Launch l = sym_launch<T, false>(s, (long long)sym_blocks_per_cu<T, FIRST, false, false>() * c->cus);
     GMG_LAUNCH(c, nm, (k_sym_split<T, FIRST, false, false>), l, Xin, Xout, B, u, bscale, a, s.geom(), c->L.hn,
                l.kc, c1, bc);
   }
@@ -1182,7 +1250,7 @@ template <typename T>
 bool sym_chosen(gmg_ctx* c) {
   const int fs = c->opt.fine_sweep;
   return c->L.shapes.size() > 1 && sym_max_planes(c->L.shapes[0]) >= 10 &&
-         (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_launch<T>(c->L.shapes[0]).kc >= 16));
+         (fs == GMG_SWEEP_FUSED || (fs == GMG_SWEEP_AUTO && sym_default_kc<T>(c->L.shapes[0]) >= 16));
 }
 template <typename T>
 bool fused_sweeps(gmg_ctx* c) {
@@ -2103,6 +2171,13 @@ int init_ctx(gmg_ctx* c, int nx, int ny, int nz, double hx, double hy, double hz
       (opt->smoother == GMG_SMOOTH_CHEBYSHEV || opt->restriction == GMG_RESTRICT_TRANSPOSE) ? -1 : bottom_level(L);
   c->err = hipSuccess;
   c->pinned = host_buf;
+  {
+    int dev = 0, n = 0;
+    c->cus = hipGetDevice(&dev) == hipSuccess &&
+                     hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0
+                 ? n
+                 : 256;
+  }
   const int m = opt->restart;
   c->R.assign((size_t)m * m, 0.0);
   c->cs.assign(m, 0.0);
