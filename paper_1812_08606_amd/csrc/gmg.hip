@@ -678,10 +678,8 @@ bool fused_face(gmg_ctx* c, int l) {
 
 // One fused symmetric sweep on coarse level l: colour c1 from Xin into Xout,
 // then the other colour from the new values (FIRST: from x = 0, Xin unused).
-// A block spans the row (one or two waves) and FaceSymShape's rows; z-chunks
-// of at least 8 planes, about 1024 blocks (measured at 256^3, float32: 148.5
-// us per sweep against 2 x 86.7 us for the half-sweeps; 4-plane chunks took
-// 149.5 us, and 29.8 us against 23.3 at 128^3).
+// A block spans the row (one to four waves) and FaceSymShape's rows; z-chunks
+// of at least 8 planes from the rounds model (rounds_kc).
 template <typename T, bool FIRST>
 void sym_face(gmg_ctx* c, int l, const T* Xin, T* Xout, const T* b, const FaceCoef<T>& co, int c1) {
   const LevelShape& s = c->L.shapes[l];
