@@ -608,14 +608,27 @@ const char* kname(const char* base, int level, size_t tsize) {
   return it->second.c_str();
 }
 
+// A z-marching launch with fewer blocks than this is latency-bound (a small
+// level): each loop trip of a block waits for its own loads, so there every
+// block marches a single trip of planes instead of min_kc planes.
+constexpr long long SMALL_GRID_BLOCKS = 1024;
+
+// z-chunk of a marching launch over nz planes with `cols` blocks per chunk
+// column: kc, or the kernel's planes per loop trip on a small grid.
+inline int small_grid_kc(int nz, long long cols, int kc, int trip) {
+  if (trip > 0 && cols * ((nz + kc - 1) / kc) < SMALL_GRID_BLOCKS) kc = trip;
+  return std::min(kc, nz);
+}
+
 // Launch of the lane-pair z-marching kernels over an nx x ny x nz grid (nx
 // even): one lane per x-pair, rows of BY threads, z-chunks of kc planes with
-// kc >= min_kc, about `target` blocks.
-Launch pair_launch(int nx, int ny, int nz, long long target, int min_kc) {
+// kc >= min_kc, about `target` blocks; on a small grid, `trip` planes (the
+// kernel's planes per loop trip; 0: keep min_kc).
+Launch pair_launch(int nx, int ny, int nz, long long target, int min_kc, int trip = 0) {
   const int gx = (nx / 2 + BX - 1) / BX, gy = (ny + BY - 1) / BY;
   const long long cols = (long long)gx * gy;
   int kc = (int)std::max<long long>(min_kc, (nz * cols + target - 1) / target);
-  kc = std::min(kc, nz);
+  kc = small_grid_kc(nz, cols, std::min(kc, nz), trip);
   return Launch{dim3(gx, gy, (nz + kc - 1) / kc), dim3(BX, BY, 1), kc};
 }
 
@@ -730,7 +743,7 @@ void smooth_pre_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co,
     }
     return;
   }
-  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4, 2);
   if (from_x)
     GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, g, pl.kc, 0);
   else
@@ -745,7 +758,7 @@ void smooth_pre_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co,
 template <typename T>
 void smooth_post_face(gmg_ctx* c, int l, T* x, const T* b, const FaceCoef<T>& co) {
   const LevelShape& s = c->L.shapes[l];
-  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4);
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz, 4096, 4, 2);
   for (int it = 0; it < c->opt.nu_post; ++it) {
     GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, s.geom(), pl.kc, 1);
     GMG_LAUNCH(c, kname("gs", l, sizeof(T)), (k_gs_pair_face<T, false>), pl, x, b, co, s.geom(), pl.kc, 0);
@@ -769,7 +782,7 @@ void resid_restrict_face(gmg_ctx* c, int l, const T* x, const T* b, const FaceCo
                s.geom());
     return;
   }
-  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2);
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2, 1);
   GMG_LAUNCH(c, kname("resid_restrict", l, sizeof(T)), k_resid_restrict_face<T>, pl, x, b, co, s.geom(), bc,
              pl.kc);
 }
@@ -790,7 +803,7 @@ void resid_restrict_fine(gmg_ctx* c, const T* X, const T* B, const double* u, co
                bc, s.geom());
     return;
   }
-  const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+  const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4, 1);
   GMG_LAUNCH(c, kname("resid_restrict", 0, sizeof(T)), k_resid_restrict_split<T>, l, X, B, a, s.geom(), c->L.hn,
              bc, l.kc);
 }
@@ -800,7 +813,7 @@ void resid_restrict_fine(gmg_ctx* c, const T* X, const T* B, const double* u, co
 template <typename T>
 void prolong_add(gmg_ctx* c, int l, T* x, const T* xc, const T* xin = nullptr) {
   const LevelShape& s = c->L.shapes[l];
-  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2);
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2, 1);
   GMG_LAUNCH(c, kname("prolong_add", l, sizeof(T)), (k_prolong_pair<T, false>), pl, x, xc, s.geom(), (size_t)0, 0,
              pl.kc, xin);
 }
@@ -809,7 +822,7 @@ void prolong_add(gmg_ctx* c, int l, T* x, const T* xc, const T* xin = nullptr) {
 template <typename T>
 void prolong_set(gmg_ctx* c, int l, T* x, const T* xc) {
   const LevelShape& s = c->L.shapes[l];
-  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2);
+  const Launch pl = pair_launch(s.nx, s.ny, s.nz / 2, 4096, 2, 1);
   GMG_LAUNCH(c, kname("prolong_set", l, sizeof(T)), (k_prolong_pair<T, false, true>), pl, x, xc, s.geom(),
              (size_t)0, 0, pl.kc, (const T*)nullptr);
 }
@@ -1001,7 +1014,7 @@ void gs_split(gmg_ctx* c, T* X, T* B, const double* u, const double* bscale, con
   const int gx = (s.nx / 2 + BX - 1) / BX, gy = (s.ny + GS_ROWS - 1) / GS_ROWS;
   const long long target = 8192LL * BY / GS_ROWS;
   int kc = (int)std::max<long long>(8, (s.nz * (long long)gx * gy + target - 1) / target);
-  kc = std::min(kc, s.nz);
+  kc = small_grid_kc(s.nz, (long long)gx * gy, std::min(kc, s.nz), SPLIT_BATCH);
   const Launch l{dim3(gx, gy, (s.nz + kc - 1) / kc), dim3(BX, GS_ROWS, 1), kc};
   const char* nm = kname(FIRST ? "gs_first" : "gs", 0, sizeof(T));
   if (FIRST && bscale)
@@ -1037,7 +1050,7 @@ void vcycle_fine_split(gmg_ctx* c, const double* u, const double* bscale, T* X, 
   resid_restrict_fine<T>(c, X, B, u, bscale, a);
   vcycle_coarse<T>(c, 1);
   {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4, 1);
     GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), (k_prolong_pair<T, true>), l, X,
                (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, npost > 0 ? 1 : 3, l.kc,
                (const T*)nullptr);
@@ -1104,7 +1117,7 @@ void vcycle_fine_cheb(gmg_ctx* c, const double* u, const double* bscale, T* X) {
   }
   vcycle_coarse<T>(c, 1);
   {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4, 1);
     GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), (k_prolong_pair<T, true>), l, X,
                (const T*)wsp<T>(c, c->L.lv[1].x), g, hn, 3, l.kc, (const T*)nullptr);
   }
@@ -1229,7 +1242,7 @@ void vcycle_fine_sym(gmg_ctx* c, const double* u, const double* bscale, T* Z, bo
   if (!fuse_resid) resid_restrict_fine<T>(c, X, B, u, bscale, a);
   vcycle_coarse<T>(c, 1);
   {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4, 1);
     GMG_LAUNCH(c, kname("prolong_add", 0, sizeof(T)), (k_prolong_pair<T, true>), l, X,
                (const T*)wsp<T>(c, c->L.lv[1].x), s.geom(), hn, 1, l.kc,
                (const T*)nullptr);
@@ -1306,7 +1319,7 @@ void fmg_fine(gmg_ctx* c, const double* u, const double* bscale, T* z) {
   const bool fused = fused_sweeps<T>(c);
   T* X0 = fused ? sym_buffer<T>(c, z, 0) : z;
   {
-    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4);
+    const Launch l = pair_launch(s.nx, s.ny, s.nz / 2, 8192, 4, 1);
     // the first pre-smoothing half-sweep (red) reads only the black guess;
     // without pre-smoothing the residual reads both colours
     GMG_LAUNCH(c, kname("prolong_set", 0, sizeof(T)), (k_prolong_pair<T, true, true>), l, X0,
