@@ -1487,14 +1487,14 @@ void launch_axpy(gmg_ctx* c, const Launch& rl, double* w, const double* V, const
   GMG_LAUNCH(c, "axpy_norm", k_axpy_norm<NV>, rl, w, c->N, V, c->L.ldv, hc, vs, last, wsp<double>(c, c->L.partials));
 }
 template <typename TZ, int NV>
-void launch_update(gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y) {
+void launch_update(gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y, int set) {
   const char* nm = sizeof(TZ) == 4 ? "update_zf32" : "update_zf64";
   if (c->L.shapes.size() > 1) {
     const LevelShape& s = c->L.shapes[0];
     const Launch l = pair_launch(s.nx, s.ny, s.nz, 8192, 8);
-    GMG_LAUNCH(c, nm, (k_update_split<TZ, NV>), l, phi, Z, c->L.hn, c->L.ldv, y, s.geom(), l.kc);
+    GMG_LAUNCH(c, nm, (k_update_split<TZ, NV>), l, phi, Z, c->L.hn, c->L.ldv, y, s.geom(), l.kc, set);
   } else {
-    GMG_LAUNCH(c, nm, (k_update<TZ, NV>), rl, phi, c->N, Z, c->L.ldv, y);
+    GMG_LAUNCH(c, nm, (k_update<TZ, NV>), rl, phi, c->N, Z, c->L.ldv, y, set);
   }
 }
 
@@ -1519,11 +1519,11 @@ void axpy_nv(int nv, gmg_ctx* c, const Launch& rl, double* w, const double* V, c
   table[nv - 1](c, rl, w, V, hc, vs, last);
 }
 template <typename TZ, size_t... I>
-void update_nv(int nv, gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y,
+void update_nv(int nv, gmg_ctx* c, const Launch& rl, double* phi, const TZ* Z, const Coeffs16& y, int set,
                std::index_sequence<I...>) {
-  using F = void (*)(gmg_ctx*, const Launch&, double*, const TZ*, const Coeffs16&);
+  using F = void (*)(gmg_ctx*, const Launch&, double*, const TZ*, const Coeffs16&, int);
   static constexpr F table[] = {&launch_update<TZ, (int)I + 1>...};
-  table[nv - 1](c, rl, phi, Z, y);
+  table[nv - 1](c, rl, phi, Z, y, set);
 }
 
 // One Arnoldi step j: z_j = M v_j, w = A z_j, classical Gram-Schmidt against
@@ -1563,7 +1563,9 @@ void arnoldi_step(gmg_ctx* c, int j) {
 }
 
 // phi += sum_{i<k} y_i z_i
-void update_solution(gmg_ctx* c, double* phi, int k) {
+// phi += Z_k y (set: phi = 0 + Z_k y, phi not read: the first update of a
+// solve from a zero guess, which then needs no zero fill beforehand).
+void update_solution(gmg_ctx* c, double* phi, int k, bool set) {
   const Launch fl = flat_launch(c->N);
   const auto seq = std::make_index_sequence<MAXV>{};
   for (int q0 = 0; q0 < k; q0 += MAXV) {
@@ -1571,10 +1573,11 @@ void update_solution(gmg_ctx* c, double* phi, int k) {
     Coeffs16 y{};
     for (int q = 0; q < nq; ++q) y.v[q] = c->y[q0 + q];
     char* Zb = c->ws + c->L.Z + (size_t)q0 * c->L.ldv * c->L.tsize;
+    const int st = set && q0 == 0 ? 1 : 0;
     if (c->mixed)
-      update_nv<float>(nq, c, fl, phi, (const float*)Zb, y, seq);
+      update_nv<float>(nq, c, fl, phi, (const float*)Zb, y, st, seq);
     else
-      update_nv<double>(nq, c, fl, phi, (const double*)Zb, y, seq);
+      update_nv<double>(nq, c, fl, phi, (const double*)Zb, y, st, seq);
   }
 }
 
@@ -1914,7 +1917,7 @@ void kapply(gmg_ctx* c, const double* x, double* w, const double* U, int nv, dou
 // basis slot V[k], then phi += M u.
 template <int NV>
 void launch_update_natural(gmg_ctx* c, const Launch& fl, double* u, const double* V, const Coeffs16& y) {
-  GMG_LAUNCH(c, "update_natural", (k_update<double, NV>), fl, u, c->N, V, c->L.ldv, y);
+  GMG_LAUNCH(c, "update_natural", (k_update<double, NV>), fl, u, c->N, V, c->L.ldv, y, 0);
 }
 template <size_t... I>
 void natural_update_nv(int nv, gmg_ctx* c, const Launch& fl, double* u, const double* V, const Coeffs16& y,
@@ -1943,9 +1946,9 @@ void gmres_update(gmg_ctx* c, double* phi, int k) {
   Coeffs16 one{};
   one.v[0] = 1.0;
   if (c->mixed)
-    launch_update<float, 1>(c, fl, phi, (const float*)Zb, one);
+    launch_update<float, 1>(c, fl, phi, (const float*)Zb, one, 0);
   else
-    launch_update<double, 1>(c, fl, phi, (const double*)Zb, one);
+    launch_update<double, 1>(c, fl, phi, (const double*)Zb, one, 0);
 }
 
 struct KrylovOut {
@@ -2290,16 +2293,23 @@ int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top,
     if (nhist < res_hist_cap) res_hist[nhist] = v;
     ++nhist;
   };
+  // without an initial guess phi starts at zero: the first update writes
+  // phi = Z y without reading it, and phi is filled with zeros only if the
+  // solve ends, or reads phi, before any update
+  bool phi_zero = !use_x0;
+  auto zero_phi = [&]() {
+    if (!phi_zero) return;
+    const Launch fl = flat_launch(c->N);
+    GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
+    phi_zero = false;
+  };
   auto finish = [&](int status, double relres) {
+    zero_phi();
     if (iterations) *iterations = it;
     if (res_hist_len) *res_hist_len = std::min(nhist, res_hist_cap);
     if (final_true_relres) *final_true_relres = relres;
     return status;
   };
-  if (!use_x0) {
-    const Launch fl = flat_launch(c->N);
-    GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
-  }
   c->fmg_now = allow_fmg && (use_x0 ? c->opt.warm_cycle : c->opt.cold_cycle) == GMG_CYCLE_FMG;
   c->gmres_mode = gmres;
   c->nprec = 0;
@@ -2321,8 +2331,8 @@ int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top,
     if (first) {
       bnorm = std::sqrt(bn2);
       if (bnorm == 0.0) {
-        const Launch fl = flat_launch(c->N);
-        GMG_LAUNCH(c, "fill", k_fill<double>, fl, phi_dev, 0.0, c->N);
+        phi_zero = true;
+        zero_phi();
         note(c, hipStreamSynchronize(c->stream));
         push_hist(0.0);
         return finish(c->err == hipSuccess ? GMG_OK : GMG_ERR_HIP, 0.0);
@@ -2386,11 +2396,12 @@ int fgmres_core(gmg_ctx* c, const double* f_dev, double phi_bot, double phi_top,
       const double rii = c->R[(size_t)i * m + i];
       c->y[i] = rii != 0.0 ? s / rii : 0.0;
     }
-    if (k > 0) {
-      if (gmres)
-        gmres_update(c, phi_dev, k);
-      else
-        update_solution(c, phi_dev, k);
+    if (k > 0 && !gmres) {
+      update_solution(c, phi_dev, k, phi_zero);
+      phi_zero = false;
+    } else {
+      zero_phi();
+      if (k > 0) gmres_update(c, phi_dev, k);
     }
   }
 }
@@ -2538,10 +2549,9 @@ int cycle_api(gmg_ctx* c, const double* v_dev, double* z_dev, bool fmg) {
     cycle_eager(c, v_dev, nullptr, z32, fmg);
     const Launch fl = flat_launch(c->N);
     if (split) {  // z = 0 + 1 * z32, exact, into the natural layout
-      GMG_LAUNCH(c, "fill", k_fill<double>, fl, z_dev, 0.0, c->N);
       Coeffs16 one{};
       one.v[0] = 1.0;
-      launch_update<float, 1>(c, fl, z_dev, z32, one);
+      launch_update<float, 1>(c, fl, z_dev, z32, one, 1);
     } else {
       GMG_LAUNCH(c, "convert_f32_f64", (k_convert<double, float>), fl, (const float*)z32, z_dev, c->N);
     }
@@ -2549,10 +2559,9 @@ int cycle_api(gmg_ctx* c, const double* v_dev, double* z_dev, bool fmg) {
     double* z64 = wsp<double>(c, c->L.Z);
     cycle_eager(c, v_dev, nullptr, z64, fmg);
     const Launch fl = flat_launch(c->N);
-    GMG_LAUNCH(c, "fill", k_fill<double>, fl, z_dev, 0.0, c->N);
     Coeffs16 one{};
     one.v[0] = 1.0;
-    launch_update<double, 1>(c, fl, z_dev, z64, one);
+    launch_update<double, 1>(c, fl, z_dev, z64, one, 1);
   } else {
     cycle_eager(c, v_dev, nullptr, z_dev, fmg);
   }

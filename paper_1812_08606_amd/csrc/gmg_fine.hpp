@@ -588,10 +588,13 @@ __global__ __launch_bounds__(NTHREADS) void k_op_multidot_split(const TZ* __rest
   block_store_partials<NV>(acc, NV, partials, gridDim.x * gridDim.y * gridDim.z);
 }
 
-// phi += sum_v y_v z_v with z_v colour-split (z promoted to float64).
+// phi += sum_v y_v z_v with z_v colour-split (z promoted to float64); set:
+// phi = 0 + sum_v y_v z_v, without reading phi (the first update of a solve
+// from a zero guess).
 template <typename TZ, int NV>
 __global__ __launch_bounds__(NTHREADS) void k_update_split(double* __restrict__ phi, const TZ* __restrict__ Z,
-                                                           size_t hn, size_t stride, Coeffs16 y, Geom g, int kc) {
+                                                           size_t hn, size_t stride, Coeffs16 y, Geom g, int kc,
+                                                           int set) {
   const Tile tl = xcd_tile();
   const int H = g.nx >> 1;
   const int m = tl.x * BX + threadIdx.x;
@@ -601,7 +604,11 @@ __global__ __launch_bounds__(NTHREADS) void k_update_split(double* __restrict__ 
   for (int k = k0; k < k1; ++k) {
     const size_t q = sidx(g, m, j, k), cn = 2 * q;
     const int p = (j + k) & 1;
-    double l = phi[cn], r = phi[cn + 1];
+    double l = 0.0, r = 0.0;
+    if (!set) {
+      l = phi[cn];
+      r = phi[cn + 1];
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double zl, zr;

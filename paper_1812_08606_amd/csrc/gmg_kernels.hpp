@@ -1023,12 +1023,13 @@ __global__ __launch_bounds__(NTHREADS) void k_axpy_norm(double* __restrict__ w, 
   if (want_norm) block_store_partials<1>(acc, 1, partials, gridDim.x);
 }
 
-// phi += sum_v y_v z_v (z promoted to float64; flat launch).
+// phi += sum_v y_v z_v (z promoted to float64; flat launch); set: phi = 0 +
+// sum_v y_v z_v, without reading phi.
 template <typename TZ, int NV>
 __global__ __launch_bounds__(NTHREADS) void k_update(double* __restrict__ phi, size_t n, const TZ* __restrict__ Z,
-                                                     size_t stride, Coeffs16 y) {
+                                                     size_t stride, Coeffs16 y, int set) {
   GMG_FLAT_LOOP(c, n) {
-    double p = phi[c];
+    double p = set ? 0.0 : phi[c];
 #pragma unroll
     for (int q = 0; q < NV; ++q) p += y.v[q] * (double)Z[(size_t)q * stride + c];
     phi[c] = p;

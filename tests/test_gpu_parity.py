@@ -426,6 +426,39 @@ def test_mixed_time_loop_two_filaments_within_residual_bound(warm):
         prev_g, prev_o = res.phi.clone(), ref.x
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_solve_from_zero_ignores_the_output_buffer(precision):
+    """A solve without an initial guess never reads phi before its first
+    update (which writes phi = Z y): the result does not depend on what the
+    output buffer held, NaN included, is the same to the bit as into a
+    zeroed buffer, and phi is exactly zero when the solve stops before any
+    step (tolerance above 1: the zero guess already passes, Algorithm 1's
+    test on the initial residual), or on max_iter = 0.  The same for GMRES
+    and for a V-cycle's output."""
+    p = make_config(2, n=32)
+    f = T(p.f)
+    for restart, max_iter in ((10, 200), (2, 200)):  # one cycle; restarts after two steps
+        s = gm.GMGPoisson(T(p.a), precision=precision, restart=restart, max_iter=max_iter)
+        zero = torch.zeros_like(f)
+        nan = torch.full_like(f, float("nan"))
+        r0 = s.solve(f, p.phi_bot, p.phi_top, out=zero)
+        r1 = s.solve(f, p.phi_bot, p.phi_top, out=nan)
+        assert r0.converged and r1.converged and r0.iterations == r1.iterations
+        assert torch.equal(r0.phi, r1.phi) and torch.isfinite(r1.phi).all()
+        assert r0.final_relres == r1.final_relres
+        for method in ("fgmres", "gmres"):
+            g0, _ = s.krylov_solve(f, p.phi_bot, p.phi_top, method=method, out=torch.zeros_like(f))
+            g1, _ = s.krylov_solve(f, p.phi_bot, p.phi_top, method=method, out=torch.full_like(f, float("nan")))
+            assert torch.equal(g0.phi, g1.phi) and torch.isfinite(g1.phi).all()
+    early = s.solve(f, p.phi_bot, p.phi_top, tol=2.0, out=torch.full_like(f, float("nan")))
+    assert early.converged and early.iterations == 0 and not early.phi.abs().max().item()
+    s0 = gm.GMGPoisson(T(p.a), precision=precision, max_iter=0)
+    none = s0.solve(f, p.phi_bot, p.phi_top, out=torch.full_like(f, float("nan")), raise_on_error=False)
+    assert none.iterations == 0 and not none.phi.abs().max().item()
+    z0 = npy(s.vcycle(f))
+    assert np.isfinite(z0).all() and np.array_equal(z0, npy(s.vcycle(f)))
+
+
 def test_determinism():
     p = make_config(2, n=32)
     s = gm.GMGPoisson(T(p.a), precision="mixed")
