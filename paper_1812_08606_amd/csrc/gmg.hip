@@ -679,7 +679,9 @@ constexpr int FACE_MAX_WAVES = sizeof(T) == 4 ? 4 : 2;
 // sweep instead of twice; on smaller levels, where a sweep is latency-bound,
 // the fused kernel takes as long as the two half-sweep kernels it replaces
 // (kernel trace of 256^3 solves: 12.2 us against 2 x 5.7 us at 64^3 and
-// below), and fewer launches did not shorten the solves.
+// below), and fewer launches did not shorten the solves (with z-chunks of
+// one or two planes there, 10.3 us per fused sweep, the 64^3 mixed step
+// took 3.71 ms against 3.49 and the 512^3 one 87.8 against 87.0).
 template <typename T>
 bool fused_face(gmg_ctx* c, int l) {
   const LevelShape& s = c->L.shapes[l];
