@@ -568,11 +568,14 @@ __global__ __launch_bounds__(NTHREADS) void k_op_multidot_split(const TZ* __rest
           s += !top ? (acv + at[e]) * hz * (zcv - zt[e]) : pz * acv * zcv;
           wv[e] = s;
         }
-        w[cn] = wv[0];
-        w[cn + 1] = wv[1];
+        // w and the basis vectors stream through once (non-temporal), so
+        // that L2 keeps the z and a rows that the adjacent rows' blocks re-read
+        __builtin_nontemporal_store(wv[0], &w[cn]);
+        __builtin_nontemporal_store(wv[1], &w[cn + 1]);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          acc[v] += wv[0] * U[(size_t)v * stride + cn] + wv[1] * U[(size_t)v * stride + cn + 1];
+          acc[v] += wv[0] * __builtin_nontemporal_load(&U[(size_t)v * stride + cn]) +
+                    wv[1] * __builtin_nontemporal_load(&U[(size_t)v * stride + cn + 1]);
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           zb[e] = zc[e];
